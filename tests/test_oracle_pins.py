@@ -1,0 +1,268 @@
+"""Pins of the CPU oracle against facts fixed outside it: hand-computed
+messages, exhaustive max-log-MAP / ML search on tiny codes, the encoder
+(valid codewords), IEEE binary16 rounding as implemented by numpy, and exact
+invariants of the algorithm. None of these retypes the oracle's formulas."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import bruteforce as bf
+from synth import (encode, make_batch, make_graph, make_toy_graph, noiseless_q, quantize,
+                   syndrome)
+from synth.channel import sigma2
+
+
+def one_row(Z=1, w=4, shifts=None):
+    base = np.array([shifts if shifts is not None else [0] * w])
+    return make_toy_graph(base, Z=Z, kb=w - 1, n_punct=0)
+
+
+# --------------------------------------------------------------------------
+# Hand-computed single-row update (min-sum with beta = 3/4 in Q1.7,
+# round half up, symmetric saturation at +-127).
+# --------------------------------------------------------------------------
+
+def _row_llr(q, iters, **kw):
+    g = one_row()
+    _, _, _, llr = oracle.decode_i8(g, np.array([q], np.int8), max_iter=iters, early_exit=False,
+                                    want_llr=True, **kw)
+    return llr[0].tolist()
+
+
+def test_hand_example_one_row():
+    # L = [10, -3, 7, -20], R = 0: m1 = 3 (edge 1), m2 = 7, sign product +;
+    # a1 = (3*3 + 2) >> 2 = 2, a2 = (3*7 + 2) >> 2 = 5 -> R' = [2, -5, 2, -2].
+    assert _row_llr([10, -3, 7, -20], 1) == [12, -8, 9, -22]
+    # Re-running the same row changes nothing when nothing saturated.
+    assert _row_llr([10, -3, 7, -20], 2) == [12, -8, 9, -22]
+
+
+def test_hand_example_offset():
+    # offset 2 before normalisation: m1 -> 1, m2 -> 5; a1 = 1, a2 = 4.
+    assert _row_llr([10, -3, 7, -20], 1, delta=2) == [11, -7, 8, -21]
+
+
+def test_hand_example_saturation_order():
+    # Iteration 1: m1 = 120, m2 = 124, a1 = 90, a2 = 93 -> L' saturates at 127.
+    # Iteration 2 sees x = 127 - R = [37, 34, 37, 37]: m1 = 34, m2 = 37,
+    # a1 = 26, a2 = 28 -> [63, 62, 63, 63]. Without the clamp after the add,
+    # iteration 2 would repeat iteration 1.
+    assert _row_llr([126, 120, 125, 124], 1) == [127, 127, 127, 127]
+    assert _row_llr([126, 120, 125, 124], 2) == [63, 62, 63, 63]
+    # The clamp is symmetric: -127, never -128.
+    assert _row_llr([-126, -120, -125, -124], 1) == [-127, -127, -127, -127]
+    assert _row_llr([-126, -120, -125, -124], 2) == [-63, -62, -63, -63]
+    # An input of -128 is read as -127: with beta = 1 the only other edge
+    # then receives 127 in magnitude.
+    g = one_row(w=2)
+    _, _, _, llr = oracle.decode_i8(g, np.array([[-128, 0]], np.int8), max_iter=1,
+                                    early_exit=False, want_llr=True,
+                                    wq=np.full((1, 1), 128, np.uint8))
+    assert llr[0].tolist() == [-127, -127]
+
+
+def test_hand_example_fp16():
+    # Same row in binary16: a1 = 0.75*3 = 2.25, a2 = 0.75*7 = 5.25 (exact).
+    g = one_row()
+    _, _, _, llr = oracle.decode_f16(g, np.array([[10, -3, 7, -20]], np.int8), max_iter=1,
+                                     early_exit=False, want_llr=True)
+    assert oracle.f16_to_f64(llr[0]).tolist() == [12.25, -8.25, 9.25, -22.25]
+
+
+# --------------------------------------------------------------------------
+# binary16 rounding against numpy's IEEE conversion
+# --------------------------------------------------------------------------
+
+def test_f16_rounding_matches_numpy():
+    rng = np.random.default_rng(0)
+    v = np.concatenate([
+        rng.standard_normal(20000) * 10.0 ** rng.uniform(-9, 5, 20000),
+        np.arange(-3000, 3000) * 0.125 + 0.0625,           # ties at several scales
+        np.array([65504.0, 65519.99, 65520.0, 1e6, -1e6, 2.0 ** -24, 2.0 ** -25,
+                  3 * 2.0 ** -26, 2.0 ** -14 - 2.0 ** -25, 0.0, -0.0]),
+    ])
+    ref = v.astype(np.float16).view(np.uint16)
+    assert (oracle.f64_to_f16(v) == ref).all()
+    h = np.arange(65536, dtype=np.uint16)
+    finite = (h & 0x7C00) != 0x7C00
+    back = oracle.f16_to_f64(h[finite])
+    assert (back == h[finite].view(np.float16).astype(np.float64)).all()
+    assert (oracle.f64_to_f16(back) == h[finite]).all()
+
+
+# --------------------------------------------------------------------------
+# Single parity check and trees against exhaustive max-log-MAP
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("w", [2, 3, 5, 8])
+def test_spc_is_maxlog_map(w):
+    # One check is a tree: one layer of min-sum with beta = 1 gives the exact
+    # max-log-MAP posterior of every bit.
+    rng = np.random.default_rng(w)
+    g = one_row(w=w)
+    words = bf.all_codewords(g.dense_H())
+    for _ in range(20):
+        q = rng.integers(-60, 61, (1, w)).astype(np.int8)
+        _, _, _, llr = oracle.decode_i8(g, q, max_iter=1, early_exit=False, want_llr=True,
+                                        wq=np.full((1, 1), 128, np.uint8))
+        assert llr[0].tolist() == bf.maxlog_map(words, q[0].astype(float)).tolist()
+        lf = rng.standard_normal((1, w)) * 3
+        _, _, _, l64 = oracle.decode_f64(g, lf, max_iter=1, early_exit=False, beta=1.0,
+                                         want_llr=True)
+        assert np.allclose(l64[0], bf.maxlog_map(words, lf[0]), rtol=0, atol=1e-12)
+
+
+TREE = np.array([
+    # a cycle-free base graph: 4 checks, 9 variables, 12 edges, connected
+    [0, 0, 0, -1, -1, -1, -1, -1, -1],
+    [-1, -1, 0, 0, 0, -1, -1, -1, -1],
+    [-1, -1, -1, -1, 0, 0, 0, -1, -1],
+    [-1, 0, -1, -1, -1, -1, -1, 0, 0],
+])
+
+
+@pytest.mark.parametrize("Z", [1, 3])
+def test_tree_is_maxlog_map(Z):
+    rng = np.random.default_rng(10 + Z)
+    base = np.where(TREE >= 0, rng.integers(0, Z, TREE.shape), -1)
+    g = make_toy_graph(base, Z=Z, kb=5)  # a lift of a tree is a forest
+    words = bf.all_codewords(g.dense_H())
+    for _ in range(10):
+        lf = rng.standard_normal((1, g.N * Z)) * 2
+        _, _, _, l64 = oracle.decode_f64(g, lf, max_iter=12, early_exit=False, beta=1.0,
+                                         want_llr=True)
+        assert np.allclose(l64[0], bf.maxlog_map(words, lf[0]), atol=1e-9)
+        qi = rng.integers(-20, 21, (1, g.N * Z)).astype(np.int8)
+        _, _, _, li = oracle.decode_i8(g, qi, max_iter=12, early_exit=False, want_llr=True,
+                                       wq=np.full((1, g.M), 128, np.uint8))
+        assert li[0].tolist() == bf.maxlog_map(words, qi[0].astype(float)).tolist()
+        _, _, _, lh = oracle.decode_f16(g, qi, max_iter=12, early_exit=False, beta=1.0,
+                                        want_llr=True)
+        assert oracle.f16_to_f64(lh[0]).tolist() == bf.maxlog_map(words, qi[0].astype(float)).tolist()
+
+
+# --------------------------------------------------------------------------
+# BG-shaped codes: noiseless input, symmetry, batch independence
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("bg,Z,M", [(2, 16, 42), (2, 16, 4), (1, 16, 46), (1, 32, 7), (2, 64, 20)])
+def test_noiseless_decodes_in_one_iteration(bg, Z, M):
+    g = make_graph(bg, Z, M)
+    u = np.random.default_rng(Z + M).integers(0, 2, (6, g.K), dtype=np.uint8)
+    c = encode(g, u)
+    q = noiseless_q(c, g)
+    for dec in (oracle.decode_i8, oracle.decode_f16):
+        bits, iters, ok, _ = dec(g, q, max_iter=10)
+        assert (iters == 1).all() and ok.all()
+        assert (oracle.unpack_bits(bits, g.K) == u).all()
+
+
+@pytest.mark.parametrize("bg,Z", [(2, 16), (1, 32)])
+def test_codeword_symmetry(bg, Z):
+    # Flipping the LLR signs of a valid codeword flips every posterior's sign
+    # and nothing else (early exit off), in both number modes.
+    g = make_graph(bg, Z)
+    rng = np.random.default_rng(5)
+    b0 = make_batch(g, 4, 1.0, data_seed=3)
+    u = rng.integers(0, 2, (4, g.K), dtype=np.uint8)
+    c = encode(g, u)
+    # LLRs for the all-zero word: |q| with the noise pattern of b0
+    q0 = (b0.q.astype(np.int16) * (1 - 2 * b0.c[:, 2 * Z:].astype(np.int16))).clip(-127, 127)
+    sgn = (1 - 2 * c.astype(np.int16))
+    qc = (q0 * sgn[:, 2 * Z:]).astype(np.int8)
+    _, _, _, l0 = oracle.decode_i8(g, q0.astype(np.int8), max_iter=6, early_exit=False,
+                                   want_llr=True)
+    _, _, _, lc = oracle.decode_i8(g, qc, max_iter=6, early_exit=False, want_llr=True)
+    assert (lc.astype(np.int16) == l0.astype(np.int16) * sgn).all()
+    _, _, _, h0 = oracle.decode_f16(g, q0.astype(np.int8), max_iter=6, early_exit=False,
+                                    want_llr=True)
+    _, _, _, hc = oracle.decode_f16(g, qc, max_iter=6, early_exit=False, want_llr=True)
+    assert (oracle.f16_to_f64(hc) == oracle.f16_to_f64(h0) * sgn).all()
+
+
+def test_batch_order_and_threads_independent():
+    g = make_graph(2, 16)
+    b = make_batch(g, 40, 1.0, data_seed=1)
+    ref = oracle.decode_i8(g, b.q, want_llr=True)
+    perm = np.random.default_rng(0).permutation(40)
+    got = oracle.decode_i8(g, b.q[perm], want_llr=True, n_threads=4)
+    for a, r in zip(got, ref):
+        assert (a == r[perm]).all()
+
+
+def test_plain_equals_q17_weight_96():
+    g = make_graph(2, 32)
+    b = make_batch(g, 30, 1.0, data_seed=2)
+    ref = oracle.decode_i8(g, b.q, want_llr=True)
+    got = oracle.decode_i8(g, b.q, want_llr=True, wq=np.full((10, g.M), 96, np.uint8))
+    for a, r in zip(got, ref):
+        assert (a == r).all()
+
+
+def test_fp16_equals_f64_when_exact():
+    # With beta = 1 and small integer LLRs every binary16 intermediate is an
+    # integer below 2048, hence exact: the binary16 mode must then agree
+    # with the double mode bit for bit.
+    g = make_graph(2, 16, 12)
+    rng = np.random.default_rng(7)
+    q = rng.integers(-6, 7, (20, g.T)).astype(np.int8)
+    _, it64, ok64, l64 = oracle.decode_f64(g, q.astype(np.float64), max_iter=5, beta=1.0,
+                                           want_llr=True)
+    assert np.abs(l64).max() < 2048 and (l64 == np.round(l64)).all()
+    _, it16, ok16, l16 = oracle.decode_f16(g, q, max_iter=5, beta=1.0, want_llr=True)
+    assert (oracle.f16_to_f64(l16) == l64).all()
+    assert (it16 == it64).all() and (ok16 == ok64).all()
+
+
+def test_early_exit_and_failure_flags():
+    g = make_graph(2, 16)
+    b = make_batch(g, 50, -10.0, data_seed=4)  # pure noise: nothing converges
+    _, iters, ok, _ = oracle.decode_i8(g, b.q, max_iter=5)
+    assert (iters == 5).all() and not ok.any()
+    b = make_batch(g, 50, 4.0, data_seed=4)
+    bits, iters, ok, llr = oracle.decode_i8(g, b.q, max_iter=10, want_llr=True)
+    assert ok.mean() > 0.9
+    # ok means the hard decisions satisfy every check
+    hd = (llr < 0).astype(np.uint8)
+    assert (syndrome(g, hd).any(axis=1) == ~ok).all()
+    # without early exit the iteration count is the maximum
+    _, iters2, ok2, _ = oracle.decode_i8(g, b.q, max_iter=10, early_exit=False)
+    assert (iters2 == 10).all()
+
+
+# --------------------------------------------------------------------------
+# Toy code against brute-force maximum likelihood
+# --------------------------------------------------------------------------
+
+def test_toy_code_matches_ml_at_high_snr():
+    rng = np.random.default_rng(11)
+    Z, kb = 4, 4
+    pat = np.array([
+        [1, 1, 1, 0, 1, 1, 0, 0],
+        [1, 0, 1, 1, 1, 1, 1, 0],
+        [1, 1, 0, 1, 0, 0, 1, 1],
+        [0, 1, 1, 1, 1, 0, 0, 1],
+    ])
+    a = int(rng.integers(0, Z))
+    base = np.where(pat > 0, rng.integers(0, Z, pat.shape), -1)
+    base[:, kb:] = np.where(pat[:, kb:] > 0, 0, -1)
+    base[0, kb] = base[3, kb] = a
+    g = make_toy_graph(base, Z=Z, kb=kb)
+    H = g.dense_H()
+    words = bf.all_codewords(H)
+    assert words.shape[0] == 2 ** (kb * Z)
+    n = 10000
+    rate = kb / (g.N)
+    s2 = sigma2(rate, 6.0)
+    idx = rng.integers(0, words.shape[0], n)
+    c = words[idx]
+    y = (1 - 2.0 * c) + np.sqrt(s2) * rng.standard_normal(c.shape)
+    q = quantize(2 * y / s2)
+    _, _, ok, llr = oracle.decode_i8(g, q, max_iter=20, want_llr=True)
+    hd = (llr < 0).astype(np.uint8)
+    corr = (1.0 - 2.0 * words) @ q.astype(np.float64).T  # [n_words, n]
+    ml = words[np.argmax(corr, axis=0)]
+    agree = (hd == ml).all(axis=1).mean()
+    assert agree >= 0.99
+    # whenever the decoder reports success its output is a codeword
+    assert not ((H.astype(int) @ hd[ok].T.astype(int)) % 2).any()
