@@ -1,0 +1,222 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the MI355X layered min-sum LDPC decoder.
+
+Workload: BG1-shaped QC-LDPC, Z = 384, all 46 block rows (rate 1/3,
+K = 8448 information bits per codeword), 4096 codewords at each Eb/N0 of
+0.5, 0.75, ..., 2.0 dB (seeded synthetic BPSK/AWGN, int8 LLRs), layered
+normalised min-sum with beta = 3/4, at most 10 iterations, early exit on a
+zero syndrome. One step decodes the 7 batches (28,672 codewords) with the
+int8 kernel; inputs are resident in HBM before timing starts.
+
+Prints one JSON line: decoded information Gbit/s, the roofline of the
+dominant kernel (VALU-bound: 11 packed-16-bit element operations per
+edge-update, peak 256 CU x 64 lanes x 2 x 2.4 GHz), the CPU oracle timed on
+a bounded sample of the same workload, plus latency, BLER and the binary16
+path as extra fields.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_ALU_TOPS = 256 * 64 * 2 * 2.4e9 / 1e12  # packed 16-bit element ops, Top/s
+OPS_PER_EDGE_UPDATE = 11
+EBN0_POINTS = (0.5, 0.75, 1.0, 1.25, 1.5, 1.75, 2.0)
+BG, Z, ROWS = 1, 384, 46
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n-cw", type=int, default=4096)
+    ap.add_argument("--max-iter", type=int, default=10)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="target wall time of the CPU-oracle baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the binary16, latency and fixed-iteration runs")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(codewords are independent; see the sharding note in DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    from synth import make_batch_parallel, make_graph
+    g = make_graph(BG, Z)
+    workers = max(1, min(16, os.cpu_count() or 1))
+    t0 = time.time()
+    batches = [make_batch_parallel(g, args.n_cw, e, data_seed=2 + i, workers=workers)
+               for i, e in enumerate(EBN0_POINTS)]
+    log(f"generated {len(batches)} x {args.n_cw} codewords in {time.time() - t0:.1f} s")
+
+    import torch
+    from paper_2009_05534_amd import ldpc
+
+    torch.cuda.set_device(0)
+    ldpc.register(g)
+    K, T, Nc, E = ldpc.query(BG, Z, ROWS)
+    U = E * Z  # edge-updates per iteration per codeword
+    dev = torch.device("cuda:0")
+    llr = [torch.from_numpy(b.q).to(dev) for b in batches]
+    n = args.n_cw
+    bits = [torch.empty((n, K // 8), dtype=torch.uint8, device=dev) for _ in batches]
+    iters = [torch.empty(n, dtype=torch.int32, device=dev) for _ in batches]
+    oks = [torch.empty(n, dtype=torch.uint8, device=dev) for _ in batches]
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+
+    def run_step(precision="i8", early_exit=True, events=None):
+        for i in range(len(batches)):
+            if events is not None:
+                events[i][0].record(stream)
+            ldpc.decode_into(llr[i], BG, Z, ROWS, bits[i], iters[i], out_ok=oks[i],
+                             max_iter=args.max_iter, precision=precision,
+                             early_exit=early_exit, stream=stream)
+            if events is not None:
+                events[i][1].record(stream)
+
+    def timed(precision, early_exit, steps, warmup):
+        for _ in range(warmup):
+            run_step(precision, early_exit)
+        torch.cuda.synchronize()
+        evs = [[[torch.cuda.Event(enable_timing=True) for _ in range(2)]
+                for _ in batches] for _ in range(steps)]
+        edge_updates = 0
+        t_start = time.perf_counter()
+        for s in range(steps):
+            run_step(precision, early_exit, evs[s])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t_start
+        launch_ms = [evs[s][i][0].elapsed_time(evs[s][i][1])
+                     for s in range(steps) for i in range(len(batches))]
+        edge_updates = sum(int(it.sum().item()) for it in iters) * U * steps
+        return wall, launch_ms, edge_updates
+
+    log("timing int8, early exit")
+    wall, launch_ms, eu = timed("i8", True, args.steps, args.warmup)
+    info_bits = args.steps * len(batches) * n * K
+    value = info_bits / wall / 1e9
+    ms_per_step = wall / args.steps * 1e3
+    kernel_s = sum(launch_ms) / 1e3
+    achieved = OPS_PER_EDGE_UPDATE * eu / kernel_s / 1e12
+    lat = np.array(launch_ms)
+
+    # BLER and mean iterations per Eb/N0 from the last step's outputs
+    bler, mean_it = {}, {}
+    for i, b in enumerate(batches):
+        got = np.unpackbits(bits[i].cpu().numpy(), axis=1, bitorder="little")[:, :K]
+        bler[str(EBN0_POINTS[i])] = float(np.mean((got != b.u).any(axis=1)))
+        mean_it[str(EBN0_POINTS[i])] = float(iters[i].float().mean().item())
+
+    result = {
+        "metric": "decoded info Gbit/s (BG1 Z=384, 10 it)",
+        "value": round(value, 3),
+        "unit": "Gbit/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int8",
+        "data": "synthetic",
+        "config": {
+            "workload": "BG1-shaped QC-LDPC Z=384, 46 rows (R=1/3), 4096 codewords x 7 Eb/N0 "
+                        "points 0.5-2.0 dB, int8 layered min-sum beta=3/4, max 10 iterations, "
+                        "early exit",
+            "bg": BG, "Z": Z, "rows": ROWS, "n_cw_per_point": n, "ebn0_db": list(EBN0_POINTS),
+            "max_iter": args.max_iter,
+        },
+        "roofline": {
+            "bound": "alu",
+            "kernel": "decode_i8_kernel",
+            "achieved": round(achieved, 3),
+            "peak": round(PEAK_ALU_TOPS, 2),
+            "unit": "Top/s",
+            "frac": round(achieved / PEAK_ALU_TOPS, 4),
+            "traffic": None,
+            "per_unit": f"{OPS_PER_EDGE_UPDATE} packed-16-bit element ops per edge-update",
+            "units_per_launch": round(eu / len(launch_ms)),
+            "avg_launch_ms": round(float(lat.mean()), 4),
+        },
+        "latency_ms": {"batch_p50": round(float(np.percentile(lat, 50)), 4),
+                       "batch_p99": round(float(np.percentile(lat, 99)), 4)},
+        "bler": bler,
+        "mean_iters": mean_it,
+    }
+
+    if not args.no_extras:
+        log("timing int8, fixed 10 iterations")
+        w10, l10, eu10 = timed("i8", False, 2, 1)
+        result["fixed_iter"] = {
+            "gbps": round(2 * len(batches) * n * K / w10 / 1e9, 3),
+            "frac": round(OPS_PER_EDGE_UPDATE * eu10 / (sum(l10) / 1e3) / 1e12 / PEAK_ALU_TOPS, 4),
+            "avg_launch_ms": round(float(np.mean(l10)), 4),
+        }
+        log("timing binary16, early exit")
+        w16, l16, _ = timed("f16", True, 2, 1)
+        result["f16"] = {"gbps": round(2 * len(batches) * n * K / w16 / 1e9, 3),
+                         "avg_launch_ms": round(float(np.mean(l16)), 4)}
+        # single-codeword latency per iteration (fixed 10 iterations)
+        one = llr[4][:1].contiguous()
+        b1 = torch.empty((1, K // 8), dtype=torch.uint8, device=dev)
+        i1 = torch.empty(1, dtype=torch.int32, device=dev)
+        for _ in range(3):
+            ldpc.decode_into(one, BG, Z, ROWS, b1, i1, max_iter=10, early_exit=False)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(50):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            ldpc.decode_into(one, BG, Z, ROWS, b1, i1, max_iter=10, early_exit=False)
+            e1.record(stream)
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        result["latency_ms"]["single_codeword_us_per_iter_p50"] = round(
+            float(np.percentile(ts, 50)) * 1e3 / 10, 2)
+
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = max(1, min(16, os.cpu_count() or 1))
+        b = batches[4]
+        probe = 64
+        t0 = time.perf_counter()
+        oracle.decode_i8(g, b.q[:probe], max_iter=args.max_iter, n_threads=threads)
+        dt = time.perf_counter() - t0
+        m = int(min(n, max(probe, probe * args.cpu_seconds / max(dt, 1e-3))))
+        log(f"CPU oracle baseline on {m} codewords, {threads} threads")
+        t0 = time.perf_counter()
+        oracle.decode_i8(g, b.q[:m], max_iter=args.max_iter, n_threads=threads)
+        dt = time.perf_counter() - t0
+        result["cpu_baseline"] = {
+            "value": round(m * K / dt / 1e9, 6),
+            "unit": "Gbit/s",
+            "cores": threads,
+            "kind": "oracle",
+            "sample": f"first {m} codewords of the 1.5 dB batch, int8 oracle, max "
+                      f"{args.max_iter} iterations, early exit, {dt:.1f} s",
+        }
+
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,151 @@
+/*
+ * ldpc.h -- C ABI of the MI355X (gfx950) layered normalised min-sum decoder
+ * for 5G-NR-shaped quasi-cyclic LDPC codes.
+ *
+ * Method: Ling & Cautereels, "Fast LDPC GPU Decoder for Cloud RAN".
+ *   - code: quasi-cyclic, base graph lifted by Z, K = K_b*Z information bits,
+ *     the first two information columns punctured, rate set by the number of
+ *     base rows kept (§II);
+ *   - decoding: horizontal layered belief propagation with the normalised
+ *     min-sum check rule, posterior and extrinsic updates, iterate until the
+ *     hard decisions satisfy every check or the iteration limit (§III);
+ *   - per-row intermediates min, second min and sign product (§IV);
+ *   - 8-bit fixed point and packed binary16 number formats (§I, §IV).
+ *
+ * Conventions shared by every entry point
+ *   - All array arguments of decode calls are DEVICE pointers owned by the
+ *     caller; graph registration takes HOST pointers and copies them.
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *     Decode calls are asynchronous: outputs are valid once the stream has
+ *     reached the point of the call.
+ *   - A call that returns an error code has launched nothing and written no
+ *     output.
+ *   - Variables are ordered column-block-major: bit j = c*Z + z.
+ *     Circulant convention: block (r, c) with shift s joins check row z of
+ *     block row r to variable (z + s) mod Z of block column c.
+ *   - The library is reentrant; graph registration and plan look-ups are
+ *     serialised by a mutex. Calls on different streams may overlap.
+ */
+#ifndef LDPC_MI355X_H
+#define LDPC_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Return codes. */
+#define LDPC_OK 0
+#define LDPC_EINVAL (-1)   /* an argument is out of range or a pointer is NULL */
+#define LDPC_ENOMEM (-2)   /* device or host allocation failed */
+#define LDPC_EHIP (-3)     /* a HIP runtime call failed (see ldpc_last_hip_error) */
+#define LDPC_ENOGRAPH (-4) /* no graph registered for (bg, Z) */
+
+/* Number formats (ldpc_args.precision). */
+#define LDPC_I8 0  /* 8-bit saturating fixed point, symmetric +-127 */
+#define LDPC_F16 1 /* IEEE binary16, round to nearest even after every op */
+
+/* Supported lifts: Z a multiple of 8 with 8 <= Z <= 384, which covers the
+ * lifts {16, 32, 64, 96, 128, 192, 256, 384}. Base graphs: 4 to 46 rows, up
+ * to 68 columns, row weight 2..32. */
+#define LDPC_MAX_Z 384
+#define LDPC_MAX_ROWS 46
+#define LDPC_MAX_COLS 68
+#define LDPC_MAX_ROW_WEIGHT 32
+#define LDPC_MAX_ITER 64
+
+/*
+ * ldpc_set_graph -- register the full base graph `bg` (an identifier >= 1)
+ * lifted by Z (§II). The graph has m_rows block rows and n_cols = kb + m_rows
+ * block columns, the first 2 columns punctured. Block e of row r
+ * (row_ptr[r] <= e < row_ptr[r+1], strictly ascending col) has column col[e]
+ * and shift shift[e] in [0, Z). Keeping the first `rows` block rows and the
+ * first kb + rows columns must give a valid sub-code for every rows in
+ * [4, m_rows], so every block of row r must lie in a column
+ * < kb + max(r + 1, 4) (as in the 5G base graphs); m_rows >= 4, row
+ * weights 2..32. Host pointers; the library copies
+ * them to device memory. Re-registering (bg, Z) replaces the graph; the
+ * caller must not do so while a decode of (bg, Z) is in flight.
+ * Errors: LDPC_EINVAL (shape, ordering, shift or weight out of range),
+ * LDPC_ENOMEM, LDPC_EHIP.
+ */
+int ldpc_set_graph(int bg, int Z, int m_rows, int kb, const int32_t *row_ptr,
+                   const int16_t *col, const int16_t *shift);
+
+/* Sizes of the sub-code keeping `rows` block rows of graph (bg, Z):
+ * K information bits, T transmitted LLRs per codeword ((kb+rows-2)*Z),
+ * Nc = (kb+rows)*Z code bits, E nonzero blocks. Any output may be NULL. */
+int ldpc_query(int bg, int Z, int rows, int *K, int *T, int *Nc, int *E);
+
+/*
+ * ldpc_decode -- layered normalised min-sum (beta = 3/4), int8 path, early
+ * exit on a zero syndrome (§III).
+ *   bg, Z, rows : registered graph and number of block rows kept, 4..m_rows
+ *   n_cw        : number of codewords (>= 1)
+ *   llr_in      : int8 [n_cw][T], channel LLRs of the transmitted bits in
+ *                 variable order (punctured columns absent), LLR units of
+ *                 1/4 (any value is legal; -128 is read as -127)
+ *   max_iter    : 1..64 iterations
+ *   out_bits    : uint8 [n_cw][K/8] hard decisions of the K information
+ *                 bits (including the punctured ones), packed LSB first
+ *   out_iters   : int32 [n_cw] iterations run (the first iteration after
+ *                 which every check held, else max_iter)
+ * Errors: LDPC_EINVAL, LDPC_ENOGRAPH, LDPC_EHIP, LDPC_ENOMEM.
+ */
+int ldpc_decode(int bg, int Z, int rows, int n_cw, const int8_t *llr_in, int max_iter,
+                uint8_t *out_bits, int32_t *out_iters, void *stream);
+
+/* Extended decode arguments. Fields not used by a precision are ignored. */
+typedef struct ldpc_args {
+    int bg, Z, rows, n_cw;
+    int precision;          /* LDPC_I8 or LDPC_F16 */
+    int max_iter;           /* 1..64 */
+    int early_exit;         /* 1: stop a codeword once all its checks hold;
+                               0: run max_iter iterations (out_ok still set) */
+    const int8_t *llr_in;   /* int8 [n_cw][T] (both precisions) */
+    /* Normalisation of the min-sum magnitude (§III correction factor):
+     *   i8  : a = min((w*max(m - offset_q, 0) + 64) >> 7, 127), w = beta_q
+     *         or wq[min(t, wq_iters) - 1][r] (Q1.7, 0..255) when wq != NULL
+     *   f16 : a = w * max(m - offset_h, 0) in binary16, w = beta_h or
+     *         wh[min(t, wh_iters) - 1][r] (binary16 bit patterns)        */
+    int beta_q;             /* Q1.7 multiplier, default 96 (= 3/4) */
+    int offset_q;           /* 0..127, default 0 */
+    const uint8_t *wq;      /* device uint8 [wq_iters][rows] or NULL */
+    int wq_iters;
+    uint16_t beta_h;        /* binary16, default 0x3A00 (= 0.75) */
+    uint16_t offset_h;      /* binary16, default 0 */
+    const uint16_t *wh;     /* device binary16 [wh_iters][rows] or NULL */
+    int wh_iters;
+    uint8_t *out_bits;      /* uint8 [n_cw][K/8] */
+    int32_t *out_iters;     /* int32 [n_cw] */
+    uint8_t *out_ok;        /* uint8 [n_cw] or NULL: 1 if every check holds */
+    void *out_llr;          /* NULL, or final posteriors [n_cw][Nc] in
+                               variable order: int8 (I8) or binary16 (F16) */
+    int cw_per_block;       /* 0 = library default; else codewords per
+                               workgroup (tuning knob) */
+    void *stream;
+} ldpc_args;
+
+/* Fill `a` with the defaults above (beta 3/4, no offset, early exit on,
+ * int8, 10 iterations, no optional outputs). */
+void ldpc_args_init(ldpc_args *a);
+
+/* ldpc_decode_ex -- decode with the options of ldpc_args. The binary16
+ * path keeps its check-to-variable messages in device memory that the
+ * library allocates per call (stream-ordered), 2 bytes per message.
+ * Errors: as ldpc_decode. */
+int ldpc_decode_ex(const ldpc_args *a);
+
+/* Error text for a return code; the last HIP error code seen by the
+ * library (hipError_t as int, 0 if none). */
+const char *ldpc_strerror(int code);
+int ldpc_last_hip_error(void);
+
+/* Release every device table the library holds (graphs). */
+void ldpc_shutdown(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LDPC_MI355X_H */

@@ -1,0 +1,242 @@
+// Layered normalised min-sum decoding in IEEE binary16 for gfx950
+// (Ling & Cautereels, §III decoding rules, §IV min/second-min/sign
+// intermediates and the packed half-precision number format).
+//
+// Same row-pair organisation as the int8 kernel: lane u owns check rows u
+// and u + Z/2 and holds them as one packed half2 register, so every update
+// is a single v_pk_*_f16 (rounded to nearest even, no contraction). The
+// posteriors live in LDS as half2 pair words (BG1-shaped at Z = 384:
+// 52,224 bytes, so three codewords fit one CU); the check-to-variable
+// messages (242 kB per codeword at that size) do not fit and stream through
+// device memory as coalesced half2 pair words -- the paper's half-precision
+// decoder met the same wall (§V). Magnitudes are compared as integers on
+// the bit patterns (monotone for non-negative halves).
+#include "ldpc_internal.h"
+
+namespace ldpc {
+namespace {
+
+typedef _Float16 h16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+__device__ inline h16x2 as_h(uint32_t v) { return __builtin_bit_cast(h16x2, v); }
+__device__ inline u16x2 as_u(uint32_t v) { return __builtin_bit_cast(u16x2, v); }
+__device__ inline uint32_t bits_of(h16x2 v) { return __builtin_bit_cast(uint32_t, v); }
+__device__ inline uint32_t bits_of(u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
+
+// Rotate a pair word by 16 bits when the halves arrive swapped.
+__device__ inline uint32_t swap_halves(uint32_t v, bool swap) {
+    return swap ? __builtin_amdgcn_alignbit(v, v, 16) : v;
+}
+
+struct Gather {
+    int addr;
+    bool swap;
+};
+
+__device__ inline Gather gather(uint32_t md, int u, int Zh) {
+    const int colw = (int)(md & 0xFFFFu);
+    const int slo = (int)((md >> 16) & 0xFFu);
+    const bool shi = (md >> 24) & 1u;
+    const int v = u + slo;
+    const bool hi = v >= Zh;
+    return Gather{colw + (hi ? v - Zh : v), hi != shi};
+}
+
+// a = w * max(m - off, 0), each step rounded to binary16.
+__device__ inline uint32_t normalise(uint32_t m, uint32_t off, h16x2 w) {
+    h16x2 v = as_h(m);
+    if (off) {
+        v = v - as_h(off);
+        v = __builtin_elementwise_max(v, (h16x2){(_Float16)0, (_Float16)0});
+    }
+    return bits_of(w * v);
+}
+
+template <int WMAX>
+__device__ inline void row_update(uint32_t *__restrict__ Lw, uint32_t *__restrict__ Rg,
+                                  const uint32_t *__restrict__ meta, int e0, int w, int u, int Zh,
+                                  bool first_iter, h16x2 wgt, uint32_t off) {
+    uint32_t xv[WMAX], axv[WMAX];
+    int la[WMAX];
+    bool sw[WMAX];
+    u16x2 m1 = {0x7C00, 0x7C00}, m2 = {0x7C00, 0x7C00};
+    uint32_t S = 0;
+#pragma unroll
+    for (int k = 0; k < WMAX; ++k) {
+        if (k < w) {
+            const Gather g = gather(meta[e0 + k], u, Zh);
+            la[k] = g.addr;
+            sw[k] = g.swap;
+            const h16x2 L = as_h(swap_halves(Lw[g.addr], g.swap));
+            h16x2 x = L;
+            if (!first_iter) x = L - as_h(Rg[(size_t)(e0 + k) * Zh + u]);
+            const uint32_t xb = bits_of(x);
+            const u16x2 ax = as_u(xb & 0x7FFF7FFFu);
+            m2 = __builtin_elementwise_min(m2, __builtin_elementwise_max(m1, ax));
+            m1 = __builtin_elementwise_min(m1, ax);
+            S ^= xb;
+            xv[k] = xb;
+            axv[k] = bits_of(ax);
+        }
+    }
+    const uint32_t a1 = normalise(bits_of(m1), off, wgt);
+    const uint32_t a2 = normalise(bits_of(m2), off, wgt);
+    const u16x2 m1p = m1 + (u16x2){1, 1};
+#pragma unroll
+    for (int k = 0; k < WMAX; ++k) {
+        if (k < w) {
+            // mask = 0xFFFF on the argmin edge (|x| == m1), else 0.
+            const u16x2 t = __builtin_elementwise_sub_sat(m1p, as_u(axv[k]));
+            const uint32_t mask = bits_of((u16x2){0, 0} - t);
+            const uint32_t mag = (a2 & mask) | (a1 & ~mask);
+            const uint32_t Rn = mag | ((S ^ xv[k]) & 0x80008000u);
+            const h16x2 Ln = as_h(xv[k]) + as_h(Rn);
+            Lw[la[k]] = swap_halves(bits_of(Ln), sw[k]);
+            Rg[(size_t)(e0 + k) * Zh + u] = Rn;
+        }
+    }
+}
+
+// Nonzero if some check of lane u's rows fails; hard decision [L_v < 0]
+// (negative zero decides 0).
+__device__ inline bool syndrome_fails(const uint32_t *__restrict__ Lw,
+                                      const int32_t *__restrict__ row_ptr,
+                                      const uint32_t *__restrict__ meta, int rows, int u, int Zh) {
+    uint32_t bad = 0;
+    for (int r = 0; r < rows; ++r) {
+        const int e0 = row_ptr[r], e1 = row_ptr[r + 1];
+        uint32_t acc = 0;
+        for (int e = e0; e < e1; ++e) {
+            const Gather g = gather(meta[e], u, Zh);
+            const uint32_t v = swap_halves(Lw[g.addr], g.swap);
+            // bit 15/31 set iff the half is strictly negative
+            const uint32_t lo = (v & 0xFFFFu) > 0x8000u ? 0x8000u : 0u;
+            const uint32_t hi = (v >> 16) > 0x8000u ? 0x80000000u : 0u;
+            acc ^= lo | hi;
+        }
+        bad |= acc;
+    }
+    return bad != 0;
+}
+
+template <int WMAX>
+__global__ __launch_bounds__(512) void decode_f16_kernel(DecodeLaunch p,
+                                                         const int32_t *__restrict__ row_ptr,
+                                                         const uint32_t *__restrict__ meta) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    const int Z = p.Z, Zh = Z >> 1;
+    const int N = p.n_cols, E = p.E, T = (N - 2) * Z;
+    const int slot_bytes = lds_bytes_f16(N, Z);
+    const int slot = threadIdx.x / Zh;
+    const int u = threadIdx.x - slot * Zh;
+    const int cw = blockIdx.x * p.cpw + slot;
+    const bool valid = cw < p.n_cw;
+    uint32_t *Lw = reinterpret_cast<uint32_t *>(smem + slot * slot_bytes);
+    int *flags = reinterpret_cast<int *>(smem + p.cpw * slot_bytes);
+    uint32_t *Rg = p.msg + (size_t)(valid ? cw : 0) * E * Zh;
+
+    if (valid) {
+        Lw[u] = 0;
+        Lw[Zh + u] = 0;
+        const int8_t *q = p.llr + (size_t)cw * T;
+        for (int c = 2; c < N; ++c) {
+            int lo = q[(c - 2) * Z + u], hi = q[(c - 2) * Z + u + Zh];
+            lo = lo < -127 ? -127 : lo;
+            hi = hi < -127 ? -127 : hi;
+            const h16x2 v = {(_Float16)lo, (_Float16)hi};
+            Lw[c * Zh + u] = bits_of(v);
+        }
+    }
+    __syncthreads();
+
+    const uint32_t off = (uint32_t)(p.offset & 0xFFFF) * 0x00010001u;
+    bool done = !valid;
+    int iters = p.max_iter, ok = 0;
+    for (int t = 1; t <= p.max_iter; ++t) {
+        uint32_t wt = (uint32_t)(p.beta & 0xFFFF);
+        const uint16_t *wrow = nullptr;
+        if (p.wh) wrow = p.wh + (size_t)((t < p.w_iters ? t : p.w_iters) - 1) * p.rows;
+        for (int r = 0; r < p.rows; ++r) {
+            const int e0 = row_ptr[r], w = row_ptr[r + 1] - e0;
+            if (wrow) wt = wrow[r];
+            const h16x2 wgt = as_h(wt * 0x00010001u);
+            if (!done) row_update<WMAX>(Lw, Rg, meta, e0, w, u, Zh, t == 1, wgt, off);
+            __syncthreads();
+        }
+        if (p.early_exit || t == p.max_iter) {
+            if ((int)threadIdx.x < p.cpw) flags[threadIdx.x] = 0;
+            __syncthreads();
+            if (!done && syndrome_fails(Lw, row_ptr, meta, p.rows, u, Zh))
+                atomicOr(&flags[slot], 1);
+            __syncthreads();
+            const bool holds = flags[slot] == 0;
+            if (!done) {
+                if (p.early_exit && holds) {
+                    done = true;
+                    iters = t;
+                    ok = 1;
+                } else if (t == p.max_iter) {
+                    ok = holds;
+                }
+            }
+            if (p.early_exit && __syncthreads_and(done)) break;
+            __syncthreads();
+        }
+    }
+    if (!valid) return;
+
+    const int K = p.kb * Z;
+    const uint16_t *Lh = reinterpret_cast<const uint16_t *>(Lw);
+    for (int j = u; j < K / 8; j += Zh) {
+        uint32_t byte = 0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int v = 8 * j + i, c = v / Z, z = v - c * Z;
+            const int zz = z < Zh ? z : z - Zh;
+            const uint16_t h = Lh[2 * (c * Zh + zz) + (z < Zh ? 0 : 1)];
+            byte |= (uint32_t)(h > 0x8000u) << i;
+        }
+        p.out_bits[(size_t)cw * (K / 8) + j] = (uint8_t)byte;
+    }
+    if (u == 0) {
+        p.out_iters[cw] = iters;
+        if (p.out_ok) p.out_ok[cw] = (uint8_t)ok;
+    }
+    if (p.out_llr) {
+        uint16_t *o = static_cast<uint16_t *>(p.out_llr) + (size_t)cw * N * Z;
+        for (int v = u; v < N * Z; v += Zh) {
+            const int c = v / Z, z = v - c * Z;
+            const int zz = z < Zh ? z : z - Zh;
+            o[v] = Lh[2 * (c * Zh + zz) + (z < Zh ? 0 : 1)];
+        }
+    }
+}
+
+template <int WMAX>
+hipError_t launch_w(const DecodeLaunch &p, hipStream_t stream) {
+    const int Zh = p.Z / 2;
+    const int lds = p.cpw * lds_bytes_f16(p.n_cols, p.Z) + p.cpw * (int)sizeof(int);
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&decode_f16_kernel<WMAX>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           max_lds_bytes());
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    const int blocks = (p.n_cw + p.cpw - 1) / p.cpw;
+    hipLaunchKernelGGL(decode_f16_kernel<WMAX>, dim3(blocks), dim3(p.cpw * Zh), lds, stream, p,
+                       p.row_ptr, p.meta);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_decode_f16(const DecodeLaunch &p, hipStream_t stream) {
+    if (p.wmax <= 10) return launch_w<10>(p, stream);
+    if (p.wmax <= 20) return launch_w<20>(p, stream);
+    return launch_w<32>(p, stream);
+}
+
+}  // namespace ldpc

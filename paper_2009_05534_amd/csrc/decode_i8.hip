@@ -1,0 +1,271 @@
+// Layered normalised min-sum decoding in 8-bit saturating fixed point for
+// gfx950 (Ling & Cautereels, §III decoding rules, §IV min/second-min/sign
+// intermediates and the 8-bit number format).
+//
+// One workgroup decodes `cpw` codewords; each codeword's posteriors L_v and
+// check-to-variable messages L_{c->v} live in LDS for the whole decode
+// (BG1-shaped at Z = 384: 26,112 + 121,344 bytes). Lane u of a codeword
+// owns the check rows u and u + Z/2 of every block row, so the Z independent
+// rows of a layer (§II) run as Z/2 lanes with two rows each in packed 16-bit
+// VALU arithmetic. Layers run strictly in order with one workgroup barrier
+// each; after every iteration the full syndrome of the hard decisions is
+// checked and a codeword whose checks all hold stops changing.
+//
+// Storage: pair words (16 bit) -- the low byte is the value for row/variable
+// p, the high byte for p + Z/2. In registers each int8 value sits in the
+// HIGH byte of a 16-bit lane ("x * 256"), so the int16 saturating subtract
+// clamps at +127 (plus a low byte of 0xFF) and one max clamps at -127; the
+// low byte is cleared before a value is negated or stored.
+#include "ldpc_internal.h"
+
+namespace ldpc {
+namespace {
+
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+__device__ inline s16x2 as_s(uint32_t v) { return __builtin_bit_cast(s16x2, v); }
+__device__ inline u16x2 as_u(uint32_t v) { return __builtin_bit_cast(u16x2, v); }
+__device__ inline uint32_t bits_of(s16x2 v) { return __builtin_bit_cast(uint32_t, v); }
+__device__ inline uint32_t bits_of(u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
+
+// v_perm selectors (source bytes 0..3 = the word, 0x0c = zero byte).
+constexpr uint32_t kUnpack = 0x010c000cu;      // word -> (b0 << 8, b1 << 24)
+constexpr uint32_t kUnpackSwap = 0x000c010cu;  // word -> (b1 << 8, b0 << 24)
+constexpr uint32_t kPack = 0x0c0c0301u;        // inverse of kUnpack
+constexpr uint32_t kPackSwap = 0x0c0c0103u;    // inverse of kUnpackSwap
+
+__device__ inline uint32_t perm(uint32_t word, uint32_t sel) {
+    return __builtin_amdgcn_perm(0u, word, sel);
+}
+
+// Normalised magnitude on the high bytes: a = min((w*max(m - off, 0) + 64)
+// >> 7, 127), returned as a * 256 (low byte zero).
+__device__ inline u16x2 normalise(u16x2 m, u16x2 off16, u16x2 w) {
+    const u16x2 mo = __builtin_elementwise_sub_sat(m, off16);
+    u16x2 v = (mo >> (u16x2){8, 8}) * w + (u16x2){64, 64};
+    v = __builtin_elementwise_min(v >> (u16x2){7, 7}, (u16x2){127, 127});
+    return v << (u16x2){8, 8};
+}
+
+// Where lane u's two rows meet block `md`: pair-word address and the
+// unpack/pack selectors.
+struct Gather {
+    int addr;
+    uint32_t sel_unpack, sel_pack;
+};
+
+__device__ inline Gather gather(uint32_t md, int u, int Zh) {
+    const int colw = (int)(md & 0xFFFFu);
+    const int slo = (int)((md >> 16) & 0xFFu);
+    const bool shi = (md >> 24) & 1u;
+    const int v = u + slo;
+    const bool hi = v >= Zh;
+    Gather g;
+    g.addr = colw + (hi ? v - Zh : v);
+    const bool swap = hi != shi;
+    g.sel_unpack = swap ? kUnpackSwap : kUnpack;
+    g.sel_pack = swap ? kPackSwap : kPack;
+    return g;
+}
+
+// One block row for lane u (rows u and u + Zh): variable-to-check messages,
+// min / second min / sign product, normalisation, check-to-variable
+// messages and posterior write-back.
+template <int WMAX>
+__device__ inline void row_update(uint16_t *__restrict__ Lw, uint16_t *__restrict__ Rw,
+                                  const uint32_t *__restrict__ meta, int e0, int w, int u, int Zh,
+                                  bool first_iter, u16x2 wgt, u16x2 off16) {
+    uint32_t xv[WMAX], axv[WMAX], sp[WMAX];
+    int la[WMAX];
+    u16x2 m1 = {0x7FFF, 0x7FFF}, m2 = {0x7FFF, 0x7FFF};
+    uint32_t S = 0;
+#pragma unroll
+    for (int k = 0; k < WMAX; ++k) {
+        if (k < w) {
+            const Gather g = gather(meta[e0 + k], u, Zh);
+            la[k] = g.addr;
+            sp[k] = g.sel_pack;
+            const s16x2 L = as_s(perm(Lw[g.addr], g.sel_unpack));
+            s16x2 x = L;
+            if (!first_iter) {
+                const s16x2 R = as_s(perm(Rw[(e0 + k) * Zh + u], kUnpack));
+                x = __builtin_elementwise_sub_sat(L, R);
+                x = __builtin_elementwise_max(x, (s16x2){-127 * 256, -127 * 256});
+            }
+            const s16x2 ax = __builtin_elementwise_max(x, (s16x2){0, 0} - x);
+            const u16x2 axu = as_u(bits_of(ax));
+            m2 = __builtin_elementwise_min(m2, __builtin_elementwise_max(m1, axu));
+            m1 = __builtin_elementwise_min(m1, axu);
+            S ^= bits_of(x);
+            xv[k] = bits_of(x);
+            axv[k] = bits_of(ax);
+        }
+    }
+    const u16x2 a1 = normalise(m1, off16, wgt);
+    const u16x2 a2 = normalise(m2, off16, wgt);
+    // b = (-1)^S * a: the message with the row's sign product applied; each
+    // edge then takes sgn(x_k) * b_k, which removes its own sign from S.
+    const s16x2 Sm = as_s(S) >> (s16x2){15, 15};
+    const s16x2 b1 = (as_s(bits_of(a1)) ^ Sm) - Sm;
+    const s16x2 b2 = (as_s(bits_of(a2)) ^ Sm) - Sm;
+    const u16x2 d21 = as_u(bits_of(b2 - b1));
+    const u16x2 m1p = m1 + (u16x2){1, 1};
+#pragma unroll
+    for (int k = 0; k < WMAX; ++k) {
+        if (k < w) {
+            // t = 1 on the argmin edge (|x| == m1), else 0.
+            const u16x2 t = __builtin_elementwise_sub_sat(m1p, as_u(axv[k]));
+            const s16x2 b = as_s(bits_of(t * d21 + as_u(bits_of(b1))));
+            // L' = sgn(x) * min(|x| + b, 127); R' = sgn(x) * b.
+            s16x2 v = __builtin_elementwise_add_sat(as_s(axv[k]), b);
+            v = as_s(bits_of(v) & 0xFF00FF00u);
+            const s16x2 sx = as_s(xv[k]) >> (s16x2){15, 15};
+            const s16x2 Ln = (v ^ sx) - sx;
+            const s16x2 Rn = (b ^ sx) - sx;
+            Lw[la[k]] = (uint16_t)perm(bits_of(Ln), sp[k]);
+            Rw[(e0 + k) * Zh + u] = (uint16_t)perm(bits_of(Rn), kPack);
+        }
+    }
+}
+
+// Nonzero if some check of lane u's two rows fails on the current hard
+// decisions (bit = [L_v < 0]).
+__device__ inline uint32_t syndrome_fails(const uint16_t *__restrict__ Lw,
+                                          const int32_t *__restrict__ row_ptr,
+                                          const uint32_t *__restrict__ meta, int rows, int u,
+                                          int Zh) {
+    uint32_t bad = 0;
+    for (int r = 0; r < rows; ++r) {
+        const int e0 = row_ptr[r], e1 = row_ptr[r + 1];
+        uint32_t acc = 0;
+        for (int e = e0; e < e1; ++e) {
+            const Gather g = gather(meta[e], u, Zh);
+            acc ^= perm(Lw[g.addr], g.sel_unpack);
+        }
+        bad |= acc;
+    }
+    return bad & 0x80008000u;
+}
+
+template <int WMAX>
+__global__ __launch_bounds__(512) void decode_i8_kernel(DecodeLaunch p,
+                                                         const int32_t *__restrict__ row_ptr,
+                                                         const uint32_t *__restrict__ meta) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    const int Z = p.Z, Zh = Z >> 1;
+    const int N = p.n_cols, E = p.E, T = (N - 2) * Z;
+    const int slot_bytes = lds_bytes_i8(N, E, Z);
+    const int slot = threadIdx.x / Zh;
+    const int u = threadIdx.x - slot * Zh;
+    const int cw = blockIdx.x * p.cpw + slot;
+    const bool valid = cw < p.n_cw;
+    uint16_t *Lw = reinterpret_cast<uint16_t *>(smem + slot * slot_bytes);
+    uint16_t *Rw = Lw + N * Zh;
+    int *flags = reinterpret_cast<int *>(smem + p.cpw * slot_bytes);
+
+    // Initialisation: punctured columns 0 and 1 carry no channel LLR.
+    if (valid) {
+        Lw[u] = 0;
+        Lw[Zh + u] = 0;
+        const int8_t *q = p.llr + (size_t)cw * T;
+        for (int c = 2; c < N; ++c) {
+            int lo = q[(c - 2) * Z + u], hi = q[(c - 2) * Z + u + Zh];
+            lo = lo < -127 ? -127 : lo;
+            hi = hi < -127 ? -127 : hi;
+            Lw[c * Zh + u] = (uint16_t)((lo & 0xFF) | ((hi & 0xFF) << 8));
+        }
+    }
+    __syncthreads();
+
+    const u16x2 off16 = {(unsigned short)(p.offset << 8), (unsigned short)(p.offset << 8)};
+    bool done = !valid;
+    int iters = p.max_iter, ok = 0;
+    for (int t = 1; t <= p.max_iter; ++t) {
+        int wt = p.beta;
+        const uint8_t *wrow = nullptr;
+        if (p.wq) wrow = p.wq + (size_t)((t < p.w_iters ? t : p.w_iters) - 1) * p.rows;
+        for (int r = 0; r < p.rows; ++r) {
+            const int e0 = row_ptr[r], w = row_ptr[r + 1] - e0;
+            if (wrow) wt = wrow[r];
+            const u16x2 wgt = {(unsigned short)wt, (unsigned short)wt};
+            if (!done) row_update<WMAX>(Lw, Rw, meta, e0, w, u, Zh, t == 1, wgt, off16);
+            __syncthreads();
+        }
+        if (p.early_exit || t == p.max_iter) {
+            if ((int)threadIdx.x < p.cpw) flags[threadIdx.x] = 0;
+            __syncthreads();
+            if (!done && syndrome_fails(Lw, row_ptr, meta, p.rows, u, Zh))
+                atomicOr(&flags[slot], 1);
+            __syncthreads();
+            const bool holds = flags[slot] == 0;
+            if (!done) {
+                if (p.early_exit && holds) {
+                    done = true;
+                    iters = t;
+                    ok = 1;
+                } else if (t == p.max_iter) {
+                    ok = holds;
+                }
+            }
+            if (p.early_exit && __syncthreads_and(done)) break;
+            __syncthreads();
+        }
+    }
+    if (!valid) return;
+
+    // Outputs: hard decisions of the K information bits packed LSB first.
+    const int K = p.kb * Z;
+    const uint8_t *Lb = reinterpret_cast<const uint8_t *>(Lw);
+    for (int j = u; j < K / 8; j += Zh) {
+        uint32_t byte = 0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int v = 8 * j + i, c = v / Z, z = v - c * Z;
+            const int zz = z < Zh ? z : z - Zh;
+            const int8_t L = (int8_t)Lb[2 * (c * Zh + zz) + (z < Zh ? 0 : 1)];
+            byte |= (uint32_t)(L < 0) << i;
+        }
+        p.out_bits[(size_t)cw * (K / 8) + j] = (uint8_t)byte;
+    }
+    if (u == 0) {
+        p.out_iters[cw] = iters;
+        if (p.out_ok) p.out_ok[cw] = (uint8_t)ok;
+    }
+    if (p.out_llr) {
+        int8_t *o = static_cast<int8_t *>(p.out_llr) + (size_t)cw * N * Z;
+        for (int v = u; v < N * Z; v += Zh) {
+            const int c = v / Z, z = v - c * Z;
+            const int zz = z < Zh ? z : z - Zh;
+            o[v] = (int8_t)Lb[2 * (c * Zh + zz) + (z < Zh ? 0 : 1)];
+        }
+    }
+}
+
+template <int WMAX>
+hipError_t launch_w(const DecodeLaunch &p, hipStream_t stream) {
+    const int Zh = p.Z / 2;
+    const int lds = p.cpw * lds_bytes_i8(p.n_cols, p.E, p.Z) + p.cpw * (int)sizeof(int);
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&decode_i8_kernel<WMAX>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           max_lds_bytes());
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    const int blocks = (p.n_cw + p.cpw - 1) / p.cpw;
+    hipLaunchKernelGGL(decode_i8_kernel<WMAX>, dim3(blocks), dim3(p.cpw * Zh), lds, stream, p,
+                       p.row_ptr, p.meta);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_decode_i8(const DecodeLaunch &p, hipStream_t stream) {
+    if (p.wmax <= 10) return launch_w<10>(p, stream);
+    if (p.wmax <= 20) return launch_w<20>(p, stream);
+    return launch_w<32>(p, stream);
+}
+
+}  // namespace ldpc

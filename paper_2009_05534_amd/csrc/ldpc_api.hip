@@ -1,0 +1,289 @@
+// C-ABI front end of the decoder library: argument checks, the graph
+// registry (host copies plus lazily uploaded per-device tables), launch
+// configuration and error reporting. Declarations and contracts:
+// include/ldpc.h.
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "../../include/ldpc.h"
+#include "ldpc_internal.h"
+
+namespace ldpc {
+namespace {
+
+struct HostGraph {
+    int bg = 0, Z = 0, m_rows = 0, kb = 0;
+    std::vector<int32_t> row_ptr;
+    std::vector<int16_t> col, shift;
+};
+
+struct DevTables {
+    int32_t *row_ptr = nullptr;  // [m_rows + 1]
+    uint32_t *meta = nullptr;    // [E_full]
+};
+
+std::mutex g_mu;
+std::map<std::pair<int, int>, HostGraph> g_graphs;                 // (bg, Z)
+std::map<std::tuple<int, int, int>, DevTables> g_dev;             // (device, bg, Z)
+std::map<int, int> g_lds;                                          // device -> bytes
+int g_last_hip = 0;
+
+int hip_fail(hipError_t e) {
+    g_last_hip = (int)e;
+    return e == hipErrorOutOfMemory ? LDPC_ENOMEM : LDPC_EHIP;
+}
+
+bool valid_lift(int Z) { return Z >= 8 && Z <= LDPC_MAX_Z && Z % 8 == 0; }
+
+void free_tables(DevTables &t) {
+    if (t.row_ptr) (void)hipFree(t.row_ptr);
+    if (t.meta) (void)hipFree(t.meta);
+    t.row_ptr = nullptr;
+    t.meta = nullptr;
+}
+
+// Device tables of graph (bg, Z) on the current device; caller holds g_mu.
+int tables_for(const HostGraph &g, DevTables **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e);
+    auto key = std::make_tuple(dev, g.bg, g.Z);
+    auto it = g_dev.find(key);
+    if (it != g_dev.end()) {
+        *out = &it->second;
+        return LDPC_OK;
+    }
+    const int Zh = g.Z / 2;
+    const int E = g.row_ptr.back();
+    std::vector<uint32_t> meta(E);
+    for (int e2 = 0; e2 < E; ++e2) meta[e2] = pack_meta(g.col[e2], g.shift[e2], Zh);
+    DevTables t;
+    if ((e = hipMalloc(&t.row_ptr, sizeof(int32_t) * g.row_ptr.size())) != hipSuccess ||
+        (e = hipMalloc(&t.meta, sizeof(uint32_t) * E)) != hipSuccess ||
+        (e = hipMemcpy(t.row_ptr, g.row_ptr.data(), sizeof(int32_t) * g.row_ptr.size(),
+                       hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(t.meta, meta.data(), sizeof(uint32_t) * E, hipMemcpyHostToDevice)) !=
+            hipSuccess) {
+        free_tables(t);
+        return hip_fail(e);
+    }
+    *out = &(g_dev[key] = t);
+    return LDPC_OK;
+}
+
+int sub_sizes(const HostGraph &g, int rows, int *K, int *T, int *Nc, int *E) {
+    if (rows < 4 || rows > g.m_rows) return LDPC_EINVAL;
+    const int n = g.kb + rows;
+    if (K) *K = g.kb * g.Z;
+    if (T) *T = (n - 2) * g.Z;
+    if (Nc) *Nc = n * g.Z;
+    if (E) *E = g.row_ptr[rows];
+    return LDPC_OK;
+}
+
+}  // namespace
+
+int max_lds_bytes() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 65536;
+    auto it = g_lds.find(dev);
+    if (it != g_lds.end()) return it->second;
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess ||
+        v <= 0) {
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) !=
+                hipSuccess ||
+            v <= 0)
+            v = 65536;
+    }
+    if (v > 163840) v = 163840;
+    g_lds[dev] = v;
+    return v;
+}
+
+}  // namespace ldpc
+
+using namespace ldpc;
+
+extern "C" {
+
+int ldpc_set_graph(int bg, int Z, int m_rows, int kb, const int32_t *row_ptr, const int16_t *col,
+                   const int16_t *shift) {
+    if (bg < 1 || !valid_lift(Z) || m_rows < 4 || m_rows > LDPC_MAX_ROWS || kb < 2 ||
+        kb + m_rows > LDPC_MAX_COLS || !row_ptr || !col || !shift || row_ptr[0] != 0)
+        return LDPC_EINVAL;
+    for (int r = 0; r < m_rows; ++r) {
+        const int w = row_ptr[r + 1] - row_ptr[r];
+        if (w < 2 || w > LDPC_MAX_ROW_WEIGHT) return LDPC_EINVAL;
+        const int col_limit = kb + (r + 1 > 4 ? r + 1 : 4);
+        for (int e = row_ptr[r]; e < row_ptr[r + 1]; ++e) {
+            if (col[e] < 0 || col[e] >= col_limit || shift[e] < 0 || shift[e] >= Z)
+                return LDPC_EINVAL;
+            if (e > row_ptr[r] && col[e] <= col[e - 1]) return LDPC_EINVAL;
+        }
+    }
+    HostGraph g;
+    g.bg = bg;
+    g.Z = Z;
+    g.m_rows = m_rows;
+    g.kb = kb;
+    const int E = row_ptr[m_rows];
+    g.row_ptr.assign(row_ptr, row_ptr + m_rows + 1);
+    g.col.assign(col, col + E);
+    g.shift.assign(shift, shift + E);
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (auto it = g_dev.begin(); it != g_dev.end();) {
+        if (std::get<1>(it->first) == bg && std::get<2>(it->first) == Z) {
+            free_tables(it->second);
+            it = g_dev.erase(it);
+        } else {
+            ++it;
+        }
+    }
+    g_graphs[{bg, Z}] = std::move(g);
+    return LDPC_OK;
+}
+
+int ldpc_query(int bg, int Z, int rows, int *K, int *T, int *Nc, int *E) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_graphs.find({bg, Z});
+    if (it == g_graphs.end()) return LDPC_ENOGRAPH;
+    return sub_sizes(it->second, rows, K, T, Nc, E);
+}
+
+void ldpc_args_init(ldpc_args *a) {
+    if (!a) return;
+    *a = ldpc_args{};
+    a->precision = LDPC_I8;
+    a->max_iter = 10;
+    a->early_exit = 1;
+    a->beta_q = 96;
+    a->offset_q = 0;
+    a->beta_h = 0x3A00;
+    a->offset_h = 0;
+}
+
+int ldpc_decode_ex(const ldpc_args *a) {
+    if (!a || a->n_cw < 1 || a->max_iter < 1 || a->max_iter > LDPC_MAX_ITER || !a->llr_in ||
+        !a->out_bits || !a->out_iters || (a->precision != LDPC_I8 && a->precision != LDPC_F16) ||
+        a->beta_q < 0 || a->beta_q > 255 || a->offset_q < 0 || a->offset_q > 127 ||
+        (a->wq && a->wq_iters < 1) || (a->wh && a->wh_iters < 1) || a->cw_per_block < 0)
+        return LDPC_EINVAL;
+    DecodeLaunch p{};
+    int lds_cap = 0;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_graphs.find({a->bg, a->Z});
+        if (it == g_graphs.end()) return LDPC_ENOGRAPH;
+        const HostGraph &g = it->second;
+        int E = 0;
+        if (sub_sizes(g, a->rows, nullptr, nullptr, nullptr, &E) != LDPC_OK) return LDPC_EINVAL;
+        DevTables *t = nullptr;
+        const int rc = tables_for(g, &t);
+        if (rc != LDPC_OK) return rc;
+        int wmax = 0;
+        for (int r = 0; r < a->rows; ++r) {
+            const int w = g.row_ptr[r + 1] - g.row_ptr[r];
+            if (w > wmax) wmax = w;
+        }
+        p.row_ptr = t->row_ptr;
+        p.meta = t->meta;
+        p.rows = a->rows;
+        p.n_cols = g.kb + a->rows;
+        p.kb = g.kb;
+        p.Z = g.Z;
+        p.E = E;
+        p.wmax = wmax;
+        lds_cap = max_lds_bytes();
+    }
+    p.llr = a->llr_in;
+    p.out_bits = a->out_bits;
+    p.out_iters = a->out_iters;
+    p.out_ok = a->out_ok;
+    p.out_llr = a->out_llr;
+    p.n_cw = a->n_cw;
+    p.max_iter = a->max_iter;
+    p.early_exit = a->early_exit ? 1 : 0;
+    const int Zh = p.Z / 2;
+    const int per_cw = a->precision == LDPC_I8 ? lds_bytes_i8(p.n_cols, p.E, p.Z) + 4
+                                               : lds_bytes_f16(p.n_cols, p.Z) + 4;
+    const int cap_lds = lds_cap / per_cw;
+    const int cap_threads = 512 / Zh;
+    int cpw = a->cw_per_block;
+    if (cpw == 0) {
+        // Default: fill one workgroup up to 256 lanes (int8) or one codeword
+        // per workgroup for large lifts (binary16 shares the CU between
+        // workgroups).
+        cpw = 256 / Zh > 0 ? 256 / Zh : 1;
+        if (a->precision == LDPC_F16) cpw = 128 / Zh > 0 ? 128 / Zh : 1;
+    }
+    if (cpw > cap_lds) cpw = cap_lds;
+    if (cpw > cap_threads) cpw = cap_threads;
+    if (cpw > a->n_cw) cpw = a->n_cw;
+    if (cpw < 1) return LDPC_EINVAL;  // a single codeword does not fit
+    p.cpw = cpw;
+    hipStream_t stream = static_cast<hipStream_t>(a->stream);
+    hipError_t e;
+    if (a->precision == LDPC_I8) {
+        p.wq = a->wq;
+        p.w_iters = a->wq_iters;
+        p.beta = a->beta_q;
+        p.offset = a->offset_q;
+        e = launch_decode_i8(p, stream);
+        if (e != hipSuccess) return hip_fail(e);
+        return LDPC_OK;
+    }
+    p.wh = a->wh;
+    p.w_iters = a->wh_iters;
+    p.beta = a->beta_h;
+    p.offset = a->offset_h;
+    const size_t msg_bytes = (size_t)a->n_cw * p.E * Zh * sizeof(uint32_t);
+    void *msg = nullptr;
+    e = hipMallocAsync(&msg, msg_bytes, stream);
+    if (e != hipSuccess) return hip_fail(e);
+    p.msg = static_cast<uint32_t *>(msg);
+    e = launch_decode_f16(p, stream);
+    const hipError_t ef = hipFreeAsync(msg, stream);
+    if (e != hipSuccess) return hip_fail(e);
+    if (ef != hipSuccess) return hip_fail(ef);
+    return LDPC_OK;
+}
+
+int ldpc_decode(int bg, int Z, int rows, int n_cw, const int8_t *llr_in, int max_iter,
+                uint8_t *out_bits, int32_t *out_iters, void *stream) {
+    ldpc_args a;
+    ldpc_args_init(&a);
+    a.bg = bg;
+    a.Z = Z;
+    a.rows = rows;
+    a.n_cw = n_cw;
+    a.llr_in = llr_in;
+    a.max_iter = max_iter;
+    a.out_bits = out_bits;
+    a.out_iters = out_iters;
+    a.stream = stream;
+    return ldpc_decode_ex(&a);
+}
+
+const char *ldpc_strerror(int code) {
+    switch (code) {
+        case LDPC_OK: return "ok";
+        case LDPC_EINVAL: return "invalid argument";
+        case LDPC_ENOMEM: return "out of memory";
+        case LDPC_EHIP: return "HIP runtime error";
+        case LDPC_ENOGRAPH: return "no graph registered for (bg, Z)";
+        default: return "unknown error";
+    }
+}
+
+int ldpc_last_hip_error(void) { return g_last_hip; }
+
+void ldpc_shutdown(void) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (auto &kv : g_dev) free_tables(kv.second);
+    g_dev.clear();
+}
+
+}  // extern "C"

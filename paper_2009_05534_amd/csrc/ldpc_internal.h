@@ -1,0 +1,55 @@
+// Internal interface between the C-ABI front end (ldpc_api.hip) and the
+// decode kernels (decode_i8.hip, decode_f16.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ldpc {
+
+// Packed per-block metadata for the row-pair layout used by both kernels.
+// With Zh = Z/2, lane u of a codeword owns check rows u and u + Zh of the
+// current block row; block column c of the posteriors is stored as Zh
+// "pair words", word p holding the variables p and p + Zh of that column.
+// A block with shift s = s_lo + Zh*s_hi (s_lo < Zh) sends both rows of lane
+// u to pair word (u + s_lo) mod Zh; the two halves arrive swapped when
+// [u + s_lo >= Zh] xor s_hi.
+//   bits [0, 16)  c * Zh   (first pair word of the column)
+//   bits [16, 24) s_lo
+//   bit  24       s_hi
+__host__ __device__ inline uint32_t pack_meta(int c, int s, int Zh) {
+    return (uint32_t)(c * Zh) | ((uint32_t)(s % Zh) << 16) | ((uint32_t)(s / Zh) << 24);
+}
+
+struct DecodeLaunch {
+    const int8_t *llr;        // [n_cw][T]
+    uint8_t *out_bits;        // [n_cw][K/8]
+    int32_t *out_iters;       // [n_cw]
+    uint8_t *out_ok;          // [n_cw] or null
+    void *out_llr;            // [n_cw][Nc] or null
+    const int32_t *row_ptr;   // device [rows + 1]
+    const uint32_t *meta;     // device [E]
+    const uint8_t *wq;        // int8 path per-(iteration,row) weights or null
+    const uint16_t *wh;       // binary16 path weights or null
+    uint32_t *msg;            // binary16 path: check-to-variable messages
+                              // [n_cw][E][Zh] pair words
+    int w_iters;
+    int n_cw, rows, n_cols, kb, Z, E;
+    int max_iter, early_exit;
+    int beta, offset;         // int8: Q1.7 beta and offset; f16: bit patterns
+    int cpw;                  // codewords per workgroup
+    int wmax;                 // max row weight over the kept rows
+};
+
+// Bytes of LDS one codeword needs in each kernel.
+__host__ __device__ inline int lds_bytes_i8(int n_cols, int E, int Z) { return (n_cols + E) * Z; }
+__host__ __device__ inline int lds_bytes_f16(int n_cols, int Z) { return n_cols * Z * 2; }
+
+// Host launchers; return hipSuccess or the launch error.
+hipError_t launch_decode_i8(const DecodeLaunch &p, hipStream_t stream);
+hipError_t launch_decode_f16(const DecodeLaunch &p, hipStream_t stream);
+
+// Largest dynamic LDS a workgroup may use on the device (bytes).
+int max_lds_bytes();
+
+}  // namespace ldpc

@@ -1,0 +1,197 @@
+"""Python binding of libldpc.so (include/ldpc.h): argument marshalling only.
+
+Every step of decoding runs in the library's HIP kernels; torch supplies
+device memory and the current stream. If the library is missing the binding
+raises -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libldpc.so")
+
+LDPC_I8 = 0
+LDPC_F16 = 1
+_ERRORS = {-1: "invalid argument", -2: "out of memory", -3: "HIP runtime error",
+           -4: "no graph registered for (bg, Z)"}
+
+
+class LdpcError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: {_ERRORS.get(code, 'error')} ({code})")
+        self.code = code
+
+
+class Args(ctypes.Structure):
+    _fields_ = [
+        ("bg", ctypes.c_int), ("Z", ctypes.c_int), ("rows", ctypes.c_int), ("n_cw", ctypes.c_int),
+        ("precision", ctypes.c_int), ("max_iter", ctypes.c_int), ("early_exit", ctypes.c_int),
+        ("llr_in", ctypes.c_void_p),
+        ("beta_q", ctypes.c_int), ("offset_q", ctypes.c_int), ("wq", ctypes.c_void_p),
+        ("wq_iters", ctypes.c_int),
+        ("beta_h", ctypes.c_uint16), ("offset_h", ctypes.c_uint16), ("wh", ctypes.c_void_p),
+        ("wh_iters", ctypes.c_int),
+        ("out_bits", ctypes.c_void_p), ("out_iters", ctypes.c_void_p),
+        ("out_ok", ctypes.c_void_p), ("out_llr", ctypes.c_void_p),
+        ("cw_per_block", ctypes.c_int), ("stream", ctypes.c_void_p),
+    ]
+
+
+EXPORTS = ("ldpc_set_graph", "ldpc_query", "ldpc_decode", "ldpc_args_init", "ldpc_decode_ex",
+           "ldpc_strerror", "ldpc_last_hip_error", "ldpc_shutdown")
+
+_lib = None
+
+
+def lib():
+    """Load libldpc.so (built in-tree by paper_2009_05534_amd/build.py)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run paper_2009_05534_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I = ctypes.c_void_p, ctypes.c_int
+        L.ldpc_set_graph.argtypes = [I, I, I, I, P, P, P]
+        L.ldpc_query.argtypes = [I, I, I, P, P, P, P]
+        L.ldpc_decode.argtypes = [I, I, I, I, P, I, P, P, P]
+        L.ldpc_args_init.argtypes = [ctypes.POINTER(Args)]
+        L.ldpc_args_init.restype = None
+        L.ldpc_decode_ex.argtypes = [ctypes.POINTER(Args)]
+        L.ldpc_strerror.argtypes = [I]
+        L.ldpc_strerror.restype = ctypes.c_char_p
+        L.ldpc_last_hip_error.argtypes = []
+        L.ldpc_shutdown.argtypes = []
+        L.ldpc_shutdown.restype = None
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise LdpcError(rc, what)
+
+
+def set_graph(bg: int, Z: int, m_rows: int, kb: int, row_ptr, col, shift) -> None:
+    """Register base graph ``bg`` lifted by ``Z`` (host arrays, copied)."""
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    c = np.ascontiguousarray(col, dtype=np.int16)
+    s = np.ascontiguousarray(shift, dtype=np.int16)
+    _check(lib().ldpc_set_graph(bg, Z, m_rows, kb, rp.ctypes.data, c.ctypes.data, s.ctypes.data),
+           "ldpc_set_graph")
+
+
+def register(g) -> None:
+    """Register a full graph object with fields bg, Z, M, kb, row_ptr, col, shift."""
+    set_graph(g.bg, g.Z, g.M, g.kb, g.row_ptr, g.col, g.shift)
+
+
+def query(bg: int, Z: int, rows: int) -> tuple[int, int, int, int]:
+    """(K, T, Nc, E) of the sub-code keeping ``rows`` block rows."""
+    out = [ctypes.c_int() for _ in range(4)]
+    _check(lib().ldpc_query(bg, Z, rows, *[ctypes.addressof(o) for o in out]), "ldpc_query")
+    return tuple(o.value for o in out)
+
+
+def _require(t, shape, itemsize, name):
+    """Device tensor of exactly ``shape``, contiguous, with ``itemsize``-byte
+    elements: the library trusts the sizes it is given."""
+    if (not t.is_cuda or tuple(t.shape) != tuple(shape) or not t.is_contiguous()
+            or t.element_size() != itemsize):
+        raise ValueError(f"{name}: need a contiguous device tensor {tuple(shape)} "
+                         f"of {itemsize}-byte elements, got {tuple(t.shape)} {t.dtype}")
+
+
+def _f16_bits(v: float) -> int:
+    return int(np.array([v], dtype=np.float16).view(np.uint16)[0])
+
+
+def _stream_ptr(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def decode_into(llr, bg: int, Z: int, rows: int, out_bits, out_iters, *, max_iter: int = 10,
+                precision: str = "i8", early_exit: bool = True, beta: float | None = None,
+                offset: float = 0, weights=None, out_ok=None, out_llr=None,
+                cw_per_block: int = 0, stream=None) -> None:
+    """Decode int8 LLRs [n_cw, T] (device tensor) into preallocated outputs.
+
+    ``weights``: per-(iteration, row) normalisation, a device tensor uint8
+    [iters, rows] (Q1.7, i8) or float16 [iters, rows] (f16).
+    ``beta``/``offset``: plain normalisation (i8: beta in units of 1/128 is
+    taken from ``round(128*beta)``, offset an integer; f16: binary16 values).
+    """
+    n_cw = int(llr.shape[0])
+    K, T, Nc, _ = query(bg, Z, rows)
+    _require(llr, (n_cw, T), 1, "llr")
+    _require(out_bits, (n_cw, K // 8), 1, "out_bits")
+    _require(out_iters, (n_cw,), 4, "out_iters")
+    if out_ok is not None:
+        _require(out_ok, (n_cw,), 1, "out_ok")
+    if out_llr is not None:
+        _require(out_llr, (n_cw, Nc), 1 if precision == "i8" else 2, "out_llr")
+    if weights is not None:
+        if weights.dim() != 2 or weights.shape[1] != rows or weights.shape[0] < 1:
+            raise ValueError("weights must be [iters, rows]")
+        _require(weights, tuple(weights.shape), 1 if precision == "i8" else 2, "weights")
+    a = Args()
+    lib().ldpc_args_init(ctypes.byref(a))
+    a.bg, a.Z, a.rows, a.n_cw = bg, Z, rows, n_cw
+    a.precision = LDPC_I8 if precision == "i8" else LDPC_F16
+    if precision not in ("i8", "f16"):
+        raise ValueError("precision must be 'i8' or 'f16'")
+    a.max_iter = max_iter
+    a.early_exit = 1 if early_exit else 0
+    a.llr_in = llr.data_ptr()
+    if precision == "i8":
+        if beta is not None:
+            a.beta_q = int(round(beta * 128))
+        a.offset_q = int(offset)
+        if weights is not None:
+            a.wq = weights.data_ptr()
+            a.wq_iters = int(weights.shape[0])
+    else:
+        if beta is not None:
+            a.beta_h = _f16_bits(beta)
+        a.offset_h = _f16_bits(offset)
+        if weights is not None:
+            a.wh = weights.data_ptr()
+            a.wh_iters = int(weights.shape[0])
+    a.out_bits = out_bits.data_ptr()
+    a.out_iters = out_iters.data_ptr()
+    a.out_ok = out_ok.data_ptr() if out_ok is not None else None
+    a.out_llr = out_llr.data_ptr() if out_llr is not None else None
+    a.cw_per_block = cw_per_block
+    a.stream = _stream_ptr(stream)
+    _check(lib().ldpc_decode_ex(ctypes.byref(a)), "ldpc_decode_ex")
+
+
+def decode(llr, bg: int, Z: int, rows: int, *, max_iter: int = 10, precision: str = "i8",
+           early_exit: bool = True, beta: float | None = None, offset: float = 0, weights=None,
+           want_ok: bool = True, want_llr: bool = False, cw_per_block: int = 0, stream=None):
+    """Allocate outputs with torch on llr's device and decode.
+
+    Returns (bits uint8 [n, K/8], iters int32 [n], ok bool [n] or None,
+    llr int8/float16 [n, Nc] or None)."""
+    import torch
+    K, T, Nc, E = query(bg, Z, rows)
+    if llr.dim() != 2 or llr.dtype != torch.int8:
+        raise ValueError(f"llr must be a device int8 tensor [n_cw, {T}]")
+    n = int(llr.shape[0])
+    dev = llr.device
+    bits = torch.empty((n, K // 8), dtype=torch.uint8, device=dev)
+    iters = torch.empty(n, dtype=torch.int32, device=dev)
+    ok = torch.empty(n, dtype=torch.uint8, device=dev) if want_ok else None
+    out = None
+    if want_llr:
+        out = torch.empty((n, Nc), dtype=torch.int8 if precision == "i8" else torch.float16,
+                          device=dev)
+    decode_into(llr, bg, Z, rows, bits, iters, max_iter=max_iter, precision=precision,
+                early_exit=early_exit, beta=beta, offset=offset, weights=weights, out_ok=ok,
+                out_llr=out, cw_per_block=cw_per_block, stream=stream)
+    return bits, iters, (ok.bool() if ok is not None else None), out

@@ -75,6 +75,30 @@ def make_batch(g: BaseGraph, n_cw: int, ebn0_db, data_seed: int, start: int = 0,
     return Batch(u=u, c=c, llr=llr.astype(np.float32), q=quantize(llr), ebn0=ebn0)
 
 
+def _chunk(args):
+    g, n, ebn0, seed, start = args
+    return make_batch(g, n, ebn0, seed, start=start)
+
+
+def make_batch_parallel(g: BaseGraph, n_cw: int, ebn0_db, data_seed: int, start: int = 0,
+                        workers: int = 8) -> Batch:
+    """``make_batch`` split over worker processes; the result is identical
+    because every codeword is keyed by its own index."""
+    if workers <= 1 or n_cw < 64:
+        return make_batch(g, n_cw, ebn0_db, data_seed, start=start)
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    ebn0 = np.broadcast_to(np.asarray(ebn0_db, dtype=np.float64), (n_cw,))
+    bounds = np.linspace(0, n_cw, workers + 1).astype(int)
+    jobs = [(g, int(b - a), ebn0[a:b].copy(), data_seed, start + int(a))
+            for a, b in zip(bounds[:-1], bounds[1:]) if b > a]
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("fork")) as ex:
+        parts = list(ex.map(_chunk, jobs))
+    return Batch(u=np.concatenate([p.u for p in parts]), c=np.concatenate([p.c for p in parts]),
+                 llr=np.concatenate([p.llr for p in parts]), q=np.concatenate([p.q for p in parts]),
+                 ebn0=np.concatenate([p.ebn0 for p in parts]))
+
+
 def noiseless_q(c: np.ndarray, g: BaseGraph, mag: int = 8) -> np.ndarray:
     """int8 LLRs of magnitude ``mag`` with the sign of each transmitted bit."""
     tx = np.asarray(c, dtype=np.int16)[:, g.n_punct * g.Z:]
