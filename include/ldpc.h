@@ -142,6 +142,10 @@ int ldpc_decode_ex(const ldpc_args *a);
 const char *ldpc_strerror(int code);
 int ldpc_last_hip_error(void);
 
+/* Text naming the last failed HIP call on this thread and its error
+ * ("" if none). */
+const char *ldpc_last_error_message(void);
+
 /* Release every device table the library holds (graphs). */
 void ldpc_shutdown(void);
 

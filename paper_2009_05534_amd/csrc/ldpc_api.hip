@@ -2,6 +2,7 @@
 // registry (host copies plus lazily uploaded per-device tables), launch
 // configuration and error reporting. Declarations and contracts:
 // include/ldpc.h.
+#include <cstdio>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -28,10 +29,12 @@ std::mutex g_mu;
 std::map<std::pair<int, int>, HostGraph> g_graphs;                 // (bg, Z)
 std::map<std::tuple<int, int, int>, DevTables> g_dev;             // (device, bg, Z)
 std::map<int, int> g_lds;                                          // device -> bytes
+std::mutex g_lds_mu;
 int g_last_hip = 0;
+thread_local char g_msg[256] = "";
 
-int hip_fail(hipError_t e) {
-    g_last_hip = (int)e;
+int hip_fail(hipError_t e, const char *where = "HIP call") {
+    note_hip_error(where, e);
     return e == hipErrorOutOfMemory ? LDPC_ENOMEM : LDPC_EHIP;
 }
 
@@ -85,9 +88,15 @@ int sub_sizes(const HostGraph &g, int rows, int *K, int *T, int *Nc, int *E) {
 
 }  // namespace
 
+void note_hip_error(const char *where, hipError_t e) {
+    g_last_hip = (int)e;
+    snprintf(g_msg, sizeof(g_msg), "%s: %s (%d)", where, hipGetErrorName(e), (int)e);
+}
+
 int max_lds_bytes() {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 65536;
+    std::lock_guard<std::mutex> lk(g_lds_mu);
     auto it = g_lds.find(dev);
     if (it != g_lds.end()) return it->second;
     int v = 0;
@@ -232,7 +241,7 @@ int ldpc_decode_ex(const ldpc_args *a) {
         p.beta = a->beta_q;
         p.offset = a->offset_q;
         e = launch_decode_i8(p, stream);
-        if (e != hipSuccess) return hip_fail(e);
+        if (e != hipSuccess) return e == hipErrorOutOfMemory ? LDPC_ENOMEM : LDPC_EHIP;
         return LDPC_OK;
     }
     p.wh = a->wh;
@@ -242,12 +251,12 @@ int ldpc_decode_ex(const ldpc_args *a) {
     const size_t msg_bytes = (size_t)a->n_cw * p.E * Zh * sizeof(uint32_t);
     void *msg = nullptr;
     e = hipMallocAsync(&msg, msg_bytes, stream);
-    if (e != hipSuccess) return hip_fail(e);
+    if (e != hipSuccess) return hip_fail(e, "hipMallocAsync(messages)");
     p.msg = static_cast<uint32_t *>(msg);
     e = launch_decode_f16(p, stream);
     const hipError_t ef = hipFreeAsync(msg, stream);
-    if (e != hipSuccess) return hip_fail(e);
-    if (ef != hipSuccess) return hip_fail(ef);
+    if (e != hipSuccess) return e == hipErrorOutOfMemory ? LDPC_ENOMEM : LDPC_EHIP;
+    if (ef != hipSuccess) return hip_fail(ef, "hipFreeAsync(messages)");
     return LDPC_OK;
 }
 
@@ -279,6 +288,8 @@ const char *ldpc_strerror(int code) {
 }
 
 int ldpc_last_hip_error(void) { return g_last_hip; }
+
+const char *ldpc_last_error_message(void) { return g_msg; }
 
 void ldpc_shutdown(void) {
     std::lock_guard<std::mutex> lk(g_mu);

@@ -52,4 +52,7 @@ hipError_t launch_decode_f16(const DecodeLaunch &p, hipStream_t stream);
 // Largest dynamic LDS a workgroup may use on the device (bytes).
 int max_lds_bytes();
 
+// Remember a failed HIP call for ldpc_last_error_message().
+void note_hip_error(const char *where, hipError_t e);
+
 }  // namespace ldpc

@@ -42,7 +42,7 @@ class Args(ctypes.Structure):
 
 
 EXPORTS = ("ldpc_set_graph", "ldpc_query", "ldpc_decode", "ldpc_args_init", "ldpc_decode_ex",
-           "ldpc_strerror", "ldpc_last_hip_error", "ldpc_shutdown")
+           "ldpc_strerror", "ldpc_last_hip_error", "ldpc_last_error_message", "ldpc_shutdown")
 
 _lib = None
 
@@ -64,6 +64,8 @@ def lib():
         L.ldpc_strerror.argtypes = [I]
         L.ldpc_strerror.restype = ctypes.c_char_p
         L.ldpc_last_hip_error.argtypes = []
+        L.ldpc_last_error_message.argtypes = []
+        L.ldpc_last_error_message.restype = ctypes.c_char_p
         L.ldpc_shutdown.argtypes = []
         L.ldpc_shutdown.restype = None
         _lib = L
@@ -72,7 +74,8 @@ def lib():
 
 def _check(rc: int, what: str):
     if rc != 0:
-        raise LdpcError(rc, what)
+        detail = lib().ldpc_last_error_message().decode() if rc == -3 or rc == -2 else ""
+        raise LdpcError(rc, what + (f" [{detail}]" if detail else ""))
 
 
 def set_graph(bg: int, Z: int, m_rows: int, kb: int, row_ptr, col, shift) -> None:

@@ -57,6 +57,8 @@ def oracle_i8(g, q, **kw):
         kw2["wq"] = np.full((1, g.M), int(round(b * 128)), np.uint8)
     if "weights" in kw2:
         kw2["wq"] = kw2.pop("weights")
+    if "offset" in kw2:
+        kw2["delta"] = kw2.pop("offset")
     kw2.pop("cw_per_block", None)
     return oracle.decode_i8(g, q, want_llr=True, n_threads=8, **kw2)
 
@@ -65,6 +67,8 @@ def oracle_f16(g, q, **kw):
     kw2 = dict(kw)
     if "weights" in kw2:
         kw2["wh"] = kw2.pop("weights").view(np.uint16)
+    if "offset" in kw2:
+        kw2["delta"] = kw2.pop("offset")
     kw2.pop("cw_per_block", None)
     return oracle.decode_f16(g, q, want_llr=True, n_threads=8, **kw2)
 
