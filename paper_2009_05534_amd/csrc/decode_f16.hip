@@ -53,69 +53,124 @@ __device__ inline uint32_t normalise(uint32_t m, uint32_t off, h16x2 w) {
     return bits_of(w * v);
 }
 
-template <int WMAX>
-__device__ inline void row_update(uint32_t *__restrict__ Lw, uint32_t *__restrict__ Rg,
-                                  const uint32_t *__restrict__ meta, int e0, int w, int u, int Zh,
-                                  bool first_iter, h16x2 wgt, uint32_t off) {
-    uint32_t xv[WMAX], axv[WMAX];
-    int la[WMAX];
-    bool sw[WMAX];
+// One block row of exactly W blocks for lane u (rows u and u + Zh). As in
+// the int8 kernel the row is branch-free: metadata in one batch of scalar
+// loads, then every read (posteriors from LDS, messages from device memory)
+// before any arithmetic.
+template <int W>
+__device__ __forceinline__ void row_update_w(uint32_t *__restrict__ Lw, uint32_t *__restrict__ Rg,
+                                             const uint32_t *__restrict__ meta, int e0, int u,
+                                             int Zh, bool first_iter, h16x2 wgt, uint32_t off) {
+    uint32_t md[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) md[k] = meta[e0 + k];
+    uint32_t lraw[W], rraw[W];
+    int la[W];
+    bool sw[W];
+    if (!first_iter) {
+#pragma unroll
+        for (int k = 0; k < W; ++k) rraw[k] = Rg[(size_t)(e0 + k) * Zh + u];
+    } else {
+#pragma unroll
+        for (int k = 0; k < W; ++k) rraw[k] = 0;
+    }
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        const Gather g = gather(md[k], u, Zh);
+        la[k] = g.addr;
+        sw[k] = g.swap;
+        lraw[k] = Lw[g.addr];
+    }
+    uint32_t xv[W], axv[W];
     u16x2 m1 = {0x7C00, 0x7C00}, m2 = {0x7C00, 0x7C00};
     uint32_t S = 0;
 #pragma unroll
-    for (int k = 0; k < WMAX; ++k) {
-        if (k < w) {
-            const Gather g = gather(meta[e0 + k], u, Zh);
-            la[k] = g.addr;
-            sw[k] = g.swap;
-            const h16x2 L = as_h(swap_halves(Lw[g.addr], g.swap));
-            h16x2 x = L;
-            if (!first_iter) x = L - as_h(Rg[(size_t)(e0 + k) * Zh + u]);
-            const uint32_t xb = bits_of(x);
-            const u16x2 ax = as_u(xb & 0x7FFF7FFFu);
-            m2 = __builtin_elementwise_min(m2, __builtin_elementwise_max(m1, ax));
-            m1 = __builtin_elementwise_min(m1, ax);
-            S ^= xb;
-            xv[k] = xb;
-            axv[k] = bits_of(ax);
-        }
+    for (int k = 0; k < W; ++k) {
+        const h16x2 L = as_h(swap_halves(lraw[k], sw[k]));
+        const h16x2 x = L - as_h(rraw[k]);
+        const uint32_t xb = bits_of(x);
+        const u16x2 ax = as_u(xb & 0x7FFF7FFFu);
+        m2 = __builtin_elementwise_min(m2, __builtin_elementwise_max(m1, ax));
+        m1 = __builtin_elementwise_min(m1, ax);
+        S ^= xb;
+        xv[k] = xb;
+        axv[k] = bits_of(ax);
     }
     const uint32_t a1 = normalise(bits_of(m1), off, wgt);
     const uint32_t a2 = normalise(bits_of(m2), off, wgt);
     const u16x2 m1p = m1 + (u16x2){1, 1};
 #pragma unroll
-    for (int k = 0; k < WMAX; ++k) {
-        if (k < w) {
-            // mask = 0xFFFF on the argmin edge (|x| == m1), else 0.
-            const u16x2 t = __builtin_elementwise_sub_sat(m1p, as_u(axv[k]));
-            const uint32_t mask = bits_of((u16x2){0, 0} - t);
-            const uint32_t mag = (a2 & mask) | (a1 & ~mask);
-            const uint32_t Rn = mag | ((S ^ xv[k]) & 0x80008000u);
-            const h16x2 Ln = as_h(xv[k]) + as_h(Rn);
-            Lw[la[k]] = swap_halves(bits_of(Ln), sw[k]);
-            Rg[(size_t)(e0 + k) * Zh + u] = Rn;
-        }
+    for (int k = 0; k < W; ++k) {
+        // mask = 0xFFFF on the argmin edge (|x| == m1), else 0.
+        const u16x2 t = __builtin_elementwise_sub_sat(m1p, as_u(axv[k]));
+        const uint32_t mask = bits_of((u16x2){0, 0} - t);
+        const uint32_t mag = (a2 & mask) | (a1 & ~mask);
+        const uint32_t Rn = mag | ((S ^ xv[k]) & 0x80008000u);
+        const h16x2 Ln = as_h(xv[k]) + as_h(Rn);
+        Lw[la[k]] = swap_halves(bits_of(Ln), sw[k]);
+        Rg[(size_t)(e0 + k) * Zh + u] = Rn;
     }
 }
 
-// Nonzero if some check of lane u's rows fails; hard decision [L_v < 0]
-// (negative zero decides 0).
+// Parity of lane u's rows over a row of exactly W blocks (bits 15 and 31);
+// hard decision [L_v < 0], negative zero decides 0.
+template <int W>
+__device__ __forceinline__ uint32_t row_parity_w(const uint32_t *__restrict__ Lw,
+                                                 const uint32_t *__restrict__ meta, int e0, int u,
+                                                 int Zh) {
+    uint32_t md[W], raw[W];
+    bool sw[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) md[k] = meta[e0 + k];
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        const Gather g = gather(md[k], u, Zh);
+        sw[k] = g.swap;
+        raw[k] = Lw[g.addr];
+    }
+    uint32_t acc = 0;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        const uint32_t v = swap_halves(raw[k], sw[k]);
+        const uint32_t lo = (v & 0xFFFFu) > 0x8000u ? 0x8000u : 0u;
+        const uint32_t hi = (v >> 16) > 0x8000u ? 0x80000000u : 0u;
+        acc ^= lo | hi;
+    }
+    return acc;
+}
+
+template <int W, int WMAX>
+__device__ __forceinline__ void row_update(int w, uint32_t *Lw, uint32_t *Rg, const uint32_t *meta,
+                                           int e0, int u, int Zh, bool first_iter, h16x2 wgt,
+                                           uint32_t off) {
+    if constexpr (W <= WMAX) {
+        if (w == W) {
+            row_update_w<W>(Lw, Rg, meta, e0, u, Zh, first_iter, wgt, off);
+            return;
+        }
+        row_update<W + 1, WMAX>(w, Lw, Rg, meta, e0, u, Zh, first_iter, wgt, off);
+    }
+}
+
+template <int W, int WMAX>
+__device__ __forceinline__ uint32_t row_parity(int w, const uint32_t *Lw, const uint32_t *meta,
+                                               int e0, int u, int Zh) {
+    if constexpr (W <= WMAX) {
+        if (w == W) return row_parity_w<W>(Lw, meta, e0, u, Zh);
+        return row_parity<W + 1, WMAX>(w, Lw, meta, e0, u, Zh);
+    }
+    return 0;
+}
+
+// Nonzero if some check of lane u's rows fails.
+template <int WMAX>
 __device__ inline bool syndrome_fails(const uint32_t *__restrict__ Lw,
                                       const int32_t *__restrict__ row_ptr,
                                       const uint32_t *__restrict__ meta, int rows, int u, int Zh) {
     uint32_t bad = 0;
     for (int r = 0; r < rows; ++r) {
-        const int e0 = row_ptr[r], e1 = row_ptr[r + 1];
-        uint32_t acc = 0;
-        for (int e = e0; e < e1; ++e) {
-            const Gather g = gather(meta[e], u, Zh);
-            const uint32_t v = swap_halves(Lw[g.addr], g.swap);
-            // bit 15/31 set iff the half is strictly negative
-            const uint32_t lo = (v & 0xFFFFu) > 0x8000u ? 0x8000u : 0u;
-            const uint32_t hi = (v >> 16) > 0x8000u ? 0x80000000u : 0u;
-            acc ^= lo | hi;
-        }
-        bad |= acc;
+        const int e0 = row_ptr[r], w = row_ptr[r + 1] - e0;
+        bad |= row_parity<2, WMAX>(w, Lw, meta, e0, u, Zh);
     }
     return bad != 0;
 }
@@ -124,6 +179,7 @@ template <int WMAX>
 __global__ __launch_bounds__(512) void decode_f16_kernel(DecodeLaunch p,
                                                          const int32_t *__restrict__ row_ptr,
                                                          const uint32_t *__restrict__ meta) {
+    static_assert(WMAX <= kMetaPad, "row metadata window exceeds the table padding");
     extern __shared__ __align__(16) uint8_t smem[];
     const int Z = p.Z, Zh = Z >> 1;
     const int N = p.n_cols, E = p.E, T = (N - 2) * Z;
@@ -161,13 +217,13 @@ __global__ __launch_bounds__(512) void decode_f16_kernel(DecodeLaunch p,
             const int e0 = row_ptr[r], w = row_ptr[r + 1] - e0;
             if (wrow) wt = wrow[r];
             const h16x2 wgt = as_h(wt * 0x00010001u);
-            if (!done) row_update<WMAX>(Lw, Rg, meta, e0, w, u, Zh, t == 1, wgt, off);
+            if (!done) row_update<2, WMAX>(w, Lw, Rg, meta, e0, u, Zh, t == 1, wgt, off);
             __syncthreads();
         }
         if (p.early_exit || t == p.max_iter) {
             if ((int)threadIdx.x < p.cpw) flags[threadIdx.x] = 0;
             __syncthreads();
-            if (!done && syndrome_fails(Lw, row_ptr, meta, p.rows, u, Zh))
+            if (!done && syndrome_fails<WMAX>(Lw, row_ptr, meta, p.rows, u, Zh))
                 atomicOr(&flags[slot], 1);
             __syncthreads();
             const bool holds = flags[slot] == 0;

@@ -69,38 +69,54 @@ __device__ inline Gather gather(uint32_t md, int u, int Zh) {
     return g;
 }
 
-// One block row for lane u (rows u and u + Zh): variable-to-check messages,
-// min / second min / sign product, normalisation, check-to-variable
-// messages and posterior write-back.
-template <int WMAX>
-__device__ inline void row_update(uint16_t *__restrict__ Lw, uint16_t *__restrict__ Rw,
-                                  const uint32_t *__restrict__ meta, int e0, int w, int u, int Zh,
-                                  bool first_iter, u16x2 wgt, u16x2 off16) {
-    uint32_t xv[WMAX], axv[WMAX], sp[WMAX];
-    int la[WMAX];
+// One block row of exactly W blocks for lane u (rows u and u + Zh):
+// variable-to-check messages, min / second min / sign product,
+// normalisation, check-to-variable messages and posterior write-back.
+// Specialising on W keeps the row free of branches, so the row's metadata
+// arrives in one batch of scalar loads and every LDS read is issued before
+// any arithmetic (scalar and LDS loads share one completion counter; a
+// scalar result consumed between LDS reads would serialise them).
+template <int W>
+__device__ __forceinline__ void row_update_w(uint16_t *__restrict__ Lw,
+                                             uint16_t *__restrict__ Rw,
+                                             const uint32_t *__restrict__ meta, int e0, int u,
+                                             int Zh, bool first_iter, u16x2 wgt, u16x2 off16) {
+    uint32_t md[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) md[k] = meta[e0 + k];
+    uint32_t lraw[W], rraw[W], su[W], sp[W];
+    int la[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        const Gather g = gather(md[k], u, Zh);
+        la[k] = g.addr;
+        su[k] = g.sel_unpack;
+        sp[k] = g.sel_pack;
+        lraw[k] = Lw[g.addr];
+    }
+    if (!first_iter) {
+#pragma unroll
+        for (int k = 0; k < W; ++k) rraw[k] = Rw[(e0 + k) * Zh + u];
+    } else {
+#pragma unroll
+        for (int k = 0; k < W; ++k) rraw[k] = 0;
+    }
+    uint32_t xv[W], axv[W];
     u16x2 m1 = {0x7FFF, 0x7FFF}, m2 = {0x7FFF, 0x7FFF};
     uint32_t S = 0;
 #pragma unroll
-    for (int k = 0; k < WMAX; ++k) {
-        if (k < w) {
-            const Gather g = gather(meta[e0 + k], u, Zh);
-            la[k] = g.addr;
-            sp[k] = g.sel_pack;
-            const s16x2 L = as_s(perm(Lw[g.addr], g.sel_unpack));
-            s16x2 x = L;
-            if (!first_iter) {
-                const s16x2 R = as_s(perm(Rw[(e0 + k) * Zh + u], kUnpack));
-                x = __builtin_elementwise_sub_sat(L, R);
-                x = __builtin_elementwise_max(x, (s16x2){-127 * 256, -127 * 256});
-            }
-            const s16x2 ax = __builtin_elementwise_max(x, (s16x2){0, 0} - x);
-            const u16x2 axu = as_u(bits_of(ax));
-            m2 = __builtin_elementwise_min(m2, __builtin_elementwise_max(m1, axu));
-            m1 = __builtin_elementwise_min(m1, axu);
-            S ^= bits_of(x);
-            xv[k] = bits_of(x);
-            axv[k] = bits_of(ax);
-        }
+    for (int k = 0; k < W; ++k) {
+        const s16x2 L = as_s(perm(lraw[k], su[k]));
+        const s16x2 R = as_s(perm(rraw[k], kUnpack));
+        s16x2 x = __builtin_elementwise_sub_sat(L, R);
+        x = __builtin_elementwise_max(x, (s16x2){-127 * 256, -127 * 256});
+        const s16x2 ax = __builtin_elementwise_max(x, (s16x2){0, 0} - x);
+        const u16x2 axu = as_u(bits_of(ax));
+        m2 = __builtin_elementwise_min(m2, __builtin_elementwise_max(m1, axu));
+        m1 = __builtin_elementwise_min(m1, axu);
+        S ^= bits_of(x);
+        xv[k] = bits_of(x);
+        axv[k] = bits_of(ax);
     }
     const u16x2 a1 = normalise(m1, off16, wgt);
     const u16x2 a2 = normalise(m2, off16, wgt);
@@ -112,38 +128,77 @@ __device__ inline void row_update(uint16_t *__restrict__ Lw, uint16_t *__restric
     const u16x2 d21 = as_u(bits_of(b2 - b1));
     const u16x2 m1p = m1 + (u16x2){1, 1};
 #pragma unroll
-    for (int k = 0; k < WMAX; ++k) {
-        if (k < w) {
-            // t = 1 on the argmin edge (|x| == m1), else 0.
-            const u16x2 t = __builtin_elementwise_sub_sat(m1p, as_u(axv[k]));
-            const s16x2 b = as_s(bits_of(t * d21 + as_u(bits_of(b1))));
-            // L' = sgn(x) * min(|x| + b, 127); R' = sgn(x) * b.
-            s16x2 v = __builtin_elementwise_add_sat(as_s(axv[k]), b);
-            v = as_s(bits_of(v) & 0xFF00FF00u);
-            const s16x2 sx = as_s(xv[k]) >> (s16x2){15, 15};
-            const s16x2 Ln = (v ^ sx) - sx;
-            const s16x2 Rn = (b ^ sx) - sx;
-            Lw[la[k]] = (uint16_t)perm(bits_of(Ln), sp[k]);
-            Rw[(e0 + k) * Zh + u] = (uint16_t)perm(bits_of(Rn), kPack);
-        }
+    for (int k = 0; k < W; ++k) {
+        // t = 1 on the argmin edge (|x| == m1), else 0.
+        const u16x2 t = __builtin_elementwise_sub_sat(m1p, as_u(axv[k]));
+        const s16x2 b = as_s(bits_of(t * d21 + as_u(bits_of(b1))));
+        // L' = sgn(x) * min(|x| + b, 127); R' = sgn(x) * b.
+        s16x2 v = __builtin_elementwise_add_sat(as_s(axv[k]), b);
+        v = as_s(bits_of(v) & 0xFF00FF00u);
+        const s16x2 sx = as_s(xv[k]) >> (s16x2){15, 15};
+        const s16x2 Ln = (v ^ sx) - sx;
+        const s16x2 Rn = (b ^ sx) - sx;
+        Lw[la[k]] = (uint16_t)perm(bits_of(Ln), sp[k]);
+        Rw[(e0 + k) * Zh + u] = (uint16_t)perm(bits_of(Rn), kPack);
     }
 }
 
+// Parity of lane u's two rows over a row of exactly W blocks, as sign bits
+// 15 and 31 (hard decision [L_v < 0]).
+template <int W>
+__device__ __forceinline__ uint32_t row_parity_w(const uint16_t *__restrict__ Lw,
+                                                 const uint32_t *__restrict__ meta, int e0, int u,
+                                                 int Zh) {
+    uint32_t md[W], raw[W], su[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) md[k] = meta[e0 + k];
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        const Gather g = gather(md[k], u, Zh);
+        su[k] = g.sel_unpack;
+        raw[k] = Lw[g.addr];
+    }
+    uint32_t acc = 0;
+#pragma unroll
+    for (int k = 0; k < W; ++k) acc ^= perm(raw[k], su[k]);
+    return acc;
+}
+
+// Scalar dispatch on the row weight w in [W, WMAX].
+template <int W, int WMAX>
+__device__ __forceinline__ void row_update(int w, uint16_t *Lw, uint16_t *Rw, const uint32_t *meta,
+                                           int e0, int u, int Zh, bool first_iter, u16x2 wgt,
+                                           u16x2 off16) {
+    if constexpr (W <= WMAX) {
+        if (w == W) {
+            row_update_w<W>(Lw, Rw, meta, e0, u, Zh, first_iter, wgt, off16);
+            return;
+        }
+        row_update<W + 1, WMAX>(w, Lw, Rw, meta, e0, u, Zh, first_iter, wgt, off16);
+    }
+}
+
+template <int W, int WMAX>
+__device__ __forceinline__ uint32_t row_parity(int w, const uint16_t *Lw, const uint32_t *meta,
+                                               int e0, int u, int Zh) {
+    if constexpr (W <= WMAX) {
+        if (w == W) return row_parity_w<W>(Lw, meta, e0, u, Zh);
+        return row_parity<W + 1, WMAX>(w, Lw, meta, e0, u, Zh);
+    }
+    return 0;
+}
+
 // Nonzero if some check of lane u's two rows fails on the current hard
-// decisions (bit = [L_v < 0]).
+// decisions.
+template <int WMAX>
 __device__ inline uint32_t syndrome_fails(const uint16_t *__restrict__ Lw,
                                           const int32_t *__restrict__ row_ptr,
                                           const uint32_t *__restrict__ meta, int rows, int u,
                                           int Zh) {
     uint32_t bad = 0;
     for (int r = 0; r < rows; ++r) {
-        const int e0 = row_ptr[r], e1 = row_ptr[r + 1];
-        uint32_t acc = 0;
-        for (int e = e0; e < e1; ++e) {
-            const Gather g = gather(meta[e], u, Zh);
-            acc ^= perm(Lw[g.addr], g.sel_unpack);
-        }
-        bad |= acc;
+        const int e0 = row_ptr[r], w = row_ptr[r + 1] - e0;
+        bad |= row_parity<2, WMAX>(w, Lw, meta, e0, u, Zh);
     }
     return bad & 0x80008000u;
 }
@@ -152,6 +207,7 @@ template <int WMAX>
 __global__ __launch_bounds__(512) void decode_i8_kernel(DecodeLaunch p,
                                                          const int32_t *__restrict__ row_ptr,
                                                          const uint32_t *__restrict__ meta) {
+    static_assert(WMAX <= kMetaPad, "row metadata window exceeds the table padding");
     extern __shared__ __align__(16) uint8_t smem[];
     const int Z = p.Z, Zh = Z >> 1;
     const int N = p.n_cols, E = p.E, T = (N - 2) * Z;
@@ -189,13 +245,13 @@ __global__ __launch_bounds__(512) void decode_i8_kernel(DecodeLaunch p,
             const int e0 = row_ptr[r], w = row_ptr[r + 1] - e0;
             if (wrow) wt = wrow[r];
             const u16x2 wgt = {(unsigned short)wt, (unsigned short)wt};
-            if (!done) row_update<WMAX>(Lw, Rw, meta, e0, w, u, Zh, t == 1, wgt, off16);
+            if (!done) row_update<2, WMAX>(w, Lw, Rw, meta, e0, u, Zh, t == 1, wgt, off16);
             __syncthreads();
         }
         if (p.early_exit || t == p.max_iter) {
             if ((int)threadIdx.x < p.cpw) flags[threadIdx.x] = 0;
             __syncthreads();
-            if (!done && syndrome_fails(Lw, row_ptr, meta, p.rows, u, Zh))
+            if (!done && syndrome_fails<WMAX>(Lw, row_ptr, meta, p.rows, u, Zh))
                 atomicOr(&flags[slot], 1);
             __syncthreads();
             const bool holds = flags[slot] == 0;

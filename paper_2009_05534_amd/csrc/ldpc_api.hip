@@ -60,15 +60,15 @@ int tables_for(const HostGraph &g, DevTables **out) {
     }
     const int Zh = g.Z / 2;
     const int E = g.row_ptr.back();
-    std::vector<uint32_t> meta(E);
+    std::vector<uint32_t> meta(E + kMetaPad, 0u);
     for (int e2 = 0; e2 < E; ++e2) meta[e2] = pack_meta(g.col[e2], g.shift[e2], Zh);
     DevTables t;
     if ((e = hipMalloc(&t.row_ptr, sizeof(int32_t) * g.row_ptr.size())) != hipSuccess ||
-        (e = hipMalloc(&t.meta, sizeof(uint32_t) * E)) != hipSuccess ||
+        (e = hipMalloc(&t.meta, sizeof(uint32_t) * meta.size())) != hipSuccess ||
         (e = hipMemcpy(t.row_ptr, g.row_ptr.data(), sizeof(int32_t) * g.row_ptr.size(),
                        hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(t.meta, meta.data(), sizeof(uint32_t) * E, hipMemcpyHostToDevice)) !=
-            hipSuccess) {
+        (e = hipMemcpy(t.meta, meta.data(), sizeof(uint32_t) * meta.size(),
+                       hipMemcpyHostToDevice)) != hipSuccess) {
         free_tables(t);
         return hip_fail(e);
     }

@@ -17,6 +17,10 @@ namespace ldpc {
 //   bits [0, 16)  c * Zh   (first pair word of the column)
 //   bits [16, 24) s_lo
 //   bit  24       s_hi
+// The device copy of the table carries kMetaPad zero entries after the last
+// block so that a kernel may read a fixed-size window from any row start.
+constexpr int kMetaPad = 64;
+
 __host__ __device__ inline uint32_t pack_meta(int c, int s, int Zh) {
     return (uint32_t)(c * Zh) | ((uint32_t)(s % Zh) << 16) | ((uint32_t)(s / Zh) << 24);
 }
