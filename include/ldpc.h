@@ -124,16 +124,28 @@ typedef struct ldpc_args {
                                variable order: int8 (I8) or binary16 (F16) */
     int cw_per_block;       /* 0 = library default; else codewords per
                                workgroup (tuning knob) */
+    int msg_placement;      /* where the int8 path keeps its check-to-
+                               variable messages: LDPC_MSG_AUTO,
+                               LDPC_MSG_LDS (next to the posteriors in LDS)
+                               or LDPC_MSG_DEVICE (device memory, allocated
+                               by the library per call, stream-ordered; more
+                               codewords then share a CU). binary16 always
+                               uses device memory. */
     void *stream;
 } ldpc_args;
+
+#define LDPC_MSG_AUTO 0
+#define LDPC_MSG_LDS 1
+#define LDPC_MSG_DEVICE 2
 
 /* Fill `a` with the defaults above (beta 3/4, no offset, early exit on,
  * int8, 10 iterations, no optional outputs). */
 void ldpc_args_init(ldpc_args *a);
 
-/* ldpc_decode_ex -- decode with the options of ldpc_args. The binary16
- * path keeps its check-to-variable messages in device memory that the
- * library allocates per call (stream-ordered), 2 bytes per message.
+/* ldpc_decode_ex -- decode with the options of ldpc_args. Messages kept in
+ * device memory take n_cw*E*Z bytes (int8) or 2*n_cw*E*Z bytes (binary16),
+ * allocated per call with hipMallocAsync on `stream` and released the same
+ * way.
  * Errors: as ldpc_decode. */
 int ldpc_decode_ex(const ldpc_args *a);
 

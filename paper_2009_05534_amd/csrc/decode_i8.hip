@@ -81,11 +81,21 @@ __device__ __forceinline__ void row_update_w(uint16_t *__restrict__ Lw,
                                              uint16_t *__restrict__ Rw,
                                              const uint32_t *__restrict__ meta, int e0, int u,
                                              int Zh, bool first_iter, u16x2 wgt, u16x2 off16) {
+    // Rw is either LDS or device memory (the caller's pointer carries the
+    // address space); messages are read before the posteriors so that a
+    // device-memory read has the longest time to arrive.
     uint32_t md[W];
 #pragma unroll
     for (int k = 0; k < W; ++k) md[k] = meta[e0 + k];
     uint32_t lraw[W], rraw[W], su[W], sp[W];
     int la[W];
+    if (!first_iter) {
+#pragma unroll
+        for (int k = 0; k < W; ++k) rraw[k] = Rw[(e0 + k) * Zh + u];
+    } else {
+#pragma unroll
+        for (int k = 0; k < W; ++k) rraw[k] = 0;
+    }
 #pragma unroll
     for (int k = 0; k < W; ++k) {
         const Gather g = gather(md[k], u, Zh);
@@ -93,13 +103,6 @@ __device__ __forceinline__ void row_update_w(uint16_t *__restrict__ Lw,
         su[k] = g.sel_unpack;
         sp[k] = g.sel_pack;
         lraw[k] = Lw[g.addr];
-    }
-    if (!first_iter) {
-#pragma unroll
-        for (int k = 0; k < W; ++k) rraw[k] = Rw[(e0 + k) * Zh + u];
-    } else {
-#pragma unroll
-        for (int k = 0; k < W; ++k) rraw[k] = 0;
     }
     uint32_t xv[W], axv[W];
     u16x2 m1 = {0x7FFF, 0x7FFF}, m2 = {0x7FFF, 0x7FFF};
@@ -203,7 +206,12 @@ __device__ inline uint32_t syndrome_fails(const uint16_t *__restrict__ Lw,
     return bad & 0x80008000u;
 }
 
-template <int WMAX>
+// MSG_IN_LDS: the check-to-variable messages live next to the posteriors in
+// LDS (one BG1-shaped Z = 384 codeword fills a CU); otherwise they stream
+// through device memory (p.msg, [n_cw][E][Z/2] pair words) and only the
+// posteriors occupy LDS, so several codewords share a CU (§IV's placement
+// of L_v in shared memory and L_{c->v} in main memory).
+template <int WMAX, bool MSG_IN_LDS>
 __global__ __launch_bounds__(512) void decode_i8_kernel(DecodeLaunch p,
                                                          const int32_t *__restrict__ row_ptr,
                                                          const uint32_t *__restrict__ meta) {
@@ -211,13 +219,15 @@ __global__ __launch_bounds__(512) void decode_i8_kernel(DecodeLaunch p,
     extern __shared__ __align__(16) uint8_t smem[];
     const int Z = p.Z, Zh = Z >> 1;
     const int N = p.n_cols, E = p.E, T = (N - 2) * Z;
-    const int slot_bytes = lds_bytes_i8(N, E, Z);
+    const int slot_bytes = MSG_IN_LDS ? lds_bytes_i8(N, E, Z) : lds_bytes_i8_post(N, Z);
     const int slot = threadIdx.x / Zh;
     const int u = threadIdx.x - slot * Zh;
     const int cw = blockIdx.x * p.cpw + slot;
     const bool valid = cw < p.n_cw;
     uint16_t *Lw = reinterpret_cast<uint16_t *>(smem + slot * slot_bytes);
-    uint16_t *Rw = Lw + N * Zh;
+    uint16_t *Rw = MSG_IN_LDS ? Lw + N * Zh
+                              : reinterpret_cast<uint16_t *>(p.msg) +
+                                    (size_t)(valid ? cw : 0) * E * Zh;
     int *flags = reinterpret_cast<int *>(smem + p.cpw * slot_bytes);
 
     // Initialisation: punctured columns 0 and 1 carry no channel LLR.
@@ -298,15 +308,17 @@ __global__ __launch_bounds__(512) void decode_i8_kernel(DecodeLaunch p,
     }
 }
 
-template <int WMAX>
+template <int WMAX, bool MSG_IN_LDS>
 hipError_t launch_w(const DecodeLaunch &p, hipStream_t stream) {
     const int Zh = p.Z / 2;
-    const int lds = p.cpw * lds_bytes_i8(p.n_cols, p.E, p.Z) + p.cpw * (int)sizeof(int);
+    const int per_cw = MSG_IN_LDS ? lds_bytes_i8(p.n_cols, p.E, p.Z)
+                                  : lds_bytes_i8_post(p.n_cols, p.Z);
+    const int lds = p.cpw * per_cw + p.cpw * (int)sizeof(int);
     static bool attr_set = false;
     if (!attr_set) {
         // Opt in to more than the default 64 KiB of dynamic LDS.
         const hipError_t e = hipFuncSetAttribute(
-            reinterpret_cast<const void *>(&decode_i8_kernel<WMAX>),
+            reinterpret_cast<const void *>(&decode_i8_kernel<WMAX, MSG_IN_LDS>),
             hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes());
         if (e != hipSuccess) note_hip_error("hipFuncSetAttribute(decode_i8_kernel)", e);
         attr_set = true;
@@ -315,19 +327,24 @@ hipError_t launch_w(const DecodeLaunch &p, hipStream_t stream) {
     // hipGetLastError reports the last error of ANY earlier runtime call on
     // this thread; clear it so the check below sees this launch only.
     (void)hipGetLastError();
-    hipLaunchKernelGGL(decode_i8_kernel<WMAX>, dim3(blocks), dim3(p.cpw * Zh), lds, stream, p,
-                       p.row_ptr, p.meta);
+    hipLaunchKernelGGL((decode_i8_kernel<WMAX, MSG_IN_LDS>), dim3(blocks), dim3(p.cpw * Zh), lds,
+                       stream, p, p.row_ptr, p.meta);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) note_hip_error("launch decode_i8_kernel", e);
     return e;
 }
 
+template <bool MSG_IN_LDS>
+hipError_t launch_placed(const DecodeLaunch &p, hipStream_t stream) {
+    if (p.wmax <= 10) return launch_w<10, MSG_IN_LDS>(p, stream);
+    if (p.wmax <= 20) return launch_w<20, MSG_IN_LDS>(p, stream);
+    return launch_w<32, MSG_IN_LDS>(p, stream);
+}
+
 }  // namespace
 
 hipError_t launch_decode_i8(const DecodeLaunch &p, hipStream_t stream) {
-    if (p.wmax <= 10) return launch_w<10>(p, stream);
-    if (p.wmax <= 20) return launch_w<20>(p, stream);
-    return launch_w<32>(p, stream);
+    return p.msg ? launch_placed<false>(p, stream) : launch_placed<true>(p, stream);
 }
 
 }  // namespace ldpc

@@ -178,7 +178,8 @@ int ldpc_decode_ex(const ldpc_args *a) {
     if (!a || a->n_cw < 1 || a->max_iter < 1 || a->max_iter > LDPC_MAX_ITER || !a->llr_in ||
         !a->out_bits || !a->out_iters || (a->precision != LDPC_I8 && a->precision != LDPC_F16) ||
         a->beta_q < 0 || a->beta_q > 255 || a->offset_q < 0 || a->offset_q > 127 ||
-        (a->wq && a->wq_iters < 1) || (a->wh && a->wh_iters < 1) || a->cw_per_block < 0)
+        (a->wq && a->wq_iters < 1) || (a->wh && a->wh_iters < 1) || a->cw_per_block < 0 ||
+        a->msg_placement < LDPC_MSG_AUTO || a->msg_placement > LDPC_MSG_DEVICE)
         return LDPC_EINVAL;
     DecodeLaunch p{};
     int lds_cap = 0;
@@ -216,17 +217,30 @@ int ldpc_decode_ex(const ldpc_args *a) {
     p.max_iter = a->max_iter;
     p.early_exit = a->early_exit ? 1 : 0;
     const int Zh = p.Z / 2;
-    const int per_cw = a->precision == LDPC_I8 ? lds_bytes_i8(p.n_cols, p.E, p.Z) + 4
-                                               : lds_bytes_f16(p.n_cols, p.Z) + 4;
+    const bool i8 = a->precision == LDPC_I8;
+    // int8 message placement: LDS when at least four codewords' full state
+    // fits a CU, else device memory so that several codewords share a CU.
+    bool msg_in_lds = false;
+    if (i8) {
+        if (a->msg_placement == LDPC_MSG_LDS)
+            msg_in_lds = true;
+        else if (a->msg_placement == LDPC_MSG_DEVICE)
+            msg_in_lds = false;
+        else
+            msg_in_lds = 4 * (lds_bytes_i8(p.n_cols, p.E, p.Z) + 4) <= lds_cap;
+    }
+    const int per_cw = (i8 ? (msg_in_lds ? lds_bytes_i8(p.n_cols, p.E, p.Z)
+                                         : lds_bytes_i8_post(p.n_cols, p.Z))
+                           : lds_bytes_f16(p.n_cols, p.Z)) + 4;
     const int cap_lds = lds_cap / per_cw;
     const int cap_threads = 512 / Zh;
     int cpw = a->cw_per_block;
     if (cpw == 0) {
-        // Default: fill one workgroup up to 256 lanes (int8) or one codeword
-        // per workgroup for large lifts (binary16 shares the CU between
-        // workgroups).
-        cpw = 256 / Zh > 0 ? 256 / Zh : 1;
-        if (a->precision == LDPC_F16) cpw = 128 / Zh > 0 ? 128 / Zh : 1;
+        // Default: up to 256 lanes per workgroup when the whole state is in
+        // LDS; otherwise about 128 lanes (one codeword per workgroup at
+        // large lifts) so that several workgroups share a CU.
+        cpw = (msg_in_lds ? 256 : 128) / Zh;
+        if (cpw < 1) cpw = 1;
     }
     if (cpw > cap_lds) cpw = cap_lds;
     if (cpw > cap_threads) cpw = cap_threads;
@@ -234,27 +248,27 @@ int ldpc_decode_ex(const ldpc_args *a) {
     if (cpw < 1) return LDPC_EINVAL;  // a single codeword does not fit
     p.cpw = cpw;
     hipStream_t stream = static_cast<hipStream_t>(a->stream);
-    hipError_t e;
-    if (a->precision == LDPC_I8) {
+    if (i8) {
         p.wq = a->wq;
         p.w_iters = a->wq_iters;
         p.beta = a->beta_q;
         p.offset = a->offset_q;
-        e = launch_decode_i8(p, stream);
-        if (e != hipSuccess) return e == hipErrorOutOfMemory ? LDPC_ENOMEM : LDPC_EHIP;
-        return LDPC_OK;
+    } else {
+        p.wh = a->wh;
+        p.w_iters = a->wh_iters;
+        p.beta = a->beta_h;
+        p.offset = a->offset_h;
     }
-    p.wh = a->wh;
-    p.w_iters = a->wh_iters;
-    p.beta = a->beta_h;
-    p.offset = a->offset_h;
-    const size_t msg_bytes = (size_t)a->n_cw * p.E * Zh * sizeof(uint32_t);
     void *msg = nullptr;
-    e = hipMallocAsync(&msg, msg_bytes, stream);
-    if (e != hipSuccess) return hip_fail(e, "hipMallocAsync(messages)");
+    hipError_t e;
+    if (!msg_in_lds) {
+        const size_t msg_bytes = (size_t)a->n_cw * p.E * Zh * (i8 ? 2 : 4);
+        e = hipMallocAsync(&msg, msg_bytes, stream);
+        if (e != hipSuccess) return hip_fail(e, "hipMallocAsync(messages)");
+    }
     p.msg = static_cast<uint32_t *>(msg);
-    e = launch_decode_f16(p, stream);
-    const hipError_t ef = hipFreeAsync(msg, stream);
+    e = i8 ? launch_decode_i8(p, stream) : launch_decode_f16(p, stream);
+    const hipError_t ef = msg ? hipFreeAsync(msg, stream) : hipSuccess;
     if (e != hipSuccess) return e == hipErrorOutOfMemory ? LDPC_ENOMEM : LDPC_EHIP;
     if (ef != hipSuccess) return hip_fail(ef, "hipFreeAsync(messages)");
     return LDPC_OK;

@@ -35,8 +35,9 @@ struct DecodeLaunch {
     const uint32_t *meta;     // device [E]
     const uint8_t *wq;        // int8 path per-(iteration,row) weights or null
     const uint16_t *wh;       // binary16 path weights or null
-    uint32_t *msg;            // binary16 path: check-to-variable messages
-                              // [n_cw][E][Zh] pair words
+    uint32_t *msg;            // check-to-variable messages in device memory,
+                              // [n_cw][E][Zh] pair words (binary16: always;
+                              // int8: when not kept in LDS, else null)
     int w_iters;
     int n_cw, rows, n_cols, kb, Z, E;
     int max_iter, early_exit;
@@ -47,6 +48,7 @@ struct DecodeLaunch {
 
 // Bytes of LDS one codeword needs in each kernel.
 __host__ __device__ inline int lds_bytes_i8(int n_cols, int E, int Z) { return (n_cols + E) * Z; }
+__host__ __device__ inline int lds_bytes_i8_post(int n_cols, int Z) { return n_cols * Z; }
 __host__ __device__ inline int lds_bytes_f16(int n_cols, int Z) { return n_cols * Z * 2; }
 
 // Host launchers; return hipSuccess or the launch error.

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(HERE, "libldpc.so")
 
 LDPC_I8 = 0
 LDPC_F16 = 1
+MSG_PLACEMENT = {"auto": 0, "lds": 1, "device": 2}
 _ERRORS = {-1: "invalid argument", -2: "out of memory", -3: "HIP runtime error",
            -4: "no graph registered for (bg, Z)"}
 
@@ -37,7 +38,8 @@ class Args(ctypes.Structure):
         ("wh_iters", ctypes.c_int),
         ("out_bits", ctypes.c_void_p), ("out_iters", ctypes.c_void_p),
         ("out_ok", ctypes.c_void_p), ("out_llr", ctypes.c_void_p),
-        ("cw_per_block", ctypes.c_int), ("stream", ctypes.c_void_p),
+        ("cw_per_block", ctypes.c_int), ("msg_placement", ctypes.c_int),
+        ("stream", ctypes.c_void_p),
     ]
 
 
@@ -121,7 +123,7 @@ def _stream_ptr(stream):
 def decode_into(llr, bg: int, Z: int, rows: int, out_bits, out_iters, *, max_iter: int = 10,
                 precision: str = "i8", early_exit: bool = True, beta: float | None = None,
                 offset: float = 0, weights=None, out_ok=None, out_llr=None,
-                cw_per_block: int = 0, stream=None) -> None:
+                cw_per_block: int = 0, msg_placement: str = "auto", stream=None) -> None:
     """Decode int8 LLRs [n_cw, T] (device tensor) into preallocated outputs.
 
     ``weights``: per-(iteration, row) normalisation, a device tensor uint8
@@ -170,13 +172,15 @@ def decode_into(llr, bg: int, Z: int, rows: int, out_bits, out_iters, *, max_ite
     a.out_ok = out_ok.data_ptr() if out_ok is not None else None
     a.out_llr = out_llr.data_ptr() if out_llr is not None else None
     a.cw_per_block = cw_per_block
+    a.msg_placement = MSG_PLACEMENT[msg_placement]
     a.stream = _stream_ptr(stream)
     _check(lib().ldpc_decode_ex(ctypes.byref(a)), "ldpc_decode_ex")
 
 
 def decode(llr, bg: int, Z: int, rows: int, *, max_iter: int = 10, precision: str = "i8",
            early_exit: bool = True, beta: float | None = None, offset: float = 0, weights=None,
-           want_ok: bool = True, want_llr: bool = False, cw_per_block: int = 0, stream=None):
+           want_ok: bool = True, want_llr: bool = False, cw_per_block: int = 0,
+           msg_placement: str = "auto", stream=None):
     """Allocate outputs with torch on llr's device and decode.
 
     Returns (bits uint8 [n, K/8], iters int32 [n], ok bool [n] or None,
@@ -196,5 +200,6 @@ def decode(llr, bg: int, Z: int, rows: int, *, max_iter: int = 10, precision: st
                           device=dev)
     decode_into(llr, bg, Z, rows, bits, iters, max_iter=max_iter, precision=precision,
                 early_exit=early_exit, beta=beta, offset=offset, weights=weights, out_ok=ok,
-                out_llr=out, cw_per_block=cw_per_block, stream=stream)
+                out_llr=out, cw_per_block=cw_per_block, msg_placement=msg_placement,
+                stream=stream)
     return bits, iters, (ok.bool() if ok is not None else None), out

@@ -206,3 +206,16 @@ def test_full_size_sampled():
     idx16 = idx[idx < 512][:16]
     ref16 = oracle_f16(g, b.q[idx16])
     assert_f16_close(tuple(x[idx16] for x in got16), ref16)
+
+
+@pytest.mark.parametrize("bg,Z,rows", [(1, 384, 46), (2, 64, 42), (1, 16, 20), (1, 192, 8)])
+def test_i8_message_placements_agree(bg, Z, rows):
+    # Messages kept in LDS or streamed through device memory: same results,
+    # both equal to the oracle.
+    g = _graph(bg, Z, rows)
+    b = make_batch(g, 12, 1.5, data_seed=11 + Z)
+    ref = oracle_i8(g, b.q)
+    for placement in ("lds", "device"):
+        for cpw in (0, 1, 3):
+            got = gpu_decode(bg, Z, rows, b.q, msg_placement=placement, cw_per_block=cpw)
+            assert_i8_equal(got, ref)
