@@ -24,23 +24,37 @@ __device__ inline u16x2 as_u(uint32_t v) { return __builtin_bit_cast(u16x2, v); 
 __device__ inline uint32_t bits_of(h16x2 v) { return __builtin_bit_cast(uint32_t, v); }
 __device__ inline uint32_t bits_of(u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
 
-// Rotate a pair word by 16 bits when the halves arrive swapped.
-__device__ inline uint32_t swap_halves(uint32_t v, bool swap) {
-    return swap ? __builtin_amdgcn_alignbit(v, v, 16) : v;
+// Message of block e for a lane: 32 bits at byte offset 4*(e*Zh + ro) from
+// the workgroup's uniform base; unsigned 32-bit offsets let the access use
+// the scalar-base + vector-offset form.
+__device__ inline uint32_t msg_ld(const uint32_t *Rb, int e, int Zh, int ro) {
+    const uint32_t off = 4u * (uint32_t)(e * Zh + ro);
+    return *reinterpret_cast<const uint32_t *>(reinterpret_cast<const uint8_t *>(Rb) + off);
+}
+__device__ inline void msg_st(uint32_t *Rb, int e, int Zh, int ro, uint32_t v) {
+    const uint32_t off = 4u * (uint32_t)(e * Zh + ro);
+    *reinterpret_cast<uint32_t *>(reinterpret_cast<uint8_t *>(Rb) + off) = v;
+}
+
+// Rotate a pair word right by `rot` bits: 16 when the halves arrive
+// swapped, else 0 (a per-lane amount, so it lives in a VGPR, not a mask).
+__device__ inline uint32_t swap_halves(uint32_t v, uint32_t rot) {
+    return __builtin_amdgcn_alignbit(v, v, rot);
 }
 
 struct Gather {
     int addr;
-    bool swap;
+    uint32_t rot;
 };
 
+// Pair word of lane u's two rows for block `md` (format in ldpc_internal.h)
+// and the rotation that puts row u in the low half.
 __device__ inline Gather gather(uint32_t md, int u, int Zh) {
-    const int colw = (int)(md & 0xFFFFu);
-    const int slo = (int)((md >> 16) & 0xFFu);
+    const int word = (int)(md & 0xFFFFu);
+    const int thr = (int)((md >> 16) & 0xFFu);
     const bool shi = (md >> 24) & 1u;
-    const int v = u + slo;
-    const bool hi = v >= Zh;
-    return Gather{colw + (hi ? v - Zh : v), hi != shi};
+    const bool wrap = u >= thr;
+    return Gather{word + u + (wrap ? -Zh : 0), (wrap != shi) ? 16u : 0u};
 }
 
 // a = w * max(m - off, 0), each step rounded to binary16.
@@ -53,48 +67,72 @@ __device__ inline uint32_t normalise(uint32_t m, uint32_t off, h16x2 w) {
     return bits_of(w * v);
 }
 
-// One block row of exactly W blocks for lane u (rows u and u + Zh). As in
-// the int8 kernel the row is branch-free: metadata in one batch of scalar
-// loads, then every read (posteriors from LDS, messages from device memory)
-// before any arithmetic.
-template <int W>
-__device__ __forceinline__ void row_update_w(uint32_t *__restrict__ Lw, uint32_t *__restrict__ Rg,
-                                             const uint32_t *__restrict__ meta, int e0, int u,
-                                             int Zh, bool first_iter, h16x2 wgt, uint32_t off) {
-    uint32_t md[W];
-#pragma unroll
-    for (int k = 0; k < W; ++k) md[k] = meta[e0 + k];
-    uint32_t lraw[W], rraw[W];
-    int la[W];
-    bool sw[W];
+// Variable-to-check messages of blocks K0..K1-1: reads first (messages
+// from device memory, then posteriors from LDS), then x = L - R rounded to
+// binary16, folded into m1 / m2 / S.
+template <int K0, int K1, bool KEEP_GATHER>
+__device__ __forceinline__ void row_phase1(const uint32_t *__restrict__ Lw,
+                                           const uint32_t *__restrict__ Rb, int ro,
+                                           const uint32_t *md, int e0, int u, int Zh,
+                                           bool first_iter, uint32_t *xv, int *la, uint32_t *sw,
+                                           u16x2 &m1, u16x2 &m2, uint32_t &S) {
+    constexpr int n = K1 - K0;
+    uint32_t lraw[n], rraw[n], swl[n];
     if (!first_iter) {
 #pragma unroll
-        for (int k = 0; k < W; ++k) rraw[k] = Rg[(size_t)(e0 + k) * Zh + u];
+        for (int i = 0; i < n; ++i) rraw[i] = msg_ld(Rb, e0 + K0 + i, Zh, ro);
     } else {
 #pragma unroll
-        for (int k = 0; k < W; ++k) rraw[k] = 0;
+        for (int i = 0; i < n; ++i) rraw[i] = 0;
     }
 #pragma unroll
-    for (int k = 0; k < W; ++k) {
-        const Gather g = gather(md[k], u, Zh);
-        la[k] = g.addr;
-        sw[k] = g.swap;
-        lraw[k] = Lw[g.addr];
+    for (int i = 0; i < n; ++i) {
+        const Gather g = gather(md[K0 + i], u, Zh);
+        swl[i] = g.rot;
+        if (KEEP_GATHER) {
+            la[K0 + i] = g.addr;
+            sw[K0 + i] = g.rot;
+        }
+        lraw[i] = Lw[g.addr];
     }
-    uint32_t xv[W], axv[W];
-    u16x2 m1 = {0x7C00, 0x7C00}, m2 = {0x7C00, 0x7C00};
-    uint32_t S = 0;
 #pragma unroll
-    for (int k = 0; k < W; ++k) {
-        const h16x2 L = as_h(swap_halves(lraw[k], sw[k]));
-        const h16x2 x = L - as_h(rraw[k]);
+    for (int i = 0; i < n; ++i) {
+        const h16x2 L = as_h(swap_halves(lraw[i], swl[i]));
+        const h16x2 x = L - as_h(rraw[i]);
         const uint32_t xb = bits_of(x);
         const u16x2 ax = as_u(xb & 0x7FFF7FFFu);
         m2 = __builtin_elementwise_min(m2, __builtin_elementwise_max(m1, ax));
         m1 = __builtin_elementwise_min(m1, ax);
         S ^= xb;
-        xv[k] = xb;
-        axv[k] = bits_of(ax);
+        xv[K0 + i] = xb;
+    }
+}
+
+// One block row of exactly W blocks for lane u (rows u and u + Zh). As in
+// the int8 kernel the row is branch-free: metadata in one batch of scalar
+// loads, then the reads before any arithmetic; rows wider than 10 blocks
+// read in two halves and recompute their gathers for the write-back.
+// Message of block e for this lane: Rb[e * Zh + ro] (uniform base, 32-bit
+// lane offset).
+template <int W>
+__device__ __forceinline__ void row_update_w(uint32_t *__restrict__ Lw, uint32_t *__restrict__ Rb,
+                                             int ro, const uint32_t *__restrict__ meta, int e0,
+                                             int u, int Zh, bool first_iter, h16x2 wgt,
+                                             uint32_t off) {
+    constexpr bool kWide = W > 10;
+    uint32_t md[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) md[k] = meta[e0 + k];
+    uint32_t xv[W], sw[W];
+    int la[W];
+    u16x2 m1 = {0x7C00, 0x7C00}, m2 = {0x7C00, 0x7C00};
+    uint32_t S = 0;
+    if constexpr (kWide) {
+        constexpr int H = (W + 1) / 2;
+        row_phase1<0, H, false>(Lw, Rb, ro, md, e0, u, Zh, first_iter, xv, la, sw, m1, m2, S);
+        row_phase1<H, W, false>(Lw, Rb, ro, md, e0, u, Zh, first_iter, xv, la, sw, m1, m2, S);
+    } else {
+        row_phase1<0, W, true>(Lw, Rb, ro, md, e0, u, Zh, first_iter, xv, la, sw, m1, m2, S);
     }
     const uint32_t a1 = normalise(bits_of(m1), off, wgt);
     const uint32_t a2 = normalise(bits_of(m2), off, wgt);
@@ -102,13 +140,18 @@ __device__ __forceinline__ void row_update_w(uint32_t *__restrict__ Lw, uint32_t
 #pragma unroll
     for (int k = 0; k < W; ++k) {
         // mask = 0xFFFF on the argmin edge (|x| == m1), else 0.
-        const u16x2 t = __builtin_elementwise_sub_sat(m1p, as_u(axv[k]));
+        const u16x2 t = __builtin_elementwise_sub_sat(m1p, as_u(xv[k] & 0x7FFF7FFFu));
         const uint32_t mask = bits_of((u16x2){0, 0} - t);
         const uint32_t mag = (a2 & mask) | (a1 & ~mask);
         const uint32_t Rn = mag | ((S ^ xv[k]) & 0x80008000u);
         const h16x2 Ln = as_h(xv[k]) + as_h(Rn);
-        Lw[la[k]] = swap_halves(bits_of(Ln), sw[k]);
-        Rg[(size_t)(e0 + k) * Zh + u] = Rn;
+        if (kWide) {
+            const Gather g = gather(md[k], u, Zh);
+            Lw[g.addr] = swap_halves(bits_of(Ln), g.rot);
+        } else {
+            Lw[la[k]] = swap_halves(bits_of(Ln), sw[k]);
+        }
+        msg_st(Rb, e0 + k, Zh, ro, Rn);
     }
 }
 
@@ -118,14 +161,13 @@ template <int W>
 __device__ __forceinline__ uint32_t row_parity_w(const uint32_t *__restrict__ Lw,
                                                  const uint32_t *__restrict__ meta, int e0, int u,
                                                  int Zh) {
-    uint32_t md[W], raw[W];
-    bool sw[W];
+    uint32_t md[W], raw[W], sw[W];
 #pragma unroll
     for (int k = 0; k < W; ++k) md[k] = meta[e0 + k];
 #pragma unroll
     for (int k = 0; k < W; ++k) {
         const Gather g = gather(md[k], u, Zh);
-        sw[k] = g.swap;
+        sw[k] = g.rot;
         raw[k] = Lw[g.addr];
     }
     uint32_t acc = 0;
@@ -140,15 +182,15 @@ __device__ __forceinline__ uint32_t row_parity_w(const uint32_t *__restrict__ Lw
 }
 
 template <int W, int WMAX>
-__device__ __forceinline__ void row_update(int w, uint32_t *Lw, uint32_t *Rg, const uint32_t *meta,
-                                           int e0, int u, int Zh, bool first_iter, h16x2 wgt,
-                                           uint32_t off) {
+__device__ __forceinline__ void row_update(int w, uint32_t *Lw, uint32_t *Rb, int ro,
+                                           const uint32_t *meta, int e0, int u, int Zh,
+                                           bool first_iter, h16x2 wgt, uint32_t off) {
     if constexpr (W <= WMAX) {
         if (w == W) {
-            row_update_w<W>(Lw, Rg, meta, e0, u, Zh, first_iter, wgt, off);
+            row_update_w<W>(Lw, Rb, ro, meta, e0, u, Zh, first_iter, wgt, off);
             return;
         }
-        row_update<W + 1, WMAX>(w, Lw, Rg, meta, e0, u, Zh, first_iter, wgt, off);
+        row_update<W + 1, WMAX>(w, Lw, Rb, ro, meta, e0, u, Zh, first_iter, wgt, off);
     }
 }
 
@@ -190,12 +232,15 @@ __global__ __launch_bounds__(512) void decode_f16_kernel(DecodeLaunch p,
     const bool valid = cw < p.n_cw;
     uint32_t *Lw = reinterpret_cast<uint32_t *>(smem + slot * slot_bytes);
     int *flags = reinterpret_cast<int *>(smem + p.cpw * slot_bytes);
-    uint32_t *Rg = p.msg + (size_t)(valid ? cw : 0) * E * Zh;
+    // Messages: uniform base for the workgroup plus a 32-bit lane offset.
+    uint32_t *Rb = p.msg + (size_t)blockIdx.x * p.cpw * E * Zh;
+    const int ro = slot * E * Zh + u;
 
     if (valid) {
         Lw[u] = 0;
         Lw[Zh + u] = 0;
         const int8_t *q = p.llr + (size_t)cw * T;
+#pragma unroll 1
         for (int c = 2; c < N; ++c) {
             int lo = q[(c - 2) * Z + u], hi = q[(c - 2) * Z + u + Zh];
             lo = lo < -127 ? -127 : lo;
@@ -217,7 +262,7 @@ __global__ __launch_bounds__(512) void decode_f16_kernel(DecodeLaunch p,
             const int e0 = row_ptr[r], w = row_ptr[r + 1] - e0;
             if (wrow) wt = wrow[r];
             const h16x2 wgt = as_h(wt * 0x00010001u);
-            if (!done) row_update<2, WMAX>(w, Lw, Rg, meta, e0, u, Zh, t == 1, wgt, off);
+            if (!done) row_update<2, WMAX>(w, Lw, Rb, ro, meta, e0, u, Zh, t == 1, wgt, off);
             __syncthreads();
         }
         if (p.early_exit || t == p.max_iter) {
@@ -242,18 +287,24 @@ __global__ __launch_bounds__(512) void decode_f16_kernel(DecodeLaunch p,
     }
     if (!valid) return;
 
-    const int K = p.kb * Z;
+    // Outputs (see the int8 kernel): byte j of a column packs bits 8j..8j+7.
     const uint16_t *Lh = reinterpret_cast<const uint16_t *>(Lw);
-    for (int j = u; j < K / 8; j += Zh) {
-        uint32_t byte = 0;
+    const int bytes_per_col = Z / 8;
+    uint8_t *ob = p.out_bits + (size_t)cw * (p.kb * bytes_per_col);
+#pragma unroll 1
+    for (int c = 0; c < p.kb; ++c) {
+#pragma unroll 1
+        for (int j = u; j < bytes_per_col; j += Zh) {
+            uint32_t byte = 0;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int v = 8 * j + i, c = v / Z, z = v - c * Z;
-            const int zz = z < Zh ? z : z - Zh;
-            const uint16_t h = Lh[2 * (c * Zh + zz) + (z < Zh ? 0 : 1)];
-            byte |= (uint32_t)(h > 0x8000u) << i;
+            for (int i = 0; i < 8; ++i) {
+                const int z = 8 * j + i;
+                const int hi = z >= Zh;
+                const uint16_t h = Lh[2 * (c * Zh + z - hi * Zh) + hi];
+                byte |= (uint32_t)(h > 0x8000u) << i;
+            }
+            ob[c * bytes_per_col + j] = (uint8_t)byte;
         }
-        p.out_bits[(size_t)cw * (K / 8) + j] = (uint8_t)byte;
     }
     if (u == 0) {
         p.out_iters[cw] = iters;
@@ -261,10 +312,11 @@ __global__ __launch_bounds__(512) void decode_f16_kernel(DecodeLaunch p,
     }
     if (p.out_llr) {
         uint16_t *o = static_cast<uint16_t *>(p.out_llr) + (size_t)cw * N * Z;
-        for (int v = u; v < N * Z; v += Zh) {
-            const int c = v / Z, z = v - c * Z;
-            const int zz = z < Zh ? z : z - Zh;
-            o[v] = Lh[2 * (c * Zh + zz) + (z < Zh ? 0 : 1)];
+#pragma unroll 1
+        for (int c = 0; c < N; ++c) {
+            const uint32_t w = Lw[c * Zh + u];
+            o[c * Z + u] = (uint16_t)(w & 0xFFFFu);
+            o[c * Z + u + Zh] = (uint16_t)(w >> 16);
         }
     }
 }

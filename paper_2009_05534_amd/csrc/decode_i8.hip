@@ -48,69 +48,80 @@ __device__ inline u16x2 normalise(u16x2 m, u16x2 off16, u16x2 w) {
     return v << (u16x2){8, 8};
 }
 
-// Where lane u's two rows meet block `md`: pair-word address and the
-// unpack/pack selectors.
+// Where lane u's two rows meet block `md`: byte offset of the pair word
+// from the lane's base (lb = codeword posteriors + 2u) and the unpack/pack
+// selectors. The offset is one compare, one select and one three-way add.
 struct Gather {
-    int addr;
+    int off;
     uint32_t sel_unpack, sel_pack;
 };
 
-__device__ inline Gather gather(uint32_t md, int u, int Zh) {
-    const int colw = (int)(md & 0xFFFFu);
-    const int slo = (int)((md >> 16) & 0xFFu);
+__device__ inline Gather gather(uint32_t md, int u, int Zh2) {
+    const int word = (int)(md & 0xFFFFu);
+    const int thr = (int)((md >> 16) & 0xFFu);
     const bool shi = (md >> 24) & 1u;
-    const int v = u + slo;
-    const bool hi = v >= Zh;
+    const bool wrap = u >= thr;
     Gather g;
-    g.addr = colw + (hi ? v - Zh : v);
-    const bool swap = hi != shi;
+    g.off = 2 * word + (wrap ? -Zh2 : 0);
+    const bool swap = wrap != shi;
     g.sel_unpack = swap ? kUnpackSwap : kUnpack;
     g.sel_pack = swap ? kPackSwap : kPack;
     return g;
 }
 
-// One block row of exactly W blocks for lane u (rows u and u + Zh):
-// variable-to-check messages, min / second min / sign product,
-// normalisation, check-to-variable messages and posterior write-back.
-// Specialising on W keeps the row free of branches, so the row's metadata
-// arrives in one batch of scalar loads and every LDS read is issued before
-// any arithmetic (scalar and LDS loads share one completion counter; a
-// scalar result consumed between LDS reads would serialise them).
-template <int W>
-__device__ __forceinline__ void row_update_w(uint16_t *__restrict__ Lw,
-                                             uint16_t *__restrict__ Rw,
-                                             const uint32_t *__restrict__ meta, int e0, int u,
-                                             int Zh, bool first_iter, u16x2 wgt, u16x2 off16) {
-    // Rw is either LDS or device memory (the caller's pointer carries the
-    // address space); messages are read before the posteriors so that a
-    // device-memory read has the longest time to arrive.
-    uint32_t md[W];
-#pragma unroll
-    for (int k = 0; k < W; ++k) md[k] = meta[e0 + k];
-    uint32_t lraw[W], rraw[W], su[W], sp[W];
-    int la[W];
+// Message of block e for a lane: 16 bits at byte offset 2*(e*Zh + ro) from
+// the workgroup's uniform base (LDS or device memory). Unsigned 32-bit
+// offsets let a device access use the scalar-base + vector-offset form.
+__device__ inline uint32_t msg_ld(const uint16_t *Rb, int e, int Zh, int ro) {
+    const uint32_t off = 2u * (uint32_t)(e * Zh + ro);
+    return *reinterpret_cast<const uint16_t *>(reinterpret_cast<const uint8_t *>(Rb) + off);
+}
+__device__ inline void msg_st(uint16_t *Rb, int e, int Zh, int ro, uint32_t v) {
+    const uint32_t off = 2u * (uint32_t)(e * Zh + ro);
+    *reinterpret_cast<uint16_t *>(reinterpret_cast<uint8_t *>(Rb) + off) = (uint16_t)v;
+}
+
+// 16-bit LDS load/store at a byte offset from lb. The load's upper half is
+// left unspecified: every consumer goes through v_perm, which reads only
+// bytes 0 and 1.
+__device__ inline uint32_t lds_ld16(const uint8_t *lb, int off) {
+    return *reinterpret_cast<const uint16_t *>(lb + off);
+}
+__device__ inline void lds_st16(uint8_t *lb, int off, uint32_t v) {
+    *reinterpret_cast<uint16_t *>(lb + off) = (uint16_t)v;
+}
+
+// Variable-to-check messages of blocks K0..K1-1 of the row: reads first
+// (messages, then posteriors), then x = sat(L - R), folded into m1 / m2 / S.
+template <int K0, int K1, bool KEEP_GATHER>
+__device__ __forceinline__ void row_phase1(const uint8_t *__restrict__ lb,
+                                           const uint16_t *__restrict__ Rb, int ro,
+                                           const uint32_t *md, int e0, int u, int Zh,
+                                           bool first_iter, uint32_t *xv, uint32_t *axv, int *la,
+                                           uint32_t *sp, u16x2 &m1, u16x2 &m2, uint32_t &S) {
+    constexpr int n = K1 - K0;
+    uint32_t lraw[n], rraw[n], su[n];
     if (!first_iter) {
 #pragma unroll
-        for (int k = 0; k < W; ++k) rraw[k] = Rw[(e0 + k) * Zh + u];
+        for (int i = 0; i < n; ++i) rraw[i] = msg_ld(Rb, e0 + K0 + i, Zh, ro);
     } else {
 #pragma unroll
-        for (int k = 0; k < W; ++k) rraw[k] = 0;
+        for (int i = 0; i < n; ++i) rraw[i] = 0;
     }
 #pragma unroll
-    for (int k = 0; k < W; ++k) {
-        const Gather g = gather(md[k], u, Zh);
-        la[k] = g.addr;
-        su[k] = g.sel_unpack;
-        sp[k] = g.sel_pack;
-        lraw[k] = Lw[g.addr];
+    for (int i = 0; i < n; ++i) {
+        const Gather g = gather(md[K0 + i], u, 2 * Zh);
+        su[i] = g.sel_unpack;
+        if (KEEP_GATHER) {
+            la[K0 + i] = g.off;
+            sp[K0 + i] = g.sel_pack;
+        }
+        lraw[i] = lds_ld16(lb, g.off);
     }
-    uint32_t xv[W], axv[W];
-    u16x2 m1 = {0x7FFF, 0x7FFF}, m2 = {0x7FFF, 0x7FFF};
-    uint32_t S = 0;
 #pragma unroll
-    for (int k = 0; k < W; ++k) {
-        const s16x2 L = as_s(perm(lraw[k], su[k]));
-        const s16x2 R = as_s(perm(rraw[k], kUnpack));
+    for (int i = 0; i < n; ++i) {
+        const s16x2 L = as_s(perm(lraw[i], su[i]));
+        const s16x2 R = as_s(perm(rraw[i], kUnpack));
         s16x2 x = __builtin_elementwise_sub_sat(L, R);
         x = __builtin_elementwise_max(x, (s16x2){-127 * 256, -127 * 256});
         const s16x2 ax = __builtin_elementwise_max(x, (s16x2){0, 0} - x);
@@ -118,8 +129,45 @@ __device__ __forceinline__ void row_update_w(uint16_t *__restrict__ Lw,
         m2 = __builtin_elementwise_min(m2, __builtin_elementwise_max(m1, axu));
         m1 = __builtin_elementwise_min(m1, axu);
         S ^= bits_of(x);
-        xv[k] = bits_of(x);
-        axv[k] = bits_of(ax);
+        xv[K0 + i] = bits_of(x);
+        if (KEEP_GATHER) axv[K0 + i] = bits_of(ax);
+    }
+}
+
+// One block row of exactly W blocks for lane u (rows u and u + Zh):
+// variable-to-check messages, min / second min / sign product,
+// normalisation, check-to-variable messages and posterior write-back.
+// Specialising on W keeps the row free of branches, so the row's metadata
+// arrives in one batch of scalar loads and the LDS reads are issued before
+// any arithmetic (scalar and LDS loads share one completion counter; a
+// scalar result consumed between LDS reads would serialise them).
+// Message of block e for this lane: Rb[e * Zh + ro], with Rb uniform across
+// the workgroup (LDS or device memory, carried by the pointer's address
+// space) and ro a 32-bit lane offset, so a device access is a scalar base
+// plus one vector offset. Rows wider than 10 blocks read in two halves and
+// recompute |x| and their gathers for the write-back, which keeps the
+// kernel under the register budget of six codewords per CU.
+template <int W>
+__device__ __forceinline__ void row_update_w(uint8_t *__restrict__ lb,
+                                             uint16_t *__restrict__ Rb, int ro,
+                                             const uint32_t *__restrict__ meta, int e0, int u,
+                                             int Zh, bool first_iter, u16x2 wgt, u16x2 off16) {
+    constexpr bool kWide = W > 10;
+    uint32_t md[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) md[k] = meta[e0 + k];
+    uint32_t xv[W], axv[W], sp[W];
+    int la[W];
+    u16x2 m1 = {0x7FFF, 0x7FFF}, m2 = {0x7FFF, 0x7FFF};
+    uint32_t S = 0;
+    if constexpr (kWide) {
+        constexpr int H = (W + 1) / 2;
+        row_phase1<0, H, false>(lb, Rb, ro, md, e0, u, Zh, first_iter, xv, axv, la, sp, m1, m2,
+                                S);
+        row_phase1<H, W, false>(lb, Rb, ro, md, e0, u, Zh, first_iter, xv, axv, la, sp, m1, m2,
+                                S);
+    } else {
+        row_phase1<0, W, true>(lb, Rb, ro, md, e0, u, Zh, first_iter, xv, axv, la, sp, m1, m2, S);
     }
     const u16x2 a1 = normalise(m1, off16, wgt);
     const u16x2 a2 = normalise(m2, off16, wgt);
@@ -132,24 +180,31 @@ __device__ __forceinline__ void row_update_w(uint16_t *__restrict__ Lw,
     const u16x2 m1p = m1 + (u16x2){1, 1};
 #pragma unroll
     for (int k = 0; k < W; ++k) {
+        const s16x2 x = as_s(xv[k]);
+        const s16x2 ax = kWide ? __builtin_elementwise_max(x, (s16x2){0, 0} - x) : as_s(axv[k]);
         // t = 1 on the argmin edge (|x| == m1), else 0.
-        const u16x2 t = __builtin_elementwise_sub_sat(m1p, as_u(axv[k]));
+        const u16x2 t = __builtin_elementwise_sub_sat(m1p, as_u(bits_of(ax)));
         const s16x2 b = as_s(bits_of(t * d21 + as_u(bits_of(b1))));
-        // L' = sgn(x) * min(|x| + b, 127); R' = sgn(x) * b.
-        s16x2 v = __builtin_elementwise_add_sat(as_s(axv[k]), b);
-        v = as_s(bits_of(v) & 0xFF00FF00u);
-        const s16x2 sx = as_s(xv[k]) >> (s16x2){15, 15};
-        const s16x2 Ln = (v ^ sx) - sx;
+        // R' = sgn(x) * b; L' = sat(x + R'). The low byte of x is 0 or 0xFF
+        // and that of R' is 0, so no carry reaches the high byte.
+        const s16x2 sx = x >> (s16x2){15, 15};
         const s16x2 Rn = (b ^ sx) - sx;
-        Lw[la[k]] = (uint16_t)perm(bits_of(Ln), sp[k]);
-        Rw[(e0 + k) * Zh + u] = (uint16_t)perm(bits_of(Rn), kPack);
+        const s16x2 Ln = __builtin_elementwise_max(__builtin_elementwise_add_sat(x, Rn),
+                                                   (s16x2){-127 * 256, -127 * 256});
+        if (kWide) {
+            const Gather g = gather(md[k], u, 2 * Zh);
+            lds_st16(lb, g.off, perm(bits_of(Ln), g.sel_pack));
+        } else {
+            lds_st16(lb, la[k], perm(bits_of(Ln), sp[k]));
+        }
+        msg_st(Rb, e0 + k, Zh, ro, perm(bits_of(Rn), kPack));
     }
 }
 
 // Parity of lane u's two rows over a row of exactly W blocks, as sign bits
 // 15 and 31 (hard decision [L_v < 0]).
 template <int W>
-__device__ __forceinline__ uint32_t row_parity_w(const uint16_t *__restrict__ Lw,
+__device__ __forceinline__ uint32_t row_parity_w(const uint8_t *__restrict__ lb,
                                                  const uint32_t *__restrict__ meta, int e0, int u,
                                                  int Zh) {
     uint32_t md[W], raw[W], su[W];
@@ -157,9 +212,9 @@ __device__ __forceinline__ uint32_t row_parity_w(const uint16_t *__restrict__ Lw
     for (int k = 0; k < W; ++k) md[k] = meta[e0 + k];
 #pragma unroll
     for (int k = 0; k < W; ++k) {
-        const Gather g = gather(md[k], u, Zh);
+        const Gather g = gather(md[k], u, 2 * Zh);
         su[k] = g.sel_unpack;
-        raw[k] = Lw[g.addr];
+        raw[k] = lds_ld16(lb, g.off);
     }
     uint32_t acc = 0;
 #pragma unroll
@@ -169,24 +224,24 @@ __device__ __forceinline__ uint32_t row_parity_w(const uint16_t *__restrict__ Lw
 
 // Scalar dispatch on the row weight w in [W, WMAX].
 template <int W, int WMAX>
-__device__ __forceinline__ void row_update(int w, uint16_t *Lw, uint16_t *Rw, const uint32_t *meta,
-                                           int e0, int u, int Zh, bool first_iter, u16x2 wgt,
-                                           u16x2 off16) {
+__device__ __forceinline__ void row_update(int w, uint8_t *lb, uint16_t *Rb, int ro,
+                                           const uint32_t *meta, int e0, int u, int Zh,
+                                           bool first_iter, u16x2 wgt, u16x2 off16) {
     if constexpr (W <= WMAX) {
         if (w == W) {
-            row_update_w<W>(Lw, Rw, meta, e0, u, Zh, first_iter, wgt, off16);
+            row_update_w<W>(lb, Rb, ro, meta, e0, u, Zh, first_iter, wgt, off16);
             return;
         }
-        row_update<W + 1, WMAX>(w, Lw, Rw, meta, e0, u, Zh, first_iter, wgt, off16);
+        row_update<W + 1, WMAX>(w, lb, Rb, ro, meta, e0, u, Zh, first_iter, wgt, off16);
     }
 }
 
 template <int W, int WMAX>
-__device__ __forceinline__ uint32_t row_parity(int w, const uint16_t *Lw, const uint32_t *meta,
+__device__ __forceinline__ uint32_t row_parity(int w, const uint8_t *lb, const uint32_t *meta,
                                                int e0, int u, int Zh) {
     if constexpr (W <= WMAX) {
-        if (w == W) return row_parity_w<W>(Lw, meta, e0, u, Zh);
-        return row_parity<W + 1, WMAX>(w, Lw, meta, e0, u, Zh);
+        if (w == W) return row_parity_w<W>(lb, meta, e0, u, Zh);
+        return row_parity<W + 1, WMAX>(w, lb, meta, e0, u, Zh);
     }
     return 0;
 }
@@ -194,14 +249,14 @@ __device__ __forceinline__ uint32_t row_parity(int w, const uint16_t *Lw, const 
 // Nonzero if some check of lane u's two rows fails on the current hard
 // decisions.
 template <int WMAX>
-__device__ inline uint32_t syndrome_fails(const uint16_t *__restrict__ Lw,
+__device__ inline uint32_t syndrome_fails(const uint8_t *__restrict__ lb,
                                           const int32_t *__restrict__ row_ptr,
                                           const uint32_t *__restrict__ meta, int rows, int u,
                                           int Zh) {
     uint32_t bad = 0;
     for (int r = 0; r < rows; ++r) {
         const int e0 = row_ptr[r], w = row_ptr[r + 1] - e0;
-        bad |= row_parity<2, WMAX>(w, Lw, meta, e0, u, Zh);
+        bad |= row_parity<2, WMAX>(w, lb, meta, e0, u, Zh);
     }
     return bad & 0x80008000u;
 }
@@ -225,9 +280,18 @@ __global__ __launch_bounds__(512) void decode_i8_kernel(DecodeLaunch p,
     const int cw = blockIdx.x * p.cpw + slot;
     const bool valid = cw < p.n_cw;
     uint16_t *Lw = reinterpret_cast<uint16_t *>(smem + slot * slot_bytes);
-    uint16_t *Rw = MSG_IN_LDS ? Lw + N * Zh
-                              : reinterpret_cast<uint16_t *>(p.msg) +
-                                    (size_t)(valid ? cw : 0) * E * Zh;
+    // Lane base for gathers: the codeword's posteriors plus 2u bytes.
+    uint8_t *lb = reinterpret_cast<uint8_t *>(Lw) + 2 * u;
+    // Messages: uniform base plus a 32-bit lane offset (see row_update_w).
+    uint16_t *Rb;
+    int ro;
+    if (MSG_IN_LDS) {
+        Rb = reinterpret_cast<uint16_t *>(smem) + N * Zh;
+        ro = slot * (slot_bytes / 2) + u;
+    } else {
+        Rb = reinterpret_cast<uint16_t *>(p.msg) + (size_t)blockIdx.x * p.cpw * E * Zh;
+        ro = slot * E * Zh + u;
+    }
     int *flags = reinterpret_cast<int *>(smem + p.cpw * slot_bytes);
 
     // Initialisation: punctured columns 0 and 1 carry no channel LLR.
@@ -235,6 +299,7 @@ __global__ __launch_bounds__(512) void decode_i8_kernel(DecodeLaunch p,
         Lw[u] = 0;
         Lw[Zh + u] = 0;
         const int8_t *q = p.llr + (size_t)cw * T;
+#pragma unroll 1
         for (int c = 2; c < N; ++c) {
             int lo = q[(c - 2) * Z + u], hi = q[(c - 2) * Z + u + Zh];
             lo = lo < -127 ? -127 : lo;
@@ -255,13 +320,13 @@ __global__ __launch_bounds__(512) void decode_i8_kernel(DecodeLaunch p,
             const int e0 = row_ptr[r], w = row_ptr[r + 1] - e0;
             if (wrow) wt = wrow[r];
             const u16x2 wgt = {(unsigned short)wt, (unsigned short)wt};
-            if (!done) row_update<2, WMAX>(w, Lw, Rw, meta, e0, u, Zh, t == 1, wgt, off16);
+            if (!done) row_update<2, WMAX>(w, lb, Rb, ro, meta, e0, u, Zh, t == 1, wgt, off16);
             __syncthreads();
         }
         if (p.early_exit || t == p.max_iter) {
             if ((int)threadIdx.x < p.cpw) flags[threadIdx.x] = 0;
             __syncthreads();
-            if (!done && syndrome_fails<WMAX>(Lw, row_ptr, meta, p.rows, u, Zh))
+            if (!done && syndrome_fails<WMAX>(lb, row_ptr, meta, p.rows, u, Zh))
                 atomicOr(&flags[slot], 1);
             __syncthreads();
             const bool holds = flags[slot] == 0;
@@ -281,18 +346,25 @@ __global__ __launch_bounds__(512) void decode_i8_kernel(DecodeLaunch p,
     if (!valid) return;
 
     // Outputs: hard decisions of the K information bits packed LSB first.
-    const int K = p.kb * Z;
+    // Byte j of a codeword covers bits 8j..8j+7, all in one block column
+    // since Z is a multiple of 8; lane u packs byte u of each column.
     const uint8_t *Lb = reinterpret_cast<const uint8_t *>(Lw);
-    for (int j = u; j < K / 8; j += Zh) {
-        uint32_t byte = 0;
+    const int bytes_per_col = Z / 8;
+    uint8_t *ob = p.out_bits + (size_t)cw * (p.kb * bytes_per_col);
+#pragma unroll 1
+    for (int c = 0; c < p.kb; ++c) {
+#pragma unroll 1
+        for (int j = u; j < bytes_per_col; j += Zh) {
+            uint32_t byte = 0;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int v = 8 * j + i, c = v / Z, z = v - c * Z;
-            const int zz = z < Zh ? z : z - Zh;
-            const int8_t L = (int8_t)Lb[2 * (c * Zh + zz) + (z < Zh ? 0 : 1)];
-            byte |= (uint32_t)(L < 0) << i;
+            for (int i = 0; i < 8; ++i) {
+                const int z = 8 * j + i;
+                const int hi = z >= Zh;
+                const int8_t L = (int8_t)Lb[2 * (c * Zh + z - hi * Zh) + hi];
+                byte |= (uint32_t)(L < 0) << i;
+            }
+            ob[c * bytes_per_col + j] = (uint8_t)byte;
         }
-        p.out_bits[(size_t)cw * (K / 8) + j] = (uint8_t)byte;
     }
     if (u == 0) {
         p.out_iters[cw] = iters;
@@ -300,10 +372,11 @@ __global__ __launch_bounds__(512) void decode_i8_kernel(DecodeLaunch p,
     }
     if (p.out_llr) {
         int8_t *o = static_cast<int8_t *>(p.out_llr) + (size_t)cw * N * Z;
-        for (int v = u; v < N * Z; v += Zh) {
-            const int c = v / Z, z = v - c * Z;
-            const int zz = z < Zh ? z : z - Zh;
-            o[v] = (int8_t)Lb[2 * (c * Zh + zz) + (z < Zh ? 0 : 1)];
+#pragma unroll 1
+        for (int c = 0; c < N; ++c) {
+            const uint16_t w = Lw[c * Zh + u];
+            o[c * Z + u] = (int8_t)(w & 0xFF);
+            o[c * Z + u + Zh] = (int8_t)(w >> 8);
         }
     }
 }

@@ -12,17 +12,19 @@ namespace ldpc {
 // current block row; block column c of the posteriors is stored as Zh
 // "pair words", word p holding the variables p and p + Zh of that column.
 // A block with shift s = s_lo + Zh*s_hi (s_lo < Zh) sends both rows of lane
-// u to pair word (u + s_lo) mod Zh; the two halves arrive swapped when
-// [u + s_lo >= Zh] xor s_hi.
-//   bits [0, 16)  c * Zh   (first pair word of the column)
-//   bits [16, 24) s_lo
+// u to pair word c*Zh + (u + s_lo) mod Zh; the two halves arrive swapped
+// when [u + s_lo >= Zh] xor s_hi. With T = Zh - s_lo the wrap test is
+// simply u >= T, so a gather is: word = c*Zh + s_lo + u - (u >= T ? Zh : 0).
+//   bits [0, 16)  c * Zh + s_lo   (pair word before the wrap)
+//   bits [16, 24) T = Zh - s_lo   (1..Zh)
 //   bit  24       s_hi
 // The device copy of the table carries kMetaPad zero entries after the last
 // block so that a kernel may read a fixed-size window from any row start.
 constexpr int kMetaPad = 64;
 
 __host__ __device__ inline uint32_t pack_meta(int c, int s, int Zh) {
-    return (uint32_t)(c * Zh) | ((uint32_t)(s % Zh) << 16) | ((uint32_t)(s / Zh) << 24);
+    const int s_lo = s % Zh;
+    return (uint32_t)(c * Zh + s_lo) | ((uint32_t)(Zh - s_lo) << 16) | ((uint32_t)(s / Zh) << 24);
 }
 
 struct DecodeLaunch {
