@@ -49,6 +49,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the binary16, latency and fixed-iteration runs")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run one plain device-to-device copy of this many MiB before timing "
+                         "(reference dispatch for calibrating memory counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -80,6 +83,13 @@ def main():
     iters = [torch.empty(n, dtype=torch.int32, device=dev) for _ in batches]
     oks = [torch.empty(n, dtype=torch.uint8, device=dev) for _ in batches]
     stream = torch.cuda.current_stream()
+    if args.copy_probe_mib:
+        src = torch.empty(args.copy_probe_mib << 20, dtype=torch.uint8, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     torch.cuda.synchronize()
 
     def run_step(precision="i8", early_exit=True, events=None):

@@ -149,6 +149,33 @@ void ldpc_args_init(ldpc_args *a);
  * Errors: as ldpc_decode. */
 int ldpc_decode_ex(const ldpc_args *a);
 
+/*
+ * ldpc_nwms_loss_grad -- learned weighted min-sum (the min-sum correction
+ * factor of §III replaced by one trainable multiplier w[t][r] per iteration
+ * t and block row r): fp32 unrolled forward pass over n_iter iterations
+ * (no early exit), loss, and the exact gradient from a hand-written
+ * backward pass through the layered schedule.
+ *   llr   : float [n_cw][T] channel LLRs (device), in units where the
+ *           natural-log LLR is llr / scale
+ *   cbits : uint8 [n_cw][Nc] the transmitted codewords, 0/1 (device)
+ *   w     : float [n_iter][rows] multipliers (device)
+ *   loss  : float [n_cw] out: mean over iterations t and code bits j of
+ *           BCE(sigmoid(-L_tj / scale), c_j), L_t the posteriors after t
+ *   grad  : float [n_iter][rows] out: d(sum of loss)/dw, summed over the
+ *           codewords in index order
+ *   out_llr : float [n_cw][Nc] final posteriors or NULL
+ * Signs and argmins are held fixed in the backward pass (min-sum is
+ * piecewise linear); argmin ties resolve to the first block in the row.
+ * Workspace (about (n_iter+1)*(E+Nc)*Z*4 bytes per codeword) is allocated
+ * per call on `stream`. Row weights up to LDPC_NWMS_MAX_ROW_WEIGHT and
+ * Nc*4 bytes of LDS per codeword.
+ * Errors: LDPC_EINVAL, LDPC_ENOGRAPH, LDPC_ENOMEM, LDPC_EHIP.
+ */
+#define LDPC_NWMS_MAX_ROW_WEIGHT 20
+int ldpc_nwms_loss_grad(int bg, int Z, int rows, int n_cw, const float *llr,
+                        const uint8_t *cbits, int n_iter, const float *w, float scale,
+                        float *loss, float *grad, float *out_llr, void *stream);
+
 /* Error text for a return code; the last HIP error code seen by the
  * library (hipError_t as int, 0 if none). */
 const char *ldpc_strerror(int code);

@@ -46,6 +46,9 @@ def _load():
                                           ctypes.c_uint16, P, I, P, P, P, P, I]
         lib.oracle_decode_f64.argtypes = [I, I, I, I, I, P, P, P, I, P, I, I, ctypes.c_double,
                                           ctypes.c_double, P, I, P, P, P, P, I]
+        lib.oracle_nwms_grad_f64.argtypes = [I, I, I, I, P, P, P, I, P, P, I, P, ctypes.c_double,
+                                             P, P]
+        lib.oracle_nwms_grad_f64.restype = ctypes.c_int
         lib.oracle_f64_to_f16.argtypes = [P, P, ctypes.c_long]
         lib.oracle_f16_to_f64.argtypes = [P, P, ctypes.c_long]
         for f in (lib.oracle_decode_i8, lib.oracle_decode_f16, lib.oracle_decode_f64):
@@ -143,6 +146,28 @@ def decode_f64(g, llr, max_iter=10, early_exit=True, beta=0.75, delta=0.0, w=Non
     if rc != 0:
         raise ValueError(f"oracle_decode_f64 failed ({rc})")
     return bits, iters, ok.astype(bool), out
+
+
+def nwms_loss_grad(g, llr, cbits, w, scale=4.0):
+    """Learned weighted min-sum in double precision: per-codeword loss
+    (mean over iterations and bits of the BCE of sigmoid(-L/scale) against
+    the codeword) and the exact gradient of the summed loss with respect to
+    the weights w [n_iter, M]. llr [n_cw, T] real, cbits [n_cw, N*Z] 0/1."""
+    llr = np.ascontiguousarray(llr, dtype=np.float64)
+    cb = np.ascontiguousarray(cbits, dtype=np.uint8)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    n_cw = llr.shape[0]
+    assert llr.shape == (n_cw, g.T) and cb.shape == (n_cw, g.N * g.Z)
+    assert w.ndim == 2 and w.shape[1] == g.M
+    dims, (rp, col, sh) = _graph_args(g)
+    loss = np.zeros(n_cw)
+    grad = np.zeros_like(w)
+    rc = _load().oracle_nwms_grad_f64(g.M, g.N, g.Z, g.n_punct, _ptr(rp), _ptr(col), _ptr(sh),
+                                      n_cw, _ptr(llr), _ptr(cb), w.shape[0], _ptr(w),
+                                      float(scale), _ptr(loss), _ptr(grad))
+    if rc != 0:
+        raise ValueError(f"oracle_nwms_grad_f64 failed ({rc})")
+    return loss, grad
 
 
 def unpack_bits(bits: np.ndarray, K: int) -> np.ndarray:

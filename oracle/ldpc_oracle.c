@@ -550,3 +550,150 @@ int oracle_decode_f64(int M, int N, int Z, int n_punct, int K,
     free(jobs);
     return status;
 }
+
+/* ------------------------------------------------------------------ */
+/* Learned (neural) weighted min-sum: loss and exact gradient, double  */
+/* ------------------------------------------------------------------ */
+/*
+ * Forward: the layered min-sum of the double mode with one multiplier per
+ * (iteration t, block row r), w[t][r], no offset, no early exit, n_iter
+ * iterations. Posterior after iteration t: L_t. With y = L_t / scale (scale
+ * converts the LLR units to natural-log units) and p = sigmoid(-y) =
+ * P(bit = 1), the loss of a codeword c is
+ *     loss = (1/n_iter) * sum_t (1/(N*Z)) * sum_j BCE(p_tj, c_j),
+ * BCE(p, c) = -(c log p + (1 - c) log(1 - p)); dBCE/dL = (c - p) / scale.
+ *
+ * Backward (reverse of the layered schedule). Each check-row update
+ *     x_k = L_k - R_k,  m1 = |x_k1|, m2 = |x_k2|  (k1 = first argmin,
+ *     k2 = first argmin over k != k1),  R'_k = s_k * w * (k == k1 ? m2 : m1)
+ *     with s_k the product of sgn(x_j) over j != k,  L'_k = x_k + R'_k
+ * is differentiated with the signs and argmins held fixed (they are
+ * piecewise constant): with gL' and gR' the gradients of the new L_k and
+ * R_k, g_k = (gL'_k + gR'_k) * s_k, then
+ *     dw += sum_k g_k * (k == k1 ? m2 : m1),
+ *     gx_k = gL'_k + [k == k1] sgn(x_k1) w sum_{j != k1} g_j
+ *                  + [k == k2] sgn(x_k2) w g_k1,
+ * and the old values get gL_k = gx_k, gR_k = -gx_k. sgn(x) = -1 iff the
+ * sign bit of x is set.
+ */
+static inline double sgn_bit(double v) { return signbit(v) ? -1.0 : 1.0; }
+
+static double softplus(double v) { return v > 0 ? v + log1p(exp(-v)) : log1p(exp(v)); }
+
+int oracle_nwms_grad_f64(int M, int N, int Z, int n_punct,
+                         const int32_t *row_ptr, const int16_t *col, const int16_t *shift,
+                         int n_cw, const double *llr, const uint8_t *cbits, int n_iter,
+                         const double *w, double scale, double *loss, double *grad_w) {
+    graph_t g = {M, N, Z, n_punct, row_ptr, col, shift};
+    if (!graph_check(&g) || n_cw < 1 || n_iter < 1 || !llr || !cbits || !w || !loss ||
+        !grad_w || !(scale > 0))
+        return ORACLE_EINVAL;
+    const int NZ = N * Z, E = row_ptr[M], T = (N - n_punct) * Z;
+    const int wmax = max_row_weight(&g);
+    double *L = malloc(sizeof(double) * NZ);
+    double *R = malloc(sizeof(double) * (size_t)E * Z);
+    double *X = malloc(sizeof(double) * (size_t)n_iter * E * Z);  /* tape of x */
+    double *Lt = malloc(sizeof(double) * (size_t)n_iter * NZ);    /* posteriors per iteration */
+    double *gL = malloc(sizeof(double) * NZ);
+    double *gR = malloc(sizeof(double) * (size_t)E * Z);
+    double *gk = malloc(sizeof(double) * (size_t)wmax);
+    if (!L || !R || !X || !Lt || !gL || !gR || !gk) {
+        free(L); free(R); free(X); free(Lt); free(gL); free(gR); free(gk);
+        return ORACLE_ENOMEM;
+    }
+    for (int i = 0; i < n_iter * M; ++i) grad_w[i] = 0.0;
+    for (int cw = 0; cw < n_cw; ++cw) {
+        const double *b = llr + (size_t)cw * T;
+        const uint8_t *c = cbits + (size_t)cw * NZ;
+        for (int j = 0; j < n_punct * Z; ++j) L[j] = 0.0;
+        for (int i = 0; i < T; ++i) L[n_punct * Z + i] = b[i];
+        for (size_t i = 0; i < (size_t)E * Z; ++i) R[i] = 0.0;
+        /* forward */
+        for (int t = 0; t < n_iter; ++t) {
+            for (int r = 0; r < M; ++r) {
+                const int e0 = row_ptr[r], wr = row_ptr[r + 1] - e0;
+                const double wt = w[(size_t)t * M + r];
+                for (int z = 0; z < Z; ++z) {
+                    double *x = X + ((size_t)t * E + e0) * Z;  /* x of edge e0+k at x[k*Z+z] */
+                    double m1 = INFINITY, m2 = INFINITY;
+                    int k1 = -1, S = 0;
+                    for (int k = 0; k < wr; ++k) {
+                        const double xv = L[var_of(&g, e0 + k, z)] - R[(size_t)(e0 + k) * Z + z];
+                        x[(size_t)k * Z + z] = xv;
+                        const double a = fabs(xv);
+                        if (a < m1) { m2 = m1; m1 = a; k1 = k; }
+                        else if (a < m2) { m2 = a; }
+                        S ^= signbit(xv) ? 1 : 0;
+                    }
+                    for (int k = 0; k < wr; ++k) {
+                        const double xv = x[(size_t)k * Z + z];
+                        const double mag = wt * ((k == k1) ? m2 : m1);
+                        const int neg = S ^ (signbit(xv) ? 1 : 0);
+                        const double rn = neg ? -mag : mag;
+                        R[(size_t)(e0 + k) * Z + z] = rn;
+                        L[var_of(&g, e0 + k, z)] = xv + rn;
+                    }
+                }
+            }
+            memcpy(Lt + (size_t)t * NZ, L, sizeof(double) * NZ);
+        }
+        /* loss */
+        double lsum = 0.0;
+        for (int t = 0; t < n_iter; ++t)
+            for (int j = 0; j < NZ; ++j) {
+                const double y = Lt[(size_t)t * NZ + j] / scale;
+                lsum += c[j] ? softplus(y) : softplus(-y);
+            }
+        loss[cw] = lsum / ((double)n_iter * NZ);
+        /* backward */
+        for (int j = 0; j < NZ; ++j) gL[j] = 0.0;
+        for (size_t i = 0; i < (size_t)E * Z; ++i) gR[i] = 0.0;
+        const double coef = 1.0 / ((double)n_iter * NZ * scale);
+        for (int t = n_iter - 1; t >= 0; --t) {
+            for (int j = 0; j < NZ; ++j) {
+                const double y = Lt[(size_t)t * NZ + j] / scale;
+                const double p = 1.0 / (1.0 + exp(y)); /* sigmoid(-y) */
+                gL[j] += (c[j] - p) * coef;
+            }
+            for (int r = M - 1; r >= 0; --r) {
+                const int e0 = row_ptr[r], wr = row_ptr[r + 1] - e0;
+                const double wt = w[(size_t)t * M + r];
+                double gw = 0.0;
+                for (int z = 0; z < Z; ++z) {
+                    const double *x = X + ((size_t)t * E + e0) * Z;
+                    double m1 = INFINITY, m2 = INFINITY;
+                    int k1 = -1, k2 = -1, S = 0;
+                    for (int k = 0; k < wr; ++k) {
+                        const double a = fabs(x[(size_t)k * Z + z]);
+                        if (a < m1) { m2 = m1; k2 = k1; m1 = a; k1 = k; }
+                        else if (a < m2) { m2 = a; k2 = k; }
+                        S ^= signbit(x[(size_t)k * Z + z]) ? 1 : 0;
+                    }
+                    double gsum_not_k1 = 0.0;
+                    for (int k = 0; k < wr; ++k) {
+                        const double xv = x[(size_t)k * Z + z];
+                        const int v = var_of(&g, e0 + k, z);
+                        const size_t er = (size_t)(e0 + k) * Z + z;
+                        const double sk = (S ^ (signbit(xv) ? 1 : 0)) ? -1.0 : 1.0;
+                        gk[k] = (gL[v] + gR[er]) * sk;
+                        gw += gk[k] * ((k == k1) ? m2 : m1);
+                        if (k != k1) gsum_not_k1 += gk[k];
+                    }
+                    for (int k = 0; k < wr; ++k) {
+                        const double xv = x[(size_t)k * Z + z];
+                        const int v = var_of(&g, e0 + k, z);
+                        const size_t er = (size_t)(e0 + k) * Z + z;
+                        double gx = gL[v];
+                        if (k == k1) gx += sgn_bit(xv) * wt * gsum_not_k1;
+                        if (k == k2) gx += sgn_bit(xv) * wt * gk[k1];
+                        gL[v] = gx;
+                        gR[er] = -gx;
+                    }
+                }
+                grad_w[(size_t)t * M + r] += gw;
+            }
+        }
+    }
+    free(L); free(R); free(X); free(Lt); free(gL); free(gR); free(gk);
+    return ORACLE_OK;
+}

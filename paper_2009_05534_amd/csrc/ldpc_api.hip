@@ -21,8 +21,9 @@ struct HostGraph {
 };
 
 struct DevTables {
-    int32_t *row_ptr = nullptr;  // [m_rows + 1]
-    uint32_t *meta = nullptr;    // [E_full]
+    int32_t *row_ptr = nullptr;   // [m_rows + 1]
+    uint32_t *meta = nullptr;     // [E_full + kMetaPad] row-pair layout
+    uint32_t *meta_row = nullptr; // [E_full + kMetaPad] one row per lane
 };
 
 std::mutex g_mu;
@@ -43,8 +44,10 @@ bool valid_lift(int Z) { return Z >= 8 && Z <= LDPC_MAX_Z && Z % 8 == 0; }
 void free_tables(DevTables &t) {
     if (t.row_ptr) (void)hipFree(t.row_ptr);
     if (t.meta) (void)hipFree(t.meta);
+    if (t.meta_row) (void)hipFree(t.meta_row);
     t.row_ptr = nullptr;
     t.meta = nullptr;
+    t.meta_row = nullptr;
 }
 
 // Device tables of graph (bg, Z) on the current device; caller holds g_mu.
@@ -60,14 +63,20 @@ int tables_for(const HostGraph &g, DevTables **out) {
     }
     const int Zh = g.Z / 2;
     const int E = g.row_ptr.back();
-    std::vector<uint32_t> meta(E + kMetaPad, 0u);
-    for (int e2 = 0; e2 < E; ++e2) meta[e2] = pack_meta(g.col[e2], g.shift[e2], Zh);
+    std::vector<uint32_t> meta(E + kMetaPad, 0u), meta_row(E + kMetaPad, 0u);
+    for (int e2 = 0; e2 < E; ++e2) {
+        meta[e2] = pack_meta(g.col[e2], g.shift[e2], Zh);
+        meta_row[e2] = pack_meta_row(g.col[e2], g.shift[e2], g.Z);
+    }
     DevTables t;
     if ((e = hipMalloc(&t.row_ptr, sizeof(int32_t) * g.row_ptr.size())) != hipSuccess ||
         (e = hipMalloc(&t.meta, sizeof(uint32_t) * meta.size())) != hipSuccess ||
+        (e = hipMalloc(&t.meta_row, sizeof(uint32_t) * meta_row.size())) != hipSuccess ||
         (e = hipMemcpy(t.row_ptr, g.row_ptr.data(), sizeof(int32_t) * g.row_ptr.size(),
                        hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(t.meta, meta.data(), sizeof(uint32_t) * meta.size(),
+                       hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(t.meta_row, meta_row.data(), sizeof(uint32_t) * meta_row.size(),
                        hipMemcpyHostToDevice)) != hipSuccess) {
         free_tables(t);
         return hip_fail(e);
@@ -288,6 +297,46 @@ int ldpc_decode(int bg, int Z, int rows, int n_cw, const int8_t *llr_in, int max
     a.out_iters = out_iters;
     a.stream = stream;
     return ldpc_decode_ex(&a);
+}
+
+int ldpc_nwms_loss_grad(int bg, int Z, int rows, int n_cw, const float *llr,
+                        const uint8_t *cbits, int n_iter, const float *w, float scale,
+                        float *loss, float *grad, float *out_llr, void *stream) {
+    if (n_cw < 1 || n_iter < 1 || n_iter > LDPC_MAX_ITER || !llr || !cbits || !w || !loss ||
+        !grad || !(scale > 0.0f))
+        return LDPC_EINVAL;
+    const int32_t *row_ptr = nullptr;
+    const uint32_t *meta_row = nullptr;
+    int E = 0, n_cols = 0, wmax = 0, lds_cap = 0;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_graphs.find({bg, Z});
+        if (it == g_graphs.end()) return LDPC_ENOGRAPH;
+        const HostGraph &g = it->second;
+        if (sub_sizes(g, rows, nullptr, nullptr, nullptr, &E) != LDPC_OK) return LDPC_EINVAL;
+        for (int r = 0; r < rows; ++r)
+            if (g.row_ptr[r + 1] - g.row_ptr[r] > wmax) wmax = g.row_ptr[r + 1] - g.row_ptr[r];
+        DevTables *t = nullptr;
+        const int rc = tables_for(g, &t);
+        if (rc != LDPC_OK) return rc;
+        row_ptr = t->row_ptr;
+        meta_row = t->meta_row;
+        n_cols = g.kb + rows;
+        lds_cap = max_lds_bytes();
+    }
+    if (wmax > LDPC_NWMS_MAX_ROW_WEIGHT || n_cols * Z * (int)sizeof(float) > lds_cap)
+        return LDPC_EINVAL;
+    hipStream_t stream_h = static_cast<hipStream_t>(stream);
+    void *ws = nullptr;
+    const size_t bytes = sizeof(float) * nwms_workspace_floats(n_cw, rows, n_cols, Z, E, n_iter);
+    hipError_t e = hipMallocAsync(&ws, bytes, stream_h);
+    if (e != hipSuccess) return hip_fail(e, "hipMallocAsync(nwms workspace)");
+    e = launch_nwms(llr, cbits, w, loss, grad, out_llr, static_cast<float *>(ws), n_cw, rows,
+                    n_cols, Z, E, n_iter, scale, row_ptr, meta_row, wmax, stream_h);
+    const hipError_t ef = hipFreeAsync(ws, stream_h);
+    if (e != hipSuccess) return e == hipErrorOutOfMemory ? LDPC_ENOMEM : LDPC_EHIP;
+    if (ef != hipSuccess) return hip_fail(ef, "hipFreeAsync(nwms workspace)");
+    return LDPC_OK;
 }
 
 const char *ldpc_strerror(int code) {

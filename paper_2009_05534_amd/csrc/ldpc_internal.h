@@ -53,9 +53,22 @@ __host__ __device__ inline int lds_bytes_i8(int n_cols, int E, int Z) { return (
 __host__ __device__ inline int lds_bytes_i8_post(int n_cols, int Z) { return n_cols * Z; }
 __host__ __device__ inline int lds_bytes_f16(int n_cols, int Z) { return n_cols * Z * 2; }
 
+// Per-block metadata for one-row-per-lane kernels (the learned min-sum):
+// bits [0, 16) c * Z, bits [16, 25) shift. Padded like the pair table.
+__host__ __device__ inline uint32_t pack_meta_row(int c, int s, int Z) {
+    return (uint32_t)(c * Z) | ((uint32_t)s << 16);
+}
+
 // Host launchers; return hipSuccess or the launch error.
 hipError_t launch_decode_i8(const DecodeLaunch &p, hipStream_t stream);
 hipError_t launch_decode_f16(const DecodeLaunch &p, hipStream_t stream);
+
+// Learned weighted min-sum: forward, backward and gradient reduction.
+size_t nwms_workspace_floats(int n_cw, int rows, int n_cols, int Z, int E, int n_iter);
+hipError_t launch_nwms(const float *llr, const uint8_t *cbits, const float *w, float *loss,
+                       float *grad, float *out_llr, float *ws, int n_cw, int rows, int n_cols,
+                       int Z, int E, int n_iter, float scale, const int32_t *row_ptr,
+                       const uint32_t *meta_row, int wmax, hipStream_t stream);
 
 // Largest dynamic LDS a workgroup may use on the device (bytes).
 int max_lds_bytes();

@@ -44,7 +44,8 @@ class Args(ctypes.Structure):
 
 
 EXPORTS = ("ldpc_set_graph", "ldpc_query", "ldpc_decode", "ldpc_args_init", "ldpc_decode_ex",
-           "ldpc_strerror", "ldpc_last_hip_error", "ldpc_last_error_message", "ldpc_shutdown")
+           "ldpc_nwms_loss_grad", "ldpc_strerror", "ldpc_last_hip_error",
+           "ldpc_last_error_message", "ldpc_shutdown")
 
 _lib = None
 
@@ -63,6 +64,7 @@ def lib():
         L.ldpc_args_init.argtypes = [ctypes.POINTER(Args)]
         L.ldpc_args_init.restype = None
         L.ldpc_decode_ex.argtypes = [ctypes.POINTER(Args)]
+        L.ldpc_nwms_loss_grad.argtypes = [I, I, I, I, P, P, I, P, ctypes.c_float, P, P, P, P]
         L.ldpc_strerror.argtypes = [I]
         L.ldpc_strerror.restype = ctypes.c_char_p
         L.ldpc_last_hip_error.argtypes = []
@@ -203,3 +205,30 @@ def decode(llr, bg: int, Z: int, rows: int, *, max_iter: int = 10, precision: st
                 out_llr=out, cw_per_block=cw_per_block, msg_placement=msg_placement,
                 stream=stream)
     return bits, iters, (ok.bool() if ok is not None else None), out
+
+
+def nwms_loss_grad(llr, cbits, w, bg: int, Z: int, rows: int, *, scale: float = 4.0,
+                   want_llr: bool = False, stream=None):
+    """Learned weighted min-sum on the GPU: fp32 unrolled forward pass over
+    w.shape[0] iterations, loss per codeword and the gradient of the summed
+    loss with respect to w [n_iter, rows] (hand-written backward kernel).
+
+    llr float32 [n, T] and cbits uint8 [n, Nc] are device tensors; returns
+    (loss [n], grad [n_iter, rows], final posteriors [n, Nc] or None)."""
+    import torch
+    K, T, Nc, E = query(bg, Z, rows)
+    n = int(llr.shape[0])
+    _require(llr, (n, T), 4, "llr")
+    _require(cbits, (n, Nc), 1, "cbits")
+    if w.dim() != 2 or w.shape[1] != rows:
+        raise ValueError("w must be [n_iter, rows]")
+    _require(w, tuple(w.shape), 4, "w")
+    dev = llr.device
+    loss = torch.empty(n, dtype=torch.float32, device=dev)
+    grad = torch.empty(tuple(w.shape), dtype=torch.float32, device=dev)
+    out = torch.empty((n, Nc), dtype=torch.float32, device=dev) if want_llr else None
+    _check(lib().ldpc_nwms_loss_grad(bg, Z, rows, n, llr.data_ptr(), cbits.data_ptr(),
+                                     int(w.shape[0]), w.data_ptr(), float(scale), loss.data_ptr(),
+                                     grad.data_ptr(), out.data_ptr() if out is not None else None,
+                                     _stream_ptr(stream)), "ldpc_nwms_loss_grad")
+    return loss, grad, out
