@@ -150,6 +150,50 @@ void ldpc_args_init(ldpc_args *a);
 int ldpc_decode_ex(const ldpc_args *a);
 
 /*
+ * Mixed-shape batches. A job is a set of codewords of one shape (bg, Z,
+ * rows) with its own device buffers: llr int8 [n_cw][T], out_bits
+ * [n_cw][K/8], out_iters int32 [n_cw], out_ok uint8 [n_cw] or NULL, and
+ * optional per-(iteration, row) Q1.7 weights wq [wq_iters][rows] (NULL:
+ * beta = 3/4). All of a batch's jobs are decoded by ONE persistent launch of
+ * the int8 kernel (messages in device memory): each workgroup takes tasks of
+ * up to 384/Z codewords of one job from a device counter until none are
+ * left. Results are identical to decoding each job alone (ldpc_decode_ex
+ * with the same options). Lifts up to 384, row weights up to 20.
+ */
+typedef struct ldpc_job {
+    int bg, Z, rows, n_cw;
+    const int8_t *llr;
+    uint8_t *out_bits;
+    int32_t *out_iters;
+    uint8_t *out_ok;
+    const uint8_t *wq;
+    int wq_iters;
+} ldpc_job;
+
+/* One-shot batch decode: builds a transient plan, launches it on `stream`,
+ * waits for the stream, and releases the plan. */
+int ldpc_decode_batch(const ldpc_job *jobs, int n_jobs, int max_iter, int early_exit,
+                      void *stream);
+
+/* A reusable plan bound to the jobs' buffers (refill the inputs and launch
+ * again). Flags: LDPC_PLAN_GRAPH captures the launch (a counter-reset
+ * kernel, then the decode) as a HIP graph that ldpc_plan_launch replays;
+ * LDPC_PLAN_AUTOTUNE times 1..k workgroups per CU on the plan's own work
+ * (running it, so the outputs are written) and keeps the fastest. Creation
+ * synchronises `stream`. Plans launched on different streams must not
+ * overlap (they share the plan's counter and message regions). */
+typedef struct ldpc_plan ldpc_plan;
+#define LDPC_PLAN_GRAPH 1
+#define LDPC_PLAN_AUTOTUNE 2
+int ldpc_plan_create(const ldpc_job *jobs, int n_jobs, int max_iter, int early_exit, int flags,
+                     void *stream, ldpc_plan **out);
+int ldpc_plan_launch(ldpc_plan *plan, void *stream);
+/* grid: persistent workgroups; n_tasks: tasks in the queue; tuned_ms: time
+ * of the chosen grid when autotuned (else 0). Any output may be NULL. */
+int ldpc_plan_info(const ldpc_plan *plan, int *grid, int *n_tasks, float *tuned_ms);
+void ldpc_plan_destroy(ldpc_plan *plan);
+
+/*
  * ldpc_nwms_loss_grad -- learned weighted min-sum (the min-sum correction
  * factor of §III replaced by one trainable multiplier w[t][r] per iteration
  * t and block row r): fp32 unrolled forward pass over n_iter iterations

@@ -1,0 +1,199 @@
+// Mixed-shape batch plans: one persistent launch decodes many jobs (each a
+// set of codewords of one (bg, Z, rows) shape with its own buffers). A plan
+// owns the device task and job tables, the per-workgroup message regions and
+// the work counter; it can be captured once as a HIP graph (a counter-reset
+// kernel, then the decode) and replayed, and it can pick its grid size by
+// timing the candidates on its own work (autotuning).
+#include <algorithm>
+#include <vector>
+
+#include "../../include/ldpc.h"
+#include "ldpc_internal.h"
+
+namespace ldpc {
+
+struct Plan {
+    BatchLaunch launch{};
+    BatchTask *d_tasks = nullptr;
+    BatchJob *d_jobs = nullptr;
+    unsigned *d_counter = nullptr;
+    uint16_t *d_msg = nullptr;
+    size_t msg_capacity = 0;  // pair words allocated
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int cus = 0, max_per_cu = 1;
+    float tuned_ms = 0.0f;
+};
+
+namespace {
+
+void free_plan(Plan *p) {
+    if (!p) return;
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->d_tasks) (void)hipFree(p->d_tasks);
+    if (p->d_jobs) (void)hipFree(p->d_jobs);
+    if (p->d_counter) (void)hipFree(p->d_counter);
+    if (p->d_msg) (void)hipFree(p->d_msg);
+    delete p;
+}
+
+// Grow the message workspace to `grid` workgroups.
+hipError_t size_messages(Plan *p, int grid) {
+    const size_t need = (size_t)grid * p->launch.msg_per_block;
+    if (need > p->msg_capacity) {
+        if (p->d_msg) (void)hipFree(p->d_msg);
+        p->d_msg = nullptr;
+        p->msg_capacity = 0;
+        hipError_t e = hipMalloc(&p->d_msg, need * sizeof(uint16_t));
+        if (e != hipSuccess) return e;
+        p->msg_capacity = need;
+    }
+    p->launch.msg = p->d_msg;
+    p->launch.grid = grid;
+    return hipSuccess;
+}
+
+}  // namespace
+
+// Fills the job table from the registered graphs; called under the graph
+// registry lock by ldpc_plan_create.
+int plan_build(Plan *p, const std::vector<BatchJob> &jobs, const std::vector<int> &job_cw,
+               int lanes, int max_iter, int early_exit, int beta, int offset, int wmax,
+               int lds_cap, hipStream_t stream) {
+    std::vector<BatchTask> tasks;
+    int lds = 0, msg_per_block = 0;
+    for (size_t j = 0; j < jobs.size(); ++j) {
+        const BatchJob &jb = jobs[j];
+        const int per_cw = lds_bytes_i8_post(jb.n_cols, jb.Z);
+        lds = std::max(lds, jb.slots * per_cw + jb.slots * (int)sizeof(int));
+        msg_per_block = std::max(msg_per_block, jb.slots * jb.E * (jb.Z / 2));
+        for (int f = 0; f < job_cw[j]; f += jb.slots)
+            tasks.push_back(BatchTask{(int)j, f, std::min(jb.slots, job_cw[j] - f), 0});
+    }
+    if (lds > lds_cap) return LDPC_EINVAL;
+    // Longest tasks first (larger lifts and more rows), so that the tail of
+    // the persistent loop holds the short ones.
+    std::stable_sort(tasks.begin(), tasks.end(), [&](const BatchTask &a, const BatchTask &b) {
+        const BatchJob &x = jobs[a.job], &y = jobs[b.job];
+        return (long)x.E * x.Z > (long)y.E * y.Z;
+    });
+    hipError_t e;
+    if ((e = hipMalloc(&p->d_tasks, sizeof(BatchTask) * std::max<size_t>(tasks.size(), 1))) !=
+            hipSuccess ||
+        (e = hipMalloc(&p->d_jobs, sizeof(BatchJob) * jobs.size())) != hipSuccess ||
+        (e = hipMalloc(&p->d_counter, sizeof(unsigned))) != hipSuccess ||
+        (e = hipMemcpyAsync(p->d_tasks, tasks.data(), sizeof(BatchTask) * tasks.size(),
+                            hipMemcpyHostToDevice, stream)) != hipSuccess ||
+        (e = hipMemcpyAsync(p->d_jobs, jobs.data(), sizeof(BatchJob) * jobs.size(),
+                            hipMemcpyHostToDevice, stream)) != hipSuccess ||
+        (e = hipStreamSynchronize(stream)) != hipSuccess) {
+        note_hip_error("plan tables", e);
+        return e == hipErrorOutOfMemory ? LDPC_ENOMEM : LDPC_EHIP;
+    }
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&p->cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (p->cus < 1) p->cus = 1;
+    p->max_per_cu = std::max(1, std::min(8, lds_cap / std::max(lds, 1)));
+    BatchLaunch &b = p->launch;
+    b.tasks = p->d_tasks;
+    b.jobs = p->d_jobs;
+    b.n_tasks = (int)tasks.size();
+    b.counter = p->d_counter;
+    b.msg_per_block = msg_per_block;
+    b.max_iter = max_iter;
+    b.early_exit = early_exit;
+    b.beta = beta;
+    b.offset = offset;
+    b.lanes = lanes;
+    b.lds = lds;
+    b.wmax = wmax;
+    // default grid: as many workgroups as LDS allows on every CU, but no
+    // more than there are tasks
+    const int grid = std::max(1, std::min(b.n_tasks, p->cus * p->max_per_cu));
+    e = size_messages(p, grid);
+    if (e != hipSuccess) {
+        note_hip_error("plan message workspace", e);
+        return e == hipErrorOutOfMemory ? LDPC_ENOMEM : LDPC_EHIP;
+    }
+    return LDPC_OK;
+}
+
+// Times each candidate grid (1..max_per_cu workgroups per CU) on the
+// plan's own work and keeps the fastest.
+int plan_autotune(Plan *p, hipStream_t stream) {
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return LDPC_EHIP;
+    float best = 1e30f;
+    int best_grid = p->launch.grid;
+    for (int per = 1; per <= p->max_per_cu; ++per) {
+        const int grid = std::max(1, std::min(p->launch.n_tasks, p->cus * per));
+        if (size_messages(p, grid) != hipSuccess) break;
+        float t = 0.0f;
+        for (int rep = 0; rep < 3; ++rep) {
+            (void)hipEventRecord(e0, stream);
+            if (launch_decode_batch(p->launch, stream) != hipSuccess) {
+                (void)hipEventDestroy(e0);
+                (void)hipEventDestroy(e1);
+                return LDPC_EHIP;
+            }
+            (void)hipEventRecord(e1, stream);
+            (void)hipEventSynchronize(e1);
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (rep > 0) t += ms;  // first run warms up
+        }
+        t /= 2.0f;
+        if (t < best) {
+            best = t;
+            best_grid = grid;
+        }
+        if (grid >= p->launch.n_tasks) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (size_messages(p, best_grid) != hipSuccess) return LDPC_ENOMEM;
+    p->tuned_ms = best;
+    return LDPC_OK;
+}
+
+int plan_capture(Plan *p) {
+    hipStream_t s;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return LDPC_EHIP;
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        const hipError_t el = launch_decode_batch(p->launch, s);
+        e = hipStreamEndCapture(s, &p->graph);
+        if (el != hipSuccess) e = el;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(s);
+    if (e != hipSuccess) {
+        note_hip_error("plan graph capture", e);
+        return LDPC_EHIP;
+    }
+    return LDPC_OK;
+}
+
+int plan_launch(Plan *p, hipStream_t stream) {
+    const hipError_t e = p->exec ? hipGraphLaunch(p->exec, stream)
+                                 : launch_decode_batch(p->launch, stream);
+    if (e != hipSuccess) {
+        note_hip_error("plan launch", e);
+        return LDPC_EHIP;
+    }
+    return LDPC_OK;
+}
+
+void plan_destroy(Plan *p) { free_plan(p); }
+
+Plan *plan_new() { return new Plan(); }
+
+void plan_info(const Plan *p, int *grid, int *n_tasks, float *tuned_ms) {
+    if (grid) *grid = p->launch.grid;
+    if (n_tasks) *n_tasks = p->launch.n_tasks;
+    if (tuned_ms) *tuned_ms = p->tuned_ms;
+}
+
+}  // namespace ldpc

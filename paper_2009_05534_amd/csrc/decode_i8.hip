@@ -150,7 +150,7 @@ __device__ __forceinline__ void row_phase1(const uint8_t *__restrict__ lb,
 template <int W>
 __device__ __forceinline__ void row_update_w(uint8_t *__restrict__ lb,
                                              uint16_t *__restrict__ Rb, int ro,
-                                             const uint32_t *__restrict__ meta, int e0, int u,
+                                             cmeta_t meta, int e0, int u,
                                              int Zh, bool first_iter, u16x2 wgt, u16x2 off16) {
     constexpr bool kWide = W > 10;
     uint32_t md[W];
@@ -205,7 +205,7 @@ __device__ __forceinline__ void row_update_w(uint8_t *__restrict__ lb,
 // 15 and 31 (hard decision [L_v < 0]).
 template <int W>
 __device__ __forceinline__ uint32_t row_parity_w(const uint8_t *__restrict__ lb,
-                                                 const uint32_t *__restrict__ meta, int e0, int u,
+                                                 cmeta_t meta, int e0, int u,
                                                  int Zh) {
     uint32_t md[W], raw[W], su[W];
 #pragma unroll
@@ -225,7 +225,7 @@ __device__ __forceinline__ uint32_t row_parity_w(const uint8_t *__restrict__ lb,
 // Scalar dispatch on the row weight w in [W, WMAX].
 template <int W, int WMAX>
 __device__ __forceinline__ void row_update(int w, uint8_t *lb, uint16_t *Rb, int ro,
-                                           const uint32_t *meta, int e0, int u, int Zh,
+                                           cmeta_t meta, int e0, int u, int Zh,
                                            bool first_iter, u16x2 wgt, u16x2 off16) {
     if constexpr (W <= WMAX) {
         if (w == W) {
@@ -237,7 +237,7 @@ __device__ __forceinline__ void row_update(int w, uint8_t *lb, uint16_t *Rb, int
 }
 
 template <int W, int WMAX>
-__device__ __forceinline__ uint32_t row_parity(int w, const uint8_t *lb, const uint32_t *meta,
+__device__ __forceinline__ uint32_t row_parity(int w, const uint8_t *lb, cmeta_t meta,
                                                int e0, int u, int Zh) {
     if constexpr (W <= WMAX) {
         if (w == W) return row_parity_w<W>(lb, meta, e0, u, Zh);
@@ -250,8 +250,7 @@ __device__ __forceinline__ uint32_t row_parity(int w, const uint8_t *lb, const u
 // decisions.
 template <int WMAX>
 __device__ inline uint32_t syndrome_fails(const uint8_t *__restrict__ lb,
-                                          const int32_t *__restrict__ row_ptr,
-                                          const uint32_t *__restrict__ meta, int rows, int u,
+                                          crow_t row_ptr, cmeta_t meta, int rows, int u,
                                           int Zh) {
     uint32_t bad = 0;
     for (int r = 0; r < rows; ++r) {
@@ -261,25 +260,26 @@ __device__ inline uint32_t syndrome_fails(const uint8_t *__restrict__ lb,
     return bad & 0x80008000u;
 }
 
+// Decodes `bw.n` codewords of one shape in this workgroup: codeword `slot`
+// is held by lanes [slot*Z/2, (slot+1)*Z/2); lanes beyond n*Z/2 only join
+// the barriers. Every thread of the workgroup must call it.
 // MSG_IN_LDS: the check-to-variable messages live next to the posteriors in
 // LDS (one BG1-shaped Z = 384 codeword fills a CU); otherwise they stream
-// through device memory (p.msg, [n_cw][E][Z/2] pair words) and only the
+// through device memory (bw.msg, [n][E][Z/2] pair words) and only the
 // posteriors occupy LDS, so several codewords share a CU (§IV's placement
 // of L_v in shared memory and L_{c->v} in main memory).
 template <int WMAX, bool MSG_IN_LDS>
-__global__ __launch_bounds__(512) void decode_i8_kernel(DecodeLaunch p,
-                                                         const int32_t *__restrict__ row_ptr,
-                                                         const uint32_t *__restrict__ meta) {
+__device__ __forceinline__ void decode_block(const BlockWork &bw, uint8_t *smem, crow_t row_ptr,
+                                             cmeta_t meta) {
     static_assert(WMAX <= kMetaPad, "row metadata window exceeds the table padding");
-    extern __shared__ __align__(16) uint8_t smem[];
-    const int Z = p.Z, Zh = Z >> 1;
-    const int N = p.n_cols, E = p.E, T = (N - 2) * Z;
+    const int Z = bw.Z, Zh = Z >> 1;
+    const int N = bw.n_cols, E = bw.E, T = (N - 2) * Z;
     const int slot_bytes = MSG_IN_LDS ? lds_bytes_i8(N, E, Z) : lds_bytes_i8_post(N, Z);
     const int slot = threadIdx.x / Zh;
     const int u = threadIdx.x - slot * Zh;
-    const int cw = blockIdx.x * p.cpw + slot;
-    const bool valid = cw < p.n_cw;
-    uint16_t *Lw = reinterpret_cast<uint16_t *>(smem + slot * slot_bytes);
+    const bool valid = slot < bw.n;
+    const int sl = valid ? slot : 0;  // keeps idle lanes' pointers in range
+    uint16_t *Lw = reinterpret_cast<uint16_t *>(smem + sl * slot_bytes);
     // Lane base for gathers: the codeword's posteriors plus 2u bytes.
     uint8_t *lb = reinterpret_cast<uint8_t *>(Lw) + 2 * u;
     // Messages: uniform base plus a 32-bit lane offset (see row_update_w).
@@ -287,18 +287,18 @@ __global__ __launch_bounds__(512) void decode_i8_kernel(DecodeLaunch p,
     int ro;
     if (MSG_IN_LDS) {
         Rb = reinterpret_cast<uint16_t *>(smem) + N * Zh;
-        ro = slot * (slot_bytes / 2) + u;
+        ro = sl * (slot_bytes / 2) + u;
     } else {
-        Rb = reinterpret_cast<uint16_t *>(p.msg) + (size_t)blockIdx.x * p.cpw * E * Zh;
-        ro = slot * E * Zh + u;
+        Rb = bw.msg;
+        ro = sl * E * Zh + u;
     }
-    int *flags = reinterpret_cast<int *>(smem + p.cpw * slot_bytes);
+    int *flags = reinterpret_cast<int *>(smem + bw.slots * slot_bytes);
 
     // Initialisation: punctured columns 0 and 1 carry no channel LLR.
     if (valid) {
         Lw[u] = 0;
         Lw[Zh + u] = 0;
-        const int8_t *q = p.llr + (size_t)cw * T;
+        const int8_t *q = bw.llr + (size_t)slot * T;
 #pragma unroll 1
         for (int c = 2; c < N; ++c) {
             int lo = q[(c - 2) * Z + u], hi = q[(c - 2) * Z + u + Zh];
@@ -309,76 +309,112 @@ __global__ __launch_bounds__(512) void decode_i8_kernel(DecodeLaunch p,
     }
     __syncthreads();
 
-    const u16x2 off16 = {(unsigned short)(p.offset << 8), (unsigned short)(p.offset << 8)};
+    const u16x2 off16 = {(unsigned short)(bw.offset << 8), (unsigned short)(bw.offset << 8)};
     bool done = !valid;
-    int iters = p.max_iter, ok = 0;
-    for (int t = 1; t <= p.max_iter; ++t) {
-        int wt = p.beta;
-        const uint8_t *wrow = nullptr;
-        if (p.wq) wrow = p.wq + (size_t)((t < p.w_iters ? t : p.w_iters) - 1) * p.rows;
-        for (int r = 0; r < p.rows; ++r) {
+    int iters = bw.max_iter, ok = 0;
+    for (int t = 1; t <= bw.max_iter; ++t) {
+        int wt = bw.beta;
+        // weights through the constant address space: a scalar load per row
+        typedef const __attribute__((address_space(4))) uint8_t *cw8_t;
+        cw8_t wrow = nullptr;
+        if (bw.wq)
+            wrow = (cw8_t)(bw.wq + (size_t)((t < bw.w_iters ? t : bw.w_iters) - 1) * bw.w_stride);
+        for (int r = 0; r < bw.rows; ++r) {
             const int e0 = row_ptr[r], w = row_ptr[r + 1] - e0;
             if (wrow) wt = wrow[r];
             const u16x2 wgt = {(unsigned short)wt, (unsigned short)wt};
             if (!done) row_update<2, WMAX>(w, lb, Rb, ro, meta, e0, u, Zh, t == 1, wgt, off16);
             __syncthreads();
         }
-        if (p.early_exit || t == p.max_iter) {
-            if ((int)threadIdx.x < p.cpw) flags[threadIdx.x] = 0;
+        if (bw.early_exit || t == bw.max_iter) {
+            if ((int)threadIdx.x < bw.slots) flags[threadIdx.x] = 0;
             __syncthreads();
-            if (!done && syndrome_fails<WMAX>(lb, row_ptr, meta, p.rows, u, Zh))
+            if (!done && syndrome_fails<WMAX>(lb, row_ptr, meta, bw.rows, u, Zh))
                 atomicOr(&flags[slot], 1);
             __syncthreads();
-            const bool holds = flags[slot] == 0;
+            const bool holds = flags[sl] == 0;
             if (!done) {
-                if (p.early_exit && holds) {
+                if (bw.early_exit && holds) {
                     done = true;
                     iters = t;
                     ok = 1;
-                } else if (t == p.max_iter) {
+                } else if (t == bw.max_iter) {
                     ok = holds;
                 }
             }
-            if (p.early_exit && __syncthreads_and(done)) break;
+            if (bw.early_exit && __syncthreads_and(done)) break;
             __syncthreads();
         }
     }
-    if (!valid) return;
-
-    // Outputs: hard decisions of the K information bits packed LSB first.
-    // Byte j of a codeword covers bits 8j..8j+7, all in one block column
-    // since Z is a multiple of 8; lane u packs byte u of each column.
-    const uint8_t *Lb = reinterpret_cast<const uint8_t *>(Lw);
-    const int bytes_per_col = Z / 8;
-    uint8_t *ob = p.out_bits + (size_t)cw * (p.kb * bytes_per_col);
+    if (valid) {
+        // Outputs: hard decisions of the K information bits packed LSB
+        // first. Byte j of a codeword covers bits 8j..8j+7, all in one block
+        // column since Z is a multiple of 8; lane u packs byte u of each
+        // column.
+        const uint8_t *Lb = reinterpret_cast<const uint8_t *>(Lw);
+        const int bytes_per_col = Z / 8;
+        uint8_t *ob = bw.out_bits + (size_t)slot * (bw.kb * bytes_per_col);
 #pragma unroll 1
-    for (int c = 0; c < p.kb; ++c) {
+        for (int c = 0; c < bw.kb; ++c) {
 #pragma unroll 1
-        for (int j = u; j < bytes_per_col; j += Zh) {
-            uint32_t byte = 0;
+            for (int j = u; j < bytes_per_col; j += Zh) {
+                uint32_t byte = 0;
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int z = 8 * j + i;
-                const int hi = z >= Zh;
-                const int8_t L = (int8_t)Lb[2 * (c * Zh + z - hi * Zh) + hi];
-                byte |= (uint32_t)(L < 0) << i;
+                for (int i = 0; i < 8; ++i) {
+                    const int z = 8 * j + i;
+                    const int hi = z >= Zh;
+                    const int8_t L = (int8_t)Lb[2 * (c * Zh + z - hi * Zh) + hi];
+                    byte |= (uint32_t)(L < 0) << i;
+                }
+                ob[c * bytes_per_col + j] = (uint8_t)byte;
             }
-            ob[c * bytes_per_col + j] = (uint8_t)byte;
         }
-    }
-    if (u == 0) {
-        p.out_iters[cw] = iters;
-        if (p.out_ok) p.out_ok[cw] = (uint8_t)ok;
-    }
-    if (p.out_llr) {
-        int8_t *o = static_cast<int8_t *>(p.out_llr) + (size_t)cw * N * Z;
+        if (u == 0) {
+            bw.out_iters[slot] = iters;
+            if (bw.out_ok) bw.out_ok[slot] = (uint8_t)ok;
+        }
+        if (bw.out_llr) {
+            int8_t *o = bw.out_llr + (size_t)slot * N * Z;
 #pragma unroll 1
-        for (int c = 0; c < N; ++c) {
-            const uint16_t w = Lw[c * Zh + u];
-            o[c * Z + u] = (int8_t)(w & 0xFF);
-            o[c * Z + u + Zh] = (int8_t)(w >> 8);
+            for (int c = 0; c < N; ++c) {
+                const uint16_t w = Lw[c * Zh + u];
+                o[c * Z + u] = (int8_t)(w & 0xFF);
+                o[c * Z + u + Zh] = (int8_t)(w >> 8);
+            }
         }
     }
+}
+
+template <int WMAX, bool MSG_IN_LDS>
+__global__ __launch_bounds__(512) void decode_i8_kernel(DecodeLaunch p,
+                                                         const int32_t *__restrict__ row_ptr,
+                                                         const uint32_t *__restrict__ meta) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    const int Zh = p.Z >> 1, T = (p.n_cols - 2) * p.Z, first = blockIdx.x * p.cpw;
+    BlockWork bw;
+    bw.n = p.n_cw - first < p.cpw ? p.n_cw - first : p.cpw;
+    bw.slots = p.cpw;
+    bw.llr = p.llr + (size_t)first * T;
+    bw.out_bits = p.out_bits + (size_t)first * (p.kb * p.Z / 8);
+    bw.out_iters = p.out_iters + first;
+    bw.out_ok = p.out_ok ? p.out_ok + first : nullptr;
+    bw.out_llr = p.out_llr ? static_cast<int8_t *>(p.out_llr) + (size_t)first * p.n_cols * p.Z
+                           : nullptr;
+    bw.msg = MSG_IN_LDS ? nullptr
+                        : reinterpret_cast<uint16_t *>(p.msg) + (size_t)first * p.E * Zh;
+    bw.wq = p.wq;
+    bw.w_iters = p.w_iters;
+    bw.w_stride = p.rows;
+    bw.rows = p.rows;
+    bw.n_cols = p.n_cols;
+    bw.kb = p.kb;
+    bw.Z = p.Z;
+    bw.E = p.E;
+    bw.max_iter = p.max_iter;
+    bw.early_exit = p.early_exit;
+    bw.beta = p.beta;
+    bw.offset = p.offset;
+    decode_block<WMAX, MSG_IN_LDS>(bw, smem, (crow_t)row_ptr, (cmeta_t)meta);
 }
 
 template <int WMAX, bool MSG_IN_LDS>
@@ -414,10 +450,93 @@ hipError_t launch_placed(const DecodeLaunch &p, hipStream_t stream) {
     return launch_w<32, MSG_IN_LDS>(p, stream);
 }
 
+
+// Persistent mixed-shape decode: each workgroup takes tasks (up to a
+// workgroup's worth of codewords of one shape) from a device counter until
+// none are left, so every wave reaches the exit once the counter passes
+// n_tasks. Messages use the device placement with one region per
+// workgroup, reused from task to task.
+template <int WMAX>
+__global__ __launch_bounds__(256) void decode_batch_kernel(const BatchTask *__restrict__ tasks,
+                                                            const BatchJob *__restrict__ jobs,
+                                                            int n_tasks, unsigned *counter,
+                                                            uint16_t *msg_ws, int msg_per_block,
+                                                            int max_iter, int early_exit,
+                                                            int beta, int offset) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    __shared__ int task_id;
+    for (;;) {
+        if (threadIdx.x == 0) task_id = (int)atomicAdd(counter, 1u);
+        __syncthreads();
+        const int ti = task_id;
+        __syncthreads();
+        if (ti >= n_tasks) break;
+        const BatchTask tk = tasks[ti];
+        const BatchJob &jb = jobs[tk.job];
+        const int T = (jb.n_cols - 2) * jb.Z;
+        BlockWork bw;
+        bw.n = tk.n;
+        bw.slots = jb.slots;
+        bw.llr = jb.llr + (size_t)tk.first * T;
+        bw.out_bits = jb.out_bits + (size_t)tk.first * (jb.kb * jb.Z / 8);
+        bw.out_iters = jb.out_iters + tk.first;
+        bw.out_ok = jb.out_ok ? jb.out_ok + tk.first : nullptr;
+        bw.out_llr = nullptr;
+        bw.msg = msg_ws + (size_t)blockIdx.x * msg_per_block;
+        bw.wq = jb.wq;
+        bw.w_iters = jb.w_iters;
+        bw.w_stride = jb.w_stride;
+        bw.rows = jb.rows;
+        bw.n_cols = jb.n_cols;
+        bw.kb = jb.kb;
+        bw.Z = jb.Z;
+        bw.E = jb.E;
+        bw.max_iter = max_iter;
+        bw.early_exit = early_exit;
+        bw.beta = beta;
+        bw.offset = offset;
+        decode_block<WMAX, false>(bw, smem, (crow_t)jb.row_ptr, (cmeta_t)jb.meta);
+        __syncthreads();
+    }
+}
+
+__global__ void reset_counter_kernel(unsigned *counter) { *counter = 0u; }
+
 }  // namespace
 
 hipError_t launch_decode_i8(const DecodeLaunch &p, hipStream_t stream) {
     return p.msg ? launch_placed<false>(p, stream) : launch_placed<true>(p, stream);
+}
+
+hipError_t launch_decode_batch(const BatchLaunch &b, hipStream_t stream) {
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, stream, b.counter);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        note_hip_error("launch reset_counter_kernel", e);
+        return e;
+    }
+    static bool attr_set[2] = {false, false};
+    const void *fn = b.wmax <= 10 ? reinterpret_cast<const void *>(&decode_batch_kernel<10>)
+                                  : reinterpret_cast<const void *>(&decode_batch_kernel<20>);
+    bool &set = attr_set[b.wmax <= 10 ? 0 : 1];
+    if (!set) {
+        e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes());
+        if (e != hipSuccess) note_hip_error("hipFuncSetAttribute(decode_batch_kernel)", e);
+        set = true;
+    }
+    (void)hipGetLastError();
+    if (b.wmax <= 10)
+        hipLaunchKernelGGL(decode_batch_kernel<10>, dim3(b.grid), dim3(b.lanes), b.lds, stream,
+                           b.tasks, b.jobs, b.n_tasks, b.counter, b.msg, b.msg_per_block,
+                           b.max_iter, b.early_exit, b.beta, b.offset);
+    else
+        hipLaunchKernelGGL(decode_batch_kernel<20>, dim3(b.grid), dim3(b.lanes), b.lds, stream,
+                           b.tasks, b.jobs, b.n_tasks, b.counter, b.msg, b.msg_per_block,
+                           b.max_iter, b.early_exit, b.beta, b.offset);
+    e = hipGetLastError();
+    if (e != hipSuccess) note_hip_error("launch decode_batch_kernel", e);
+    return e;
 }
 
 }  // namespace ldpc

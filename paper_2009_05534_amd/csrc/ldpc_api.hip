@@ -2,6 +2,7 @@
 // registry (host copies plus lazily uploaded per-device tables), launch
 // configuration and error reporting. Declarations and contracts:
 // include/ldpc.h.
+#include <algorithm>
 #include <cstdio>
 #include <map>
 #include <mutex>
@@ -336,6 +337,100 @@ int ldpc_nwms_loss_grad(int bg, int Z, int rows, int n_cw, const float *llr,
     const hipError_t ef = hipFreeAsync(ws, stream_h);
     if (e != hipSuccess) return e == hipErrorOutOfMemory ? LDPC_ENOMEM : LDPC_EHIP;
     if (ef != hipSuccess) return hip_fail(ef, "hipFreeAsync(nwms workspace)");
+    return LDPC_OK;
+}
+
+struct ldpc_plan {
+    ldpc::Plan *p;
+};
+
+int ldpc_plan_create(const ldpc_job *jobs, int n_jobs, int max_iter, int early_exit, int flags,
+                     void *stream, ldpc_plan **out) {
+    if (!jobs || n_jobs < 1 || !out || max_iter < 1 || max_iter > LDPC_MAX_ITER) return LDPC_EINVAL;
+    constexpr int kLanes = 192;  // Z/2 lanes per codeword at the largest lift
+    std::vector<BatchJob> bj;
+    std::vector<int> job_cw;
+    int wmax = 0, lds_cap = 0;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        for (int j = 0; j < n_jobs; ++j) {
+            const ldpc_job &jb = jobs[j];
+            auto it = g_graphs.find({jb.bg, jb.Z});
+            if (it == g_graphs.end()) return LDPC_ENOGRAPH;
+            const HostGraph &g = it->second;
+            int E = 0;
+            if (jb.n_cw < 1 || !jb.llr || !jb.out_bits || !jb.out_iters || g.Z > 2 * kLanes ||
+                (jb.wq && jb.wq_iters < 1) ||
+                sub_sizes(g, jb.rows, nullptr, nullptr, nullptr, &E) != LDPC_OK)
+                return LDPC_EINVAL;
+            for (int r = 0; r < jb.rows; ++r)
+                wmax = std::max(wmax, (int)(g.row_ptr[r + 1] - g.row_ptr[r]));
+            DevTables *t = nullptr;
+            const int rc = tables_for(g, &t);
+            if (rc != LDPC_OK) return rc;
+            BatchJob b{};
+            b.llr = jb.llr;
+            b.out_bits = jb.out_bits;
+            b.out_iters = jb.out_iters;
+            b.out_ok = jb.out_ok;
+            b.row_ptr = t->row_ptr;
+            b.meta = t->meta;
+            b.wq = jb.wq;
+            b.w_iters = jb.wq ? jb.wq_iters : 0;
+            b.w_stride = jb.rows;
+            b.rows = jb.rows;
+            b.n_cols = g.kb + jb.rows;
+            b.kb = g.kb;
+            b.Z = g.Z;
+            b.E = E;
+            b.slots = std::max(1, kLanes / (g.Z / 2));
+            bj.push_back(b);
+            job_cw.push_back(jb.n_cw);
+        }
+        lds_cap = max_lds_bytes();
+    }
+    if (wmax > 20) return LDPC_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    ldpc::Plan *p = plan_new();
+    int rc = plan_build(p, bj, job_cw, kLanes, max_iter, early_exit ? 1 : 0, 96, 0, wmax,
+                        lds_cap, s);
+    if (rc == LDPC_OK && (flags & LDPC_PLAN_AUTOTUNE)) rc = plan_autotune(p, s);
+    if (rc == LDPC_OK && (flags & LDPC_PLAN_GRAPH)) rc = plan_capture(p);
+    if (rc != LDPC_OK) {
+        plan_destroy(p);
+        return rc;
+    }
+    *out = new ldpc_plan{p};
+    return LDPC_OK;
+}
+
+int ldpc_plan_launch(ldpc_plan *plan, void *stream) {
+    if (!plan || !plan->p) return LDPC_EINVAL;
+    return plan_launch(plan->p, static_cast<hipStream_t>(stream));
+}
+
+int ldpc_plan_info(const ldpc_plan *plan, int *grid, int *n_tasks, float *tuned_ms) {
+    if (!plan || !plan->p) return LDPC_EINVAL;
+    plan_info(plan->p, grid, n_tasks, tuned_ms);
+    return LDPC_OK;
+}
+
+void ldpc_plan_destroy(ldpc_plan *plan) {
+    if (!plan) return;
+    plan_destroy(plan->p);
+    delete plan;
+}
+
+int ldpc_decode_batch(const ldpc_job *jobs, int n_jobs, int max_iter, int early_exit,
+                      void *stream) {
+    ldpc_plan *plan = nullptr;
+    int rc = ldpc_plan_create(jobs, n_jobs, max_iter, early_exit, 0, stream, &plan);
+    if (rc != LDPC_OK) return rc;
+    rc = ldpc_plan_launch(plan, stream);
+    const hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+    ldpc_plan_destroy(plan);
+    if (rc != LDPC_OK) return rc;
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize(batch)");
     return LDPC_OK;
 }
 

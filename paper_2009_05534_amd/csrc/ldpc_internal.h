@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace ldpc {
 
 // Packed per-block metadata for the row-pair layout used by both kernels.
@@ -27,6 +29,12 @@ __host__ __device__ inline uint32_t pack_meta(int c, int s, int Zh) {
     return (uint32_t)(c * Zh + s_lo) | ((uint32_t)(Zh - s_lo) << 16) | ((uint32_t)(s / Zh) << 24);
 }
 
+// Graph tables as seen by the kernels: constant address space, so uniform
+// reads are scalar loads even when the pointer itself was loaded from a
+// device table (a generic pointer would give per-lane flat loads).
+typedef const __attribute__((address_space(4))) uint32_t *cmeta_t;
+typedef const __attribute__((address_space(4))) int32_t *crow_t;
+
 struct DecodeLaunch {
     const int8_t *llr;        // [n_cw][T]
     uint8_t *out_bits;        // [n_cw][K/8]
@@ -47,6 +55,61 @@ struct DecodeLaunch {
     int cpw;                  // codewords per workgroup
     int wmax;                 // max row weight over the kept rows
 };
+
+// A workgroup's share of an int8 decode: n codewords of one shape, each with
+// its own input, outputs and (device placement) message region.
+struct BlockWork {
+    const int8_t *llr;        // first codeword's LLRs, [n][T]
+    uint8_t *out_bits;        // [n][K/8]
+    int32_t *out_iters;       // [n]
+    uint8_t *out_ok;          // [n] or null
+    int8_t *out_llr;          // [n][Nc] or null
+    uint16_t *msg;            // [n][E][Z/2] pair words (device placement)
+    const uint8_t *wq;        // per-(iteration, row) weights or null
+    int w_iters, w_stride;    // weight rows and row stride
+    int n, slots;             // codewords here; codeword slots of the block
+    int rows, n_cols, kb, Z, E;
+    int max_iter, early_exit, beta, offset;
+};
+
+// Mixed-shape batch: one job per (shape, buffers), tasks of up to `slots`
+// codewords of one job.
+struct BatchJob {
+    const int8_t *llr;
+    uint8_t *out_bits;
+    int32_t *out_iters;
+    uint8_t *out_ok;
+    const int32_t *row_ptr;
+    const uint32_t *meta;
+    const uint8_t *wq;
+    int w_iters, w_stride;
+    int rows, n_cols, kb, Z, E, slots;
+};
+struct BatchTask {
+    int job, first, n, pad;
+};
+struct BatchLaunch {
+    const BatchTask *tasks;
+    const BatchJob *jobs;
+    int n_tasks;
+    unsigned *counter;
+    uint16_t *msg;            // grid * msg_per_block pair words
+    int msg_per_block;
+    int max_iter, early_exit, beta, offset;
+    int grid, lanes, lds, wmax;
+};
+hipError_t launch_decode_batch(const BatchLaunch &b, hipStream_t stream);
+
+struct Plan;
+int plan_build(Plan *p, const std::vector<BatchJob> &jobs, const std::vector<int> &job_cw,
+               int lanes, int max_iter, int early_exit, int beta, int offset, int wmax,
+               int lds_cap, hipStream_t stream);
+int plan_autotune(Plan *p, hipStream_t stream);
+int plan_capture(Plan *p);
+int plan_launch(Plan *p, hipStream_t stream);
+void plan_destroy(Plan *p);
+Plan *plan_new();
+void plan_info(const Plan *p, int *grid, int *n_tasks, float *tuned_ms);
 
 // Bytes of LDS one codeword needs in each kernel.
 __host__ __device__ inline int lds_bytes_i8(int n_cols, int E, int Z) { return (n_cols + E) * Z; }

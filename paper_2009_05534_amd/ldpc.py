@@ -43,8 +43,20 @@ class Args(ctypes.Structure):
     ]
 
 
+class Job(ctypes.Structure):
+    _fields_ = [
+        ("bg", ctypes.c_int), ("Z", ctypes.c_int), ("rows", ctypes.c_int), ("n_cw", ctypes.c_int),
+        ("llr", ctypes.c_void_p), ("out_bits", ctypes.c_void_p), ("out_iters", ctypes.c_void_p),
+        ("out_ok", ctypes.c_void_p), ("wq", ctypes.c_void_p), ("wq_iters", ctypes.c_int),
+    ]
+
+
+PLAN_GRAPH = 1
+PLAN_AUTOTUNE = 2
+
 EXPORTS = ("ldpc_set_graph", "ldpc_query", "ldpc_decode", "ldpc_args_init", "ldpc_decode_ex",
-           "ldpc_nwms_loss_grad", "ldpc_strerror", "ldpc_last_hip_error",
+           "ldpc_decode_batch", "ldpc_plan_create", "ldpc_plan_launch", "ldpc_plan_info",
+           "ldpc_plan_destroy", "ldpc_nwms_loss_grad", "ldpc_strerror", "ldpc_last_hip_error",
            "ldpc_last_error_message", "ldpc_shutdown")
 
 _lib = None
@@ -64,6 +76,13 @@ def lib():
         L.ldpc_args_init.argtypes = [ctypes.POINTER(Args)]
         L.ldpc_args_init.restype = None
         L.ldpc_decode_ex.argtypes = [ctypes.POINTER(Args)]
+        L.ldpc_decode_batch.argtypes = [ctypes.POINTER(Job), I, I, I, P]
+        L.ldpc_plan_create.argtypes = [ctypes.POINTER(Job), I, I, I, I, P,
+                                       ctypes.POINTER(ctypes.c_void_p)]
+        L.ldpc_plan_launch.argtypes = [P, P]
+        L.ldpc_plan_info.argtypes = [P, P, P, P]
+        L.ldpc_plan_destroy.argtypes = [P]
+        L.ldpc_plan_destroy.restype = None
         L.ldpc_nwms_loss_grad.argtypes = [I, I, I, I, P, P, I, P, ctypes.c_float, P, P, P, P]
         L.ldpc_strerror.argtypes = [I]
         L.ldpc_strerror.restype = ctypes.c_char_p
@@ -232,3 +251,87 @@ def nwms_loss_grad(llr, cbits, w, bg: int, Z: int, rows: int, *, scale: float = 
                                      grad.data_ptr(), out.data_ptr() if out is not None else None,
                                      _stream_ptr(stream)), "ldpc_nwms_loss_grad")
     return loss, grad, out
+
+
+class BatchJob:
+    """One job of a mixed-shape batch: codewords of one shape with their
+    device buffers (outputs allocated here unless given)."""
+
+    def __init__(self, llr, bg: int, Z: int, rows: int, weights=None, out_bits=None,
+                 out_iters=None, out_ok=None):
+        import torch
+        K, T, Nc, E = query(bg, Z, rows)
+        n = int(llr.shape[0])
+        _require(llr, (n, T), 1, "llr")
+        dev = llr.device
+        self.bg, self.Z, self.rows, self.n = bg, Z, rows, n
+        self.llr = llr
+        self.out_bits = out_bits if out_bits is not None else torch.empty(
+            (n, K // 8), dtype=torch.uint8, device=dev)
+        self.out_iters = out_iters if out_iters is not None else torch.empty(
+            n, dtype=torch.int32, device=dev)
+        self.out_ok = out_ok if out_ok is not None else torch.empty(n, dtype=torch.uint8,
+                                                                    device=dev)
+        _require(self.out_bits, (n, K // 8), 1, "out_bits")
+        _require(self.out_iters, (n,), 4, "out_iters")
+        _require(self.out_ok, (n,), 1, "out_ok")
+        self.weights = weights
+        if weights is not None:
+            if weights.dim() != 2 or weights.shape[1] != rows:
+                raise ValueError("weights must be [iters, rows]")
+            _require(weights, tuple(weights.shape), 1, "weights")
+
+    def c_struct(self) -> Job:
+        return Job(self.bg, self.Z, self.rows, self.n, self.llr.data_ptr(),
+                   self.out_bits.data_ptr(), self.out_iters.data_ptr(), self.out_ok.data_ptr(),
+                   self.weights.data_ptr() if self.weights is not None else None,
+                   int(self.weights.shape[0]) if self.weights is not None else 0)
+
+
+def _job_array(jobs):
+    arr = (Job * len(jobs))()
+    for i, j in enumerate(jobs):
+        arr[i] = j.c_struct()
+    return arr
+
+
+def decode_batch(jobs, *, max_iter: int = 10, early_exit: bool = True, stream=None) -> None:
+    """One persistent launch over all jobs; waits for the stream."""
+    arr = _job_array(jobs)
+    _check(lib().ldpc_decode_batch(arr, len(jobs), max_iter, int(early_exit), _stream_ptr(stream)),
+           "ldpc_decode_batch")
+
+
+class Plan:
+    """Reusable mixed-shape plan bound to the jobs' buffers; optionally a HIP
+    graph and autotuned grid (see include/ldpc.h)."""
+
+    def __init__(self, jobs, *, max_iter: int = 10, early_exit: bool = True, graph: bool = False,
+                 autotune: bool = False, stream=None):
+        self.jobs = list(jobs)  # keeps the tensors alive
+        arr = _job_array(self.jobs)
+        h = ctypes.c_void_p()
+        flags = (PLAN_GRAPH if graph else 0) | (PLAN_AUTOTUNE if autotune else 0)
+        _check(lib().ldpc_plan_create(arr, len(self.jobs), max_iter, int(early_exit), flags,
+                                      _stream_ptr(stream), ctypes.byref(h)), "ldpc_plan_create")
+        self._h = h
+
+    def launch(self, stream=None) -> None:
+        _check(lib().ldpc_plan_launch(self._h, _stream_ptr(stream)), "ldpc_plan_launch")
+
+    def info(self) -> dict:
+        g, n, t = ctypes.c_int(), ctypes.c_int(), ctypes.c_float()
+        _check(lib().ldpc_plan_info(self._h, ctypes.byref(g), ctypes.byref(n), ctypes.byref(t)),
+               "ldpc_plan_info")
+        return {"grid": g.value, "n_tasks": n.value, "tuned_ms": t.value}
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().ldpc_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

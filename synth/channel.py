@@ -53,13 +53,15 @@ def info_bits(g: BaseGraph, data_seed: int, idx: np.ndarray) -> np.ndarray:
 
 
 def make_batch(g: BaseGraph, n_cw: int, ebn0_db, data_seed: int, start: int = 0,
-               encoder: ElimEncoder | None = None) -> Batch:
-    """Codewords start..start+n_cw-1 of data seed ``data_seed``.
+               encoder: ElimEncoder | None = None, indices=None) -> Batch:
+    """Codewords start..start+n_cw-1 (or the given ``indices``) of data seed
+    ``data_seed``.
 
     ``ebn0_db`` is a scalar or one value per codeword. The information bits
     and the noise of codeword i are drawn, in that order, from stream i.
     """
-    idx = np.arange(start, start + n_cw)
+    idx = np.arange(start, start + n_cw) if indices is None else np.asarray(indices)
+    n_cw = len(idx)
     ebn0 = np.broadcast_to(np.asarray(ebn0_db, dtype=np.float64), (n_cw,)).copy()
     u = np.empty((n_cw, g.K), dtype=np.uint8)
     noise = np.empty((n_cw, g.T), dtype=np.float64)

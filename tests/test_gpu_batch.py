@@ -1,0 +1,93 @@
+"""Mixed-shape persistent batch decode, plans, graph replay and autotuning:
+every job's results equal decoding it alone and the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from synth import make_graph
+from synth.mixed import make_mixed
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2009_05534_amd import ldpc
+    for bg in (1, 2):
+        for Z in (16, 32, 64, 96, 128, 192, 256, 384):
+            ldpc.register(make_graph(bg, Z))
+    return ldpc
+
+
+def _jobs(ldpc, groups):
+    return [ldpc.BatchJob(torch.from_numpy(gr.batch.q).cuda(), gr.bg, gr.Z, gr.rows)
+            for gr in groups]
+
+
+def _alone(ldpc, gr, **kw):
+    bits, iters, ok, _ = ldpc.decode(torch.from_numpy(gr.batch.q).cuda(), gr.bg, gr.Z, gr.rows,
+                                     msg_placement="device", **kw)
+    return bits.cpu().numpy(), iters.cpu().numpy(), ok.cpu().numpy()
+
+
+def test_mixed_batch_equals_alone_and_oracle(lib):
+    groups = make_mixed(300, 1.5, seed=3)
+    assert len(groups) > 20
+    jobs = _jobs(lib, groups)
+    lib.decode_batch(jobs)
+    for gr, jb in zip(groups, jobs):
+        got = (jb.out_bits.cpu().numpy(), jb.out_iters.cpu().numpy(),
+               jb.out_ok.cpu().numpy().astype(bool))
+        alone = _alone(lib, gr)
+        for a, b in zip(got, alone):
+            assert (a == b).all(), (gr.bg, gr.Z, gr.rows)
+        g = make_graph(gr.bg, gr.Z, gr.rows)
+        ref = oracle.decode_i8(g, gr.batch.q, n_threads=4)
+        for a, b in zip(got, ref[:3]):
+            assert (a == b).all(), (gr.bg, gr.Z, gr.rows)
+
+
+def test_plan_graph_replays_match_eager(lib):
+    from synth import make_batch
+    groups = make_mixed(120, 1.75, seed=12)
+    jobs = _jobs(lib, groups)
+    plan = lib.Plan(jobs, graph=True, autotune=True)
+    info = plan.info()
+    assert info["grid"] >= 1 and info["n_tasks"] >= len(groups) and info["tuned_ms"] > 0
+    for rep in range(3):
+        # refill every job's input buffer in place with fresh data of its shape
+        qs = []
+        for gr, jb in zip(groups, jobs):
+            g = make_graph(gr.bg, gr.Z, gr.rows)
+            q = make_batch(g, jb.n, 1.75, data_seed=100 + rep, indices=gr.indices).q
+            jb.llr.copy_(torch.from_numpy(q))
+            qs.append(q)
+        plan.launch()
+        torch.cuda.synchronize()
+        _ = torch.ones(1000, device="cuda").sum().item()  # eager work between replays
+        for gr, jb, q in zip(groups, jobs, qs):
+            bits, iters, ok, _ = lib.decode(torch.from_numpy(q).cuda(), gr.bg, gr.Z, gr.rows)
+            assert (jb.out_bits.cpu() == bits.cpu()).all(), (rep, gr.bg, gr.Z, gr.rows)
+            assert (jb.out_iters.cpu() == iters.cpu()).all(), (rep, gr.bg, gr.Z, gr.rows)
+    plan.close()
+
+
+def test_batch_with_learned_weights(lib):
+    groups = [g for g in make_mixed(200, 1.5, seed=15) if g.bg == 1][:6]
+    rng = np.random.default_rng(9)
+    jobs = []
+    ws = []
+    for gr in groups:
+        w = rng.integers(64, 128, (3, gr.rows)).astype(np.uint8)
+        ws.append(w)
+        jobs.append(lib.BatchJob(torch.from_numpy(gr.batch.q).cuda(), gr.bg, gr.Z, gr.rows,
+                                 weights=torch.from_numpy(w).cuda()))
+    lib.decode_batch(jobs)
+    for gr, jb, w in zip(groups, jobs, ws):
+        g = make_graph(gr.bg, gr.Z, gr.rows)
+        ref = oracle.decode_i8(g, gr.batch.q, wq=w, n_threads=4)
+        assert (jb.out_bits.cpu().numpy() == ref[0]).all()
+        assert (jb.out_iters.cpu().numpy() == ref[1]).all()
