@@ -29,6 +29,7 @@
 #ifndef LDPC_MI355X_H
 #define LDPC_MI355X_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -174,6 +175,13 @@ typedef struct ldpc_job {
  * waits for the stream, and releases the plan. */
 int ldpc_decode_batch(const ldpc_job *jobs, int n_jobs, int max_iter, int early_exit,
                       void *stream);
+
+/* Asynchronous one-shot batch: the job tables, task queue and message
+ * regions are allocated, used and released in stream order on `stream`;
+ * the call returns without waiting. *bytes_in_flight (may be NULL) receives
+ * the device memory the launch holds until it completes. */
+int ldpc_decode_batch_async(const ldpc_job *jobs, int n_jobs, int max_iter, int early_exit,
+                            void *stream, size_t *bytes_in_flight);
 
 /* A reusable plan bound to the jobs' buffers (refill the inputs and launch
  * again). Flags: LDPC_PLAN_GRAPH captures the launch (a counter-reset

@@ -188,6 +188,77 @@ int plan_launch(Plan *p, hipStream_t stream) {
 
 void plan_destroy(Plan *p) { free_plan(p); }
 
+// One launch over `jobs` with every buffer stream-ordered on `stream`: the
+// tables and message regions are allocated with hipMallocAsync, filled,
+// used by the persistent kernel and released, all without blocking the
+// host. Returns the device bytes the launch holds while in flight.
+int batch_async(const std::vector<BatchJob> &jobs, const std::vector<int> &job_cw, int lanes,
+                int max_iter, int early_exit, int wmax, int lds_cap, hipStream_t stream,
+                size_t *bytes_in_flight) {
+    std::vector<BatchTask> tasks;
+    int lds = 0, msg_per_block = 0;
+    for (size_t j = 0; j < jobs.size(); ++j) {
+        const BatchJob &jb = jobs[j];
+        lds = std::max(lds, jb.slots * lds_bytes_i8_post(jb.n_cols, jb.Z) +
+                                jb.slots * (int)sizeof(int));
+        msg_per_block = std::max(msg_per_block, jb.slots * jb.E * (jb.Z / 2));
+        for (int f = 0; f < job_cw[j]; f += jb.slots)
+            tasks.push_back(BatchTask{(int)j, f, std::min(jb.slots, job_cw[j] - f), 0});
+    }
+    if (lds > lds_cap || tasks.empty()) return LDPC_EINVAL;
+    std::stable_sort(tasks.begin(), tasks.end(), [&](const BatchTask &a, const BatchTask &b) {
+        const BatchJob &x = jobs[a.job], &y = jobs[b.job];
+        return (long)x.E * x.Z > (long)y.E * y.Z;
+    });
+    int dev = 0, cus = 1;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int per_cu = std::max(1, std::min(8, lds_cap / std::max(lds, 1)));
+    const int grid = std::max(1, std::min((int)tasks.size(), std::max(cus, 1) * per_cu));
+    const size_t tb = sizeof(BatchTask) * tasks.size(), jbytes = sizeof(BatchJob) * jobs.size();
+    const size_t mbytes = (size_t)grid * msg_per_block * sizeof(uint16_t);
+    const size_t total = tb + jbytes + 256 + mbytes;
+    uint8_t *buf = nullptr;
+    hipError_t e = hipMallocAsync(reinterpret_cast<void **>(&buf), total, stream);
+    if (e != hipSuccess) {
+        note_hip_error("hipMallocAsync(batch)", e);
+        return e == hipErrorOutOfMemory ? LDPC_ENOMEM : LDPC_EHIP;
+    }
+    BatchLaunch b{};
+    b.tasks = reinterpret_cast<BatchTask *>(buf);
+    b.jobs = reinterpret_cast<BatchJob *>(buf + tb);
+    b.counter = reinterpret_cast<unsigned *>(buf + tb + jbytes);
+    b.msg = reinterpret_cast<uint16_t *>(buf + tb + jbytes + 256);
+    b.n_tasks = (int)tasks.size();
+    b.msg_per_block = msg_per_block;
+    b.max_iter = max_iter;
+    b.early_exit = early_exit;
+    b.beta = 96;
+    b.offset = 0;
+    b.grid = grid;
+    b.lanes = lanes;
+    b.lds = lds;
+    b.wmax = wmax;
+    // pageable sources: the runtime has staged them when the calls return
+    e = hipMemcpyAsync(const_cast<BatchTask *>(b.tasks), tasks.data(), tb, hipMemcpyHostToDevice,
+                       stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(const_cast<BatchJob *>(b.jobs), jobs.data(), jbytes,
+                           hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = launch_decode_batch(b, stream);
+    const hipError_t ef = hipFreeAsync(buf, stream);
+    if (e != hipSuccess) {
+        note_hip_error("batch_async", e);
+        return LDPC_EHIP;
+    }
+    if (ef != hipSuccess) {
+        note_hip_error("hipFreeAsync(batch)", ef);
+        return LDPC_EHIP;
+    }
+    if (bytes_in_flight) *bytes_in_flight = total;
+    return LDPC_OK;
+}
+
 Plan *plan_new() { return new Plan(); }
 
 void plan_info(const Plan *p, int *grid, int *n_tasks, float *tuned_ms) {

@@ -344,51 +344,62 @@ struct ldpc_plan {
     ldpc::Plan *p;
 };
 
+namespace {
+constexpr int kBatchLanes = 192;  // Z/2 lanes per codeword at the largest lift
+
+// Device job table entries for `jobs` (registered graphs, kept rows).
+int batch_jobs(const ldpc_job *jobs, int n_jobs, std::vector<BatchJob> &bj,
+               std::vector<int> &job_cw, int &wmax, int &lds_cap) {
+    wmax = 0;
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (int j = 0; j < n_jobs; ++j) {
+        const ldpc_job &jb = jobs[j];
+        auto it = g_graphs.find({jb.bg, jb.Z});
+        if (it == g_graphs.end()) return LDPC_ENOGRAPH;
+        const HostGraph &g = it->second;
+        int E = 0;
+        if (jb.n_cw < 1 || !jb.llr || !jb.out_bits || !jb.out_iters || g.Z > 2 * kBatchLanes ||
+            (jb.wq && jb.wq_iters < 1) ||
+            sub_sizes(g, jb.rows, nullptr, nullptr, nullptr, &E) != LDPC_OK)
+            return LDPC_EINVAL;
+        for (int r = 0; r < jb.rows; ++r)
+            wmax = std::max(wmax, (int)(g.row_ptr[r + 1] - g.row_ptr[r]));
+        DevTables *t = nullptr;
+        const int rc = tables_for(g, &t);
+        if (rc != LDPC_OK) return rc;
+        BatchJob b{};
+        b.llr = jb.llr;
+        b.out_bits = jb.out_bits;
+        b.out_iters = jb.out_iters;
+        b.out_ok = jb.out_ok;
+        b.row_ptr = t->row_ptr;
+        b.meta = t->meta;
+        b.wq = jb.wq;
+        b.w_iters = jb.wq ? jb.wq_iters : 0;
+        b.w_stride = jb.rows;
+        b.rows = jb.rows;
+        b.n_cols = g.kb + jb.rows;
+        b.kb = g.kb;
+        b.Z = g.Z;
+        b.E = E;
+        b.slots = std::max(1, kBatchLanes / (g.Z / 2));
+        bj.push_back(b);
+        job_cw.push_back(jb.n_cw);
+    }
+    lds_cap = max_lds_bytes();
+    return wmax > 20 ? LDPC_EINVAL : LDPC_OK;
+}
+}  // namespace
+
 int ldpc_plan_create(const ldpc_job *jobs, int n_jobs, int max_iter, int early_exit, int flags,
                      void *stream, ldpc_plan **out) {
     if (!jobs || n_jobs < 1 || !out || max_iter < 1 || max_iter > LDPC_MAX_ITER) return LDPC_EINVAL;
-    constexpr int kLanes = 192;  // Z/2 lanes per codeword at the largest lift
+    constexpr int kLanes = kBatchLanes;
     std::vector<BatchJob> bj;
     std::vector<int> job_cw;
     int wmax = 0, lds_cap = 0;
-    {
-        std::lock_guard<std::mutex> lk(g_mu);
-        for (int j = 0; j < n_jobs; ++j) {
-            const ldpc_job &jb = jobs[j];
-            auto it = g_graphs.find({jb.bg, jb.Z});
-            if (it == g_graphs.end()) return LDPC_ENOGRAPH;
-            const HostGraph &g = it->second;
-            int E = 0;
-            if (jb.n_cw < 1 || !jb.llr || !jb.out_bits || !jb.out_iters || g.Z > 2 * kLanes ||
-                (jb.wq && jb.wq_iters < 1) ||
-                sub_sizes(g, jb.rows, nullptr, nullptr, nullptr, &E) != LDPC_OK)
-                return LDPC_EINVAL;
-            for (int r = 0; r < jb.rows; ++r)
-                wmax = std::max(wmax, (int)(g.row_ptr[r + 1] - g.row_ptr[r]));
-            DevTables *t = nullptr;
-            const int rc = tables_for(g, &t);
-            if (rc != LDPC_OK) return rc;
-            BatchJob b{};
-            b.llr = jb.llr;
-            b.out_bits = jb.out_bits;
-            b.out_iters = jb.out_iters;
-            b.out_ok = jb.out_ok;
-            b.row_ptr = t->row_ptr;
-            b.meta = t->meta;
-            b.wq = jb.wq;
-            b.w_iters = jb.wq ? jb.wq_iters : 0;
-            b.w_stride = jb.rows;
-            b.rows = jb.rows;
-            b.n_cols = g.kb + jb.rows;
-            b.kb = g.kb;
-            b.Z = g.Z;
-            b.E = E;
-            b.slots = std::max(1, kLanes / (g.Z / 2));
-            bj.push_back(b);
-            job_cw.push_back(jb.n_cw);
-        }
-        lds_cap = max_lds_bytes();
-    }
+    const int rcj = batch_jobs(jobs, n_jobs, bj, job_cw, wmax, lds_cap);
+    if (rcj != LDPC_OK) return rcj;
     if (wmax > 20) return LDPC_EINVAL;
     hipStream_t s = static_cast<hipStream_t>(stream);
     ldpc::Plan *p = plan_new();
@@ -419,6 +430,18 @@ void ldpc_plan_destroy(ldpc_plan *plan) {
     if (!plan) return;
     plan_destroy(plan->p);
     delete plan;
+}
+
+int ldpc_decode_batch_async(const ldpc_job *jobs, int n_jobs, int max_iter, int early_exit,
+                            void *stream, size_t *bytes_in_flight) {
+    if (!jobs || n_jobs < 1 || max_iter < 1 || max_iter > LDPC_MAX_ITER) return LDPC_EINVAL;
+    std::vector<BatchJob> bj;
+    std::vector<int> job_cw;
+    int wmax = 0, lds_cap = 0;
+    const int rc = batch_jobs(jobs, n_jobs, bj, job_cw, wmax, lds_cap);
+    if (rc != LDPC_OK) return rc;
+    return batch_async(bj, job_cw, kBatchLanes, max_iter, early_exit ? 1 : 0, wmax, lds_cap,
+                       static_cast<hipStream_t>(stream), bytes_in_flight);
 }
 
 int ldpc_decode_batch(const ldpc_job *jobs, int n_jobs, int max_iter, int early_exit,

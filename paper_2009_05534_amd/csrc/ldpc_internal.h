@@ -110,6 +110,9 @@ int plan_launch(Plan *p, hipStream_t stream);
 void plan_destroy(Plan *p);
 Plan *plan_new();
 void plan_info(const Plan *p, int *grid, int *n_tasks, float *tuned_ms);
+int batch_async(const std::vector<BatchJob> &jobs, const std::vector<int> &job_cw, int lanes,
+                int max_iter, int early_exit, int wmax, int lds_cap, hipStream_t stream,
+                size_t *bytes_in_flight);
 
 // Bytes of LDS one codeword needs in each kernel.
 __host__ __device__ inline int lds_bytes_i8(int n_cols, int E, int Z) { return (n_cols + E) * Z; }

@@ -55,7 +55,7 @@ PLAN_GRAPH = 1
 PLAN_AUTOTUNE = 2
 
 EXPORTS = ("ldpc_set_graph", "ldpc_query", "ldpc_decode", "ldpc_args_init", "ldpc_decode_ex",
-           "ldpc_decode_batch", "ldpc_plan_create", "ldpc_plan_launch", "ldpc_plan_info",
+           "ldpc_decode_batch", "ldpc_decode_batch_async", "ldpc_plan_create", "ldpc_plan_launch", "ldpc_plan_info",
            "ldpc_plan_destroy", "ldpc_nwms_loss_grad", "ldpc_strerror", "ldpc_last_hip_error",
            "ldpc_last_error_message", "ldpc_shutdown")
 
@@ -77,6 +77,8 @@ def lib():
         L.ldpc_args_init.restype = None
         L.ldpc_decode_ex.argtypes = [ctypes.POINTER(Args)]
         L.ldpc_decode_batch.argtypes = [ctypes.POINTER(Job), I, I, I, P]
+        L.ldpc_decode_batch_async.argtypes = [ctypes.POINTER(Job), I, I, I, P,
+                                              ctypes.POINTER(ctypes.c_size_t)]
         L.ldpc_plan_create.argtypes = [ctypes.POINTER(Job), I, I, I, I, P,
                                        ctypes.POINTER(ctypes.c_void_p)]
         L.ldpc_plan_launch.argtypes = [P, P]
@@ -300,6 +302,19 @@ def decode_batch(jobs, *, max_iter: int = 10, early_exit: bool = True, stream=No
     arr = _job_array(jobs)
     _check(lib().ldpc_decode_batch(arr, len(jobs), max_iter, int(early_exit), _stream_ptr(stream)),
            "ldpc_decode_batch")
+
+
+def decode_batch_async(jobs, *, max_iter: int = 10, early_exit: bool = True,
+                       stream=None) -> int:
+    """One persistent launch over all jobs, enqueued on `stream` without
+    waiting; returns the device bytes the launch holds until it completes.
+    The caller keeps the jobs' tensors alive until then."""
+    arr = _job_array(jobs)
+    nb = ctypes.c_size_t()
+    _check(lib().ldpc_decode_batch_async(arr, len(jobs), max_iter, int(early_exit),
+                                         _stream_ptr(stream), ctypes.byref(nb)),
+           "ldpc_decode_batch_async")
+    return int(nb.value)
 
 
 class Plan:

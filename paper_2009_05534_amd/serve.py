@@ -1,0 +1,231 @@
+"""Continuous-batching decode server for transport blocks.
+
+A transport block is 1..8 codewords of one shape (bg, Z, rows); blocks
+arrive as a Poisson process. Their int8 LLRs sit in device memory from
+arrival on (the device-resident input queue). The server keeps up to
+`n_slots` decode launches in flight, each on its own stream: whenever a slot
+is free and blocks are waiting, it admits waiting blocks in earliest-deadline
+order for as long as the device-memory budget for check-to-variable
+messages allows, and launches them as ONE persistent mixed-shape decode
+(ldpc.decode_batch_async). Blocks that arrive while other launches run are
+admitted as soon as a slot and memory free up, so their work overlaps on the
+device. BG1 blocks are decoded with the learned per-(iteration, row) weights
+when given; codewords whose checks fail are decoded again with plain
+normalised min-sum (beta = 3/4) as the fallback. A block's latency runs from
+its arrival to the host seeing its last launch complete.
+"""
+from __future__ import annotations
+
+import dataclasses
+import time
+
+import numpy as np
+
+from synth import LIFTS, full_shape, make_batch, make_graph
+from synth.prng import stream
+
+DEADLINE_S = 0.5e-3
+
+
+@dataclasses.dataclass
+class Block:
+    id: int
+    arrival: float          # seconds from the start of the trace
+    bg: int
+    Z: int
+    rows: int
+    n_cw: int
+    ebn0: float
+    q: np.ndarray           # int8 [n_cw, T]
+    u: np.ndarray           # uint8 [n_cw, K] information bits
+    # filled by the server
+    t_done: float = -1.0
+    fallback: bool = False
+    bits: np.ndarray | None = None
+    iters: np.ndarray | None = None
+    ok: np.ndarray | None = None
+
+
+def make_trace(n_blocks: int, seed: int = 6, lifts=LIFTS, min_cw: int = 1,
+               max_cw: int = 8) -> list[Block]:
+    """Blocks with unit-rate exponential gaps (scale them with rescale());
+    shapes drawn as in the mixed batch, Eb/N0 uniform in [1, 2] dB."""
+    gaps = stream(seed, 21, 0).exponential(1.0, n_blocks)
+    t = np.cumsum(gaps)
+    blocks = []
+    for i in range(n_blocks):
+        s = stream(seed, 22, i)
+        bg = int(s.integers(1, 3))
+        Z = int(lifts[int(s.integers(0, len(lifts)))])
+        rows = int(s.integers(4, full_shape(bg)[0] + 1))
+        n_cw = int(s.integers(min_cw, max_cw + 1))
+        ebn0 = float(s.uniform(1.0, 2.0))
+        g = make_graph(bg, Z, rows)
+        b = make_batch(g, n_cw, ebn0, seed, indices=np.arange(8 * i, 8 * i + n_cw))
+        blocks.append(Block(i, float(t[i]), bg, Z, rows, n_cw, ebn0, b.q, b.u))
+    return blocks
+
+
+def rescale(blocks: list[Block], rate_hz: float) -> list[Block]:
+    """Copies of the blocks with arrival times for an offered load of
+    rate_hz blocks per second."""
+    return [dataclasses.replace(b, arrival=b.arrival / rate_hz, t_done=-1.0, bits=None,
+                                iters=None, ok=None, fallback=False) for b in blocks]
+
+
+def message_bytes(bg: int, Z: int, rows: int, n_cw: int) -> int:
+    """Device bytes of int8 messages a block needs while it is decoded."""
+    from . import ldpc
+    _, _, _, E = ldpc.query(bg, Z, rows)
+    return n_cw * E * Z
+
+
+class Server:
+    def __init__(self, weights_bg1: np.ndarray | None = None, n_slots: int = 4,
+                 mem_budget: int = 256 << 20, max_iter: int = 10, max_blocks_per_launch: int = 256,
+                 device: str = "cuda:0"):
+        import torch
+        from . import ldpc
+        self.ldpc = ldpc
+        self.torch = torch
+        self.dev = torch.device(device)
+        self.n_slots = n_slots
+        self.mem_budget = mem_budget
+        self.max_iter = max_iter
+        self.max_blocks = max_blocks_per_launch
+        self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(n_slots)]
+        self._w_full = None if weights_bg1 is None else np.ascontiguousarray(weights_bg1, np.uint8)
+        self._w_dev: dict[int, object] = {}
+
+    def _weights(self, bg: int, rows: int):
+        if self._w_full is None or bg != 1:
+            return None
+        if rows not in self._w_dev:
+            w = np.ascontiguousarray(self._w_full[:, :rows])
+            self._w_dev[rows] = self.torch.from_numpy(w).to(self.dev)
+        return self._w_dev[rows]
+
+    def _prepare(self, blocks):
+        torch, ldpc = self.torch, self.ldpc
+        for b in blocks:
+            b._llr = torch.from_numpy(b.q).to(self.dev)
+            K = b.u.shape[1]
+            b._bits = torch.empty((b.n_cw, K // 8), dtype=torch.uint8, device=self.dev)
+            b._iters = torch.empty(b.n_cw, dtype=torch.int32, device=self.dev)
+            b._ok = torch.empty(b.n_cw, dtype=torch.uint8, device=self.dev)
+            b._ok_host = torch.empty(b.n_cw, dtype=torch.uint8, pin_memory=True)
+            b._mem = message_bytes(b.bg, b.Z, b.rows, b.n_cw)
+            if b._mem > self.mem_budget:
+                raise ValueError(f"block {b.id} needs more message memory than the budget")
+        torch.cuda.synchronize(self.dev)
+        del ldpc
+
+    def _jobs(self, batch, plain: bool):
+        ldpc = self.ldpc
+        jobs = []
+        for b in batch:
+            w = None if plain else self._weights(b.bg, b.rows)
+            jobs.append(ldpc.BatchJob(b._llr, b.bg, b.Z, b.rows, weights=w, out_bits=b._bits,
+                                      out_iters=b._iters, out_ok=b._ok))
+        return jobs
+
+    def run(self, blocks: list[Block]) -> dict:
+        """Serve the trace in real time; returns latency/throughput stats."""
+        torch = self.torch
+        self._prepare(blocks)
+        order = sorted(blocks, key=lambda b: b.arrival)
+        pending: list[Block] = []      # arrived, waiting for a slot
+        fallback: list[Block] = []     # learned pass failed, waiting for plain pass
+        in_flight: list[tuple] = []    # (slot, event, batch, plain, mem)
+        free_slots = list(range(self.n_slots))
+        mem_used = 0
+        nxt = 0
+        done = 0
+        launches = 0
+        t0 = time.perf_counter()
+        while done < len(order):
+            now = time.perf_counter() - t0
+            while nxt < len(order) and order[nxt].arrival <= now:
+                pending.append(order[nxt])
+                nxt += 1
+            # completions
+            still = []
+            for slot, ev, batch, plain, mem in in_flight:
+                if ev.query():
+                    t_done = time.perf_counter() - t0
+                    free_slots.append(slot)
+                    mem_used -= mem
+                    for b in batch:
+                        # the flags were copied to pinned memory on the
+                        # launch's stream before its event: no device sync
+                        ok = b._ok_host.numpy().astype(bool)
+                        if not plain and self._weights(b.bg, b.rows) is not None and not ok.all():
+                            b.fallback = True
+                            fallback.append(b)
+                        else:
+                            b.t_done = t_done
+                            done += 1
+                else:
+                    still.append((slot, ev, batch, plain, mem))
+            in_flight = still
+            # admissions: fallback passes first, then new blocks by deadline
+            for queue, plain in ((fallback, True), (pending, False)):
+                while free_slots and queue:
+                    queue.sort(key=lambda b: b.arrival)  # earliest deadline first
+                    batch, mem = [], 0
+                    while (queue and len(batch) < self.max_blocks
+                           and mem_used + mem + queue[0]._mem <= self.mem_budget):
+                        b = queue.pop(0)
+                        batch.append(b)
+                        mem += b._mem
+                    if not batch:
+                        break
+                    slot = free_slots.pop()
+                    st = self.streams[slot]
+                    self.ldpc.decode_batch_async(self._jobs(batch, plain), max_iter=self.max_iter,
+                                                 stream=st)
+                    with torch.cuda.stream(st):
+                        for b in batch:
+                            b._ok_host.copy_(b._ok, non_blocking=True)
+                    ev = torch.cuda.Event()
+                    ev.record(st)
+                    in_flight.append((slot, ev, batch, plain, mem))
+                    mem_used += mem
+                    launches += 1
+        t_end = time.perf_counter() - t0
+        torch.cuda.synchronize(self.dev)
+        for b in order:
+            b.bits = b._bits.cpu().numpy()
+            b.iters = b._iters.cpu().numpy()
+            b.ok = b._ok.cpu().numpy().astype(bool)
+        lat = np.array([b.t_done - b.arrival for b in order])
+        bits = sum(b.u.shape[0] * b.u.shape[1] for b in order)
+        errs = sum(int((np.unpackbits(b.bits, axis=1, bitorder="little")[:, :b.u.shape[1]] != b.u)
+                       .any(axis=1).sum()) for b in order)
+        return {
+            "blocks": len(order),
+            "codewords": int(sum(b.n_cw for b in order)),
+            "launches": launches,
+            "offered_blocks_per_s": len(order) / max(order[-1].arrival, 1e-9),
+            "gbps": bits / t_end / 1e9,
+            "latency_ms_p50": float(np.percentile(lat, 50) * 1e3),
+            "latency_ms_p99": float(np.percentile(lat, 99) * 1e3),
+            "deadline_met": float(np.mean(lat <= DEADLINE_S)),
+            "fallback_blocks": int(sum(b.fallback for b in order)),
+            "codeword_error_rate": errs / max(1, sum(b.n_cw for b in order)),
+            "seconds": t_end,
+        }
+
+    def decode_alone(self, b: Block) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
+        """The same policy on one block by itself (learned pass, plain pass
+        for failures), for checking results against the mixed run."""
+        ldpc, torch = self.ldpc, self.torch
+        llr = torch.from_numpy(b.q).to(self.dev)
+        w = self._weights(b.bg, b.rows)
+        bits, iters, ok, _ = ldpc.decode(llr, b.bg, b.Z, b.rows, max_iter=self.max_iter,
+                                         weights=w, msg_placement="device")
+        if w is not None and not bool(ok.all()):
+            bits, iters, ok, _ = ldpc.decode(llr, b.bg, b.Z, b.rows, max_iter=self.max_iter,
+                                             msg_placement="device")
+        torch.cuda.synchronize(self.dev)
+        return bits.cpu().numpy(), iters.cpu().numpy(), ok.cpu().numpy().astype(bool)
