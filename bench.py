@@ -203,6 +203,44 @@ def main():
         result["latency_ms"]["single_codeword_us_per_iter_p50"] = round(
             float(np.percentile(ts, 50)) * 1e3 / 10, 2)
 
+    if not args.no_extras:
+        # Mixed-shape batch: 2048 codewords, (bg, Z, rows) drawn per codeword,
+        # one persistent launch, captured as a HIP graph with an autotuned grid.
+        from synth.mixed import make_mixed
+        from synth import LIFTS
+        for bgx in (1, 2):
+            for Zx in LIFTS:
+                ldpc.register(make_graph(bgx, Zx))
+        groups = make_mixed(2048, 1.5, seed=3)
+        jobs = [ldpc.BatchJob(torch.from_numpy(gr.batch.q).to(dev), gr.bg, gr.Z, gr.rows)
+                for gr in groups]
+        plan = ldpc.Plan(jobs, graph=True, autotune=True)
+        plan.launch()
+        torch.cuda.synchronize()
+        reps = 10
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            plan.launch(stream)
+        e1.record(stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        kbits = sum(gr.batch.u.shape[0] * gr.batch.u.shape[1] for gr in groups)
+        result["batched"] = {"workload": "2048 codewords, BG1/BG2-shaped, Z in {16..384}, "
+                                         "rows 4..M, 1.5 dB, one persistent launch",
+                             "gbps": round(kbits / (ms / 1e3) / 1e9, 3),
+                             "ms_per_launch": round(ms, 4), "shapes": len(groups),
+                             **plan.info()}
+        plan.close()
+        log("serving sweep")
+        from paper_2009_05534_amd import serve, nwms
+        wpath = os.path.join(ROOT, "paper_2009_05534_amd", "weights", "nwms_bg1_z384.npz")
+        wq = nwms.load_weights(wpath)[0] if os.path.exists(wpath) else None
+        blocks = serve.make_trace(600, seed=6)
+        srv = serve.Server(weights_bg1=wq, n_slots=4, mem_budget=256 << 20)
+        srv.run(serve.rescale(blocks[:100], 1e4))
+        result["serving"] = [srv.run(serve.rescale(blocks, r)) for r in (2e4, 1e5)]
+
     if not args.no_cpu_baseline:
         import oracle
         threads = max(1, min(16, os.cpu_count() or 1))

@@ -229,3 +229,38 @@ class Server:
                                              msg_placement="device")
         torch.cuda.synchronize(self.dev)
         return bits.cpu().numpy(), iters.cpu().numpy(), ok.cpu().numpy().astype(bool)
+
+
+def main():
+    import argparse
+    import json
+    import os
+    import sys
+    ap = argparse.ArgumentParser(description="offered-load sweep of the decode server")
+    ap.add_argument("--blocks", type=int, default=2000)
+    ap.add_argument("--rates", default="20000,50000,100000,200000,400000")
+    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--mem-mib", type=int, default=256)
+    ap.add_argument("--weights", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                                      "weights", "nwms_bg1_z384.npz"))
+    ap.add_argument("--seed", type=int, default=6)
+    args = ap.parse_args()
+    from . import ldpc, nwms
+    wq = None
+    if args.weights and os.path.exists(args.weights):
+        wq, _ = nwms.load_weights(args.weights)
+    blocks = make_trace(args.blocks, seed=args.seed)
+    for bg in (1, 2):
+        for Z in LIFTS:
+            ldpc.register(make_graph(bg, Z))
+    srv = Server(weights_bg1=wq, n_slots=args.slots, mem_budget=args.mem_mib << 20)
+    srv.run(rescale(blocks[:200], 1e4))  # warm-up
+    for r in [float(x) for x in args.rates.split(",")]:
+        st = srv.run(rescale(blocks, r))
+        st["rate_blocks_per_s"] = r
+        print(json.dumps(st), flush=True)
+    sys.stdout.flush()
+
+
+if __name__ == "__main__":
+    main()
