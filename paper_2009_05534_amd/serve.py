@@ -139,6 +139,7 @@ class Server:
         in_flight: list[tuple] = []    # (slot, event, batch, plain, mem)
         free_slots = list(range(self.n_slots))
         mem_used = 0
+        peak_mem = 0
         nxt = 0
         done = 0
         launches = 0
@@ -191,6 +192,7 @@ class Server:
                     ev.record(st)
                     in_flight.append((slot, ev, batch, plain, mem))
                     mem_used += mem
+                    peak_mem = max(peak_mem, mem_used)
                     launches += 1
         t_end = time.perf_counter() - t0
         torch.cuda.synchronize(self.dev)
@@ -206,6 +208,7 @@ class Server:
             "blocks": len(order),
             "codewords": int(sum(b.n_cw for b in order)),
             "launches": launches,
+            "peak_message_bytes": peak_mem,
             "offered_blocks_per_s": len(order) / max(order[-1].arrival, 1e-9),
             "gbps": bits / t_end / 1e9,
             "latency_ms_p50": float(np.percentile(lat, 50) * 1e3),
