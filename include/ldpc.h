@@ -124,11 +124,15 @@ typedef struct ldpc_args {
     void *out_llr;          /* NULL, or final posteriors [n_cw][Nc] in
                                variable order: int8 (I8) or binary16 (F16) */
     int cw_per_block;       /* 0 = library default; else codewords per
-                               workgroup (tuning knob) */
+                               workgroup (tuning knob; the int8 path decodes
+                               codewords in pairs and rounds it up to even) */
     int msg_placement;      /* where the int8 path keeps its check-to-
                                variable messages: LDPC_MSG_AUTO,
-                               LDPC_MSG_LDS (next to the posteriors in LDS)
-                               or LDPC_MSG_DEVICE (device memory, allocated
+                               LDPC_MSG_LDS (next to the posteriors in LDS;
+                               LDPC_EINVAL if one codeword pair's posteriors
+                               and messages, 2*(Nc/Z + E)*Z bytes, exceed a
+                               workgroup's LDS) or LDPC_MSG_DEVICE (device
+                               memory, allocated
                                by the library per call, stream-ordered; more
                                codewords then share a CU). binary16 always
                                uses device memory. */

@@ -65,9 +65,9 @@ int plan_build(Plan *p, const std::vector<BatchJob> &jobs, const std::vector<int
     int lds = 0, msg_per_block = 0;
     for (size_t j = 0; j < jobs.size(); ++j) {
         const BatchJob &jb = jobs[j];
-        const int per_cw = lds_bytes_i8_post(jb.n_cols, jb.Z);
-        lds = std::max(lds, jb.slots * per_cw + jb.slots * (int)sizeof(int));
-        msg_per_block = std::max(msg_per_block, jb.slots * jb.E * (jb.Z / 2));
+        const int per_pair = lds_bytes_i8_pair_post(jb.n_cols, jb.Z);
+        lds = std::max(lds, jb.slots / 2 * per_pair + jb.slots * (int)sizeof(int));
+        msg_per_block = std::max(msg_per_block, jb.slots / 2 * jb.E * jb.Z);
         for (int f = 0; f < job_cw[j]; f += jb.slots)
             tasks.push_back(BatchTask{(int)j, f, std::min(jb.slots, job_cw[j] - f), 0});
     }
@@ -199,9 +199,9 @@ int batch_async(const std::vector<BatchJob> &jobs, const std::vector<int> &job_c
     int lds = 0, msg_per_block = 0;
     for (size_t j = 0; j < jobs.size(); ++j) {
         const BatchJob &jb = jobs[j];
-        lds = std::max(lds, jb.slots * lds_bytes_i8_post(jb.n_cols, jb.Z) +
+        lds = std::max(lds, jb.slots / 2 * lds_bytes_i8_pair_post(jb.n_cols, jb.Z) +
                                 jb.slots * (int)sizeof(int));
-        msg_per_block = std::max(msg_per_block, jb.slots * jb.E * (jb.Z / 2));
+        msg_per_block = std::max(msg_per_block, jb.slots / 2 * jb.E * jb.Z);
         for (int f = 0; f < job_cw[j]; f += jb.slots)
             tasks.push_back(BatchTask{(int)j, f, std::min(jb.slots, job_cw[j] - f), 0});
     }

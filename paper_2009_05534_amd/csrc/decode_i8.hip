@@ -2,20 +2,28 @@
 // gfx950 (Ling & Cautereels, §III decoding rules, §IV min/second-min/sign
 // intermediates and the 8-bit number format).
 //
-// One workgroup decodes `cpw` codewords; each codeword's posteriors L_v and
-// check-to-variable messages L_{c->v} live in LDS for the whole decode
-// (BG1-shaped at Z = 384: 26,112 + 121,344 bytes). Lane u of a codeword
-// owns the check rows u and u + Z/2 of every block row, so the Z independent
-// rows of a layer (§II) run as Z/2 lanes with two rows each in packed 16-bit
-// VALU arithmetic. Layers run strictly in order with one workgroup barrier
-// each; after every iteration the full syndrome of the hard decisions is
-// checked and a codeword whose checks all hold stops changing.
+// Codeword pairs. A workgroup holds `slots` pairs; pair p is codewords 2p
+// and 2p+1 of the workgroup's range and occupies lanes [p*Z, (p+1)*Z). Lane
+// u of a pair owns check row u of every block row for BOTH codewords: a
+// 32-bit register carries two 16-bit lanes, the low one for codeword 2p and
+// the high one for 2p+1, so every packed VALU instruction advances the same
+// check of two codewords. Both codewords share the graph, so the circulant
+// gather of block (c, s) reads the same variable (u + s) mod Z for both
+// halves: the posterior of variable v of column c is one 16-bit pair word
+// in LDS (low byte codeword 2p, high byte 2p+1) and a gather is an address
+// plus one fixed byte shuffle, with no per-lane half swapping.
 //
-// Storage: pair words (16 bit) -- the low byte is the value for row/variable
-// p, the high byte for p + Z/2. In registers each int8 value sits in the
-// HIGH byte of a 16-bit lane ("x * 256"), so the int16 saturating subtract
-// clamps at +127 (plus a low byte of 0xFF) and one max clamps at -127; the
-// low byte is cleared before a value is negated or stored.
+// The Z independent rows of a layer (§II) run in parallel, layers strictly
+// in order with one workgroup barrier each; after every iteration the
+// syndrome of the hard decisions is checked per codeword (a sweep that stops
+// at the first failing check), and a codeword whose checks all hold has its
+// outputs written at once (its half of the pair is still computed, but
+// nothing reads it again).
+//
+// Register format: each int8 value sits in the HIGH byte of its 16-bit lane
+// ("x * 256"), so the int16 saturating subtract clamps at +127 (plus a low
+// byte of 0xFF) and one max clamps at -127; the low byte is cleared before a
+// value is negated or stored.
 #include "ldpc_internal.h"
 
 namespace ldpc {
@@ -30,10 +38,8 @@ __device__ inline uint32_t bits_of(s16x2 v) { return __builtin_bit_cast(uint32_t
 __device__ inline uint32_t bits_of(u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
 
 // v_perm selectors (source bytes 0..3 = the word, 0x0c = zero byte).
-constexpr uint32_t kUnpack = 0x010c000cu;      // word -> (b0 << 8, b1 << 24)
-constexpr uint32_t kUnpackSwap = 0x000c010cu;  // word -> (b1 << 8, b0 << 24)
-constexpr uint32_t kPack = 0x0c0c0301u;        // inverse of kUnpack
-constexpr uint32_t kPackSwap = 0x0c0c0103u;    // inverse of kUnpackSwap
+constexpr uint32_t kUnpack = 0x010c000cu;  // pair word -> (b0 << 8, b1 << 24)
+constexpr uint32_t kPack = 0x0c0c0301u;    // inverse of kUnpack
 
 __device__ inline uint32_t perm(uint32_t word, uint32_t sel) {
     return __builtin_amdgcn_perm(0u, word, sel);
@@ -48,81 +54,72 @@ __device__ inline u16x2 normalise(u16x2 m, u16x2 off16, u16x2 w) {
     return v << (u16x2){8, 8};
 }
 
-// Where lane u's two rows meet block `md`: byte offset of the pair word
-// from the lane's base (lb = codeword posteriors + 2u) and the unpack/pack
-// selectors. The offset is one compare, one select and one three-way add.
-struct Gather {
-    int off;
-    uint32_t sel_unpack, sel_pack;
+// Block metadata md = 2(c*Z + s) | (Z - s) << 16 (column c, shift s). Lane
+// u reads variable (u + s) mod Z of column c: LDS byte address lb + 2(cZ +
+// s), minus 2Z when u + s wraps (u >= Z - s); lb = pair posteriors + 2u.
+// The fields are scalar; the lane work is one compare, one select, one add.
+__device__ inline uint32_t gather(uint32_t md, uint32_t lb, uint32_t u, uint32_t Z) {
+    const uint32_t off = md & 0xFFFFu, thr = md >> 16;
+    const uint32_t wrap = u >= thr ? 2u * Z : 0u;
+    return lb + off - wrap;
+}
+
+__device__ inline uint32_t lds_ld16(const uint8_t *smem, uint32_t a) {
+    return *reinterpret_cast<const uint16_t *>(smem + a);
+}
+__device__ inline void lds_st16(uint8_t *smem, uint32_t a, uint32_t v) {
+    *reinterpret_cast<uint16_t *>(smem + a) = (uint16_t)v;
+}
+
+// Check-to-variable messages of one block row: pair words [k][Z] from the
+// row start. Device placement: a raw buffer over the pair's message region
+// with the lane's byte offset as the vector offset and the row and block
+// offsets as the scalar offset, so no address arithmetic runs per edge.
+// LDS placement: ro is the lane's LDS byte address of the row's first
+// message.
+template <bool IN_LDS>
+struct MsgRow {
+    __amdgpu_buffer_rsrc_t rsrc;  // device placement
+    uint8_t *lds;                 // LDS placement
+    uint32_t ro;                  // lane byte offset
+    uint32_t row;                 // byte offset of the row (device placement)
+    __device__ inline uint32_t ld(int k, int Z) const {
+        const uint32_t off = 2u * (uint32_t)(k * Z);
+        if constexpr (IN_LDS)
+            return *reinterpret_cast<const uint16_t *>(lds + (ro + off));
+        else
+            return __builtin_amdgcn_raw_buffer_load_b16(rsrc, ro, row + off, 0);
+    }
+    __device__ inline void st(int k, int Z, uint32_t v) const {
+        const uint32_t off = 2u * (uint32_t)(k * Z);
+        if constexpr (IN_LDS)
+            *reinterpret_cast<uint16_t *>(lds + (ro + off)) = (uint16_t)v;
+        else
+            __builtin_amdgcn_raw_buffer_store_b16((uint16_t)v, rsrc, ro, row + off, 0);
+    }
 };
 
-__device__ inline Gather gather(uint32_t md, int u, int Zh2) {
-    const int word = (int)(md & 0xFFFFu);
-    const int thr = (int)((md >> 16) & 0xFFu);
-    const bool shi = (md >> 24) & 1u;
-    const bool wrap = u >= thr;
-    Gather g;
-    g.off = 2 * word + (wrap ? -Zh2 : 0);
-    const bool swap = wrap != shi;
-    g.sel_unpack = swap ? kUnpackSwap : kUnpack;
-    g.sel_pack = swap ? kPackSwap : kPack;
-    return g;
-}
-
-// Message of block e for a lane: 16 bits at byte offset 2*(e*Zh + ro) from
-// the workgroup's uniform base (LDS or device memory). Unsigned 32-bit
-// offsets let a device access use the scalar-base + vector-offset form.
-__device__ inline uint32_t msg_ld(const uint16_t *Rb, int e, int Zh, int ro) {
-    const uint32_t off = 2u * (uint32_t)(e * Zh + ro);
-    return *reinterpret_cast<const uint16_t *>(reinterpret_cast<const uint8_t *>(Rb) + off);
-}
-__device__ inline void msg_st(uint16_t *Rb, int e, int Zh, int ro, uint32_t v) {
-    const uint32_t off = 2u * (uint32_t)(e * Zh + ro);
-    *reinterpret_cast<uint16_t *>(reinterpret_cast<uint8_t *>(Rb) + off) = (uint16_t)v;
-}
-
-// 16-bit LDS load/store at a byte offset from lb. The load's upper half is
-// left unspecified: every consumer goes through v_perm, which reads only
-// bytes 0 and 1.
-__device__ inline uint32_t lds_ld16(const uint8_t *lb, int off) {
-    return *reinterpret_cast<const uint16_t *>(lb + off);
-}
-__device__ inline void lds_st16(uint8_t *lb, int off, uint32_t v) {
-    *reinterpret_cast<uint16_t *>(lb + off) = (uint16_t)v;
-}
-
-// Variable-to-check messages of blocks K0..K1-1 of the row: reads first
-// (messages, then posteriors), then x = sat(L - R), folded into m1 / m2 / S.
+// Variable-to-check messages of blocks K0..K1-1 of the row from the
+// check-to-variable messages rv (already loaded), the posterior reads
+// issued first, then x = sat(L - R), folded into m1 / m2 / S.
 template <int K0, int K1, bool KEEP_GATHER>
-__device__ __forceinline__ void row_phase1(const uint8_t *__restrict__ lb,
-                                           const uint16_t *__restrict__ Rb, int ro,
-                                           const uint32_t *md, int e0, int u, int Zh,
-                                           bool first_iter, uint32_t *xv, uint32_t *axv, int *la,
-                                           uint32_t *sp, u16x2 &m1, u16x2 &m2, uint32_t &S) {
+__device__ __forceinline__ void row_phase1(const uint8_t *__restrict__ smem, uint32_t lb,
+                                           const uint32_t *rv, const uint32_t *md, uint32_t u,
+                                           int Z, uint32_t *xv, uint32_t *axv, uint32_t *la,
+                                           u16x2 &m1, u16x2 &m2, uint32_t &S) {
     constexpr int n = K1 - K0;
-    uint32_t lraw[n], rraw[n], su[n];
-    if (!first_iter) {
+    uint32_t lraw[n];
 #pragma unroll
-        for (int i = 0; i < n; ++i) rraw[i] = msg_ld(Rb, e0 + K0 + i, Zh, ro);
-    } else {
-#pragma unroll
-        for (int i = 0; i < n; ++i) rraw[i] = 0;
+    for (int i = 0; i < n; ++i) {
+        const uint32_t a = gather(md[K0 + i], lb, u, (uint32_t)Z);
+        if (KEEP_GATHER) la[K0 + i] = a;
+        lraw[i] = lds_ld16(smem, a);
     }
 #pragma unroll
     for (int i = 0; i < n; ++i) {
-        const Gather g = gather(md[K0 + i], u, 2 * Zh);
-        su[i] = g.sel_unpack;
-        if (KEEP_GATHER) {
-            la[K0 + i] = g.off;
-            sp[K0 + i] = g.sel_pack;
-        }
-        lraw[i] = lds_ld16(lb, g.off);
-    }
-#pragma unroll
-    for (int i = 0; i < n; ++i) {
-        const s16x2 L = as_s(perm(lraw[i], su[i]));
-        const s16x2 R = as_s(perm(rraw[i], kUnpack));
-        s16x2 x = __builtin_elementwise_sub_sat(L, R);
+        const s16x2 L = as_s(perm(lraw[i], kUnpack));
+        const s16x2 Rm = as_s(perm(rv[K0 + i], kUnpack));
+        s16x2 x = __builtin_elementwise_sub_sat(L, Rm);
         x = __builtin_elementwise_max(x, (s16x2){-127 * 256, -127 * 256});
         const s16x2 ax = __builtin_elementwise_max(x, (s16x2){0, 0} - x);
         const u16x2 axu = as_u(bits_of(ax));
@@ -134,40 +131,38 @@ __device__ __forceinline__ void row_phase1(const uint8_t *__restrict__ lb,
     }
 }
 
-// One block row of exactly W blocks for lane u (rows u and u + Zh):
-// variable-to-check messages, min / second min / sign product,
-// normalisation, check-to-variable messages and posterior write-back.
-// Specialising on W keeps the row free of branches, so the row's metadata
+// One block row of exactly W blocks for lane u: variable-to-check messages,
+// min / second min / sign product, normalisation, check-to-variable
+// messages and posterior write-back, for both codewords of the pair.
+// Specialising on W keeps the row free of branches: the row's metadata
 // arrives in one batch of scalar loads and the LDS reads are issued before
-// any arithmetic (scalar and LDS loads share one completion counter; a
-// scalar result consumed between LDS reads would serialise them).
-// Message of block e for this lane: Rb[e * Zh + ro], with Rb uniform across
-// the workgroup (LDS or device memory, carried by the pointer's address
-// space) and ro a 32-bit lane offset, so a device access is a scalar base
-// plus one vector offset. Rows wider than 10 blocks read in two halves and
+// any arithmetic. Rows wider than 10 blocks read in two halves and
 // recompute |x| and their gathers for the write-back, which keeps the
-// kernel under the register budget of six codewords per CU.
-template <int W>
-__device__ __forceinline__ void row_update_w(uint8_t *__restrict__ lb,
-                                             uint16_t *__restrict__ Rb, int ro,
-                                             cmeta_t meta, int e0, int u,
-                                             int Zh, bool first_iter, u16x2 wgt, u16x2 off16) {
+// register count low enough for several pairs per CU.
+template <int W, bool IN_LDS, bool FIRST>
+__device__ __forceinline__ void row_update_w(uint8_t *__restrict__ smem, uint32_t lb,
+                                             const MsgRow<IN_LDS> &R, cmeta_t meta, int e0,
+                                             uint32_t u, int Z, u16x2 wgt, u16x2 off16) {
     constexpr bool kWide = W > 10;
     uint32_t md[W];
 #pragma unroll
     for (int k = 0; k < W; ++k) md[k] = meta[e0 + k];
-    uint32_t xv[W], axv[W], sp[W];
-    int la[W];
+    // This row's check-to-variable messages (none in the first iteration).
+    uint32_t rv[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) rv[k] = FIRST ? 0u : R.ld(k, Z);
+    uint32_t xv[W], axv[W], la[W];
     u16x2 m1 = {0x7FFF, 0x7FFF}, m2 = {0x7FFF, 0x7FFF};
     uint32_t S = 0;
     if constexpr (kWide) {
         constexpr int H = (W + 1) / 2;
-        row_phase1<0, H, false>(lb, Rb, ro, md, e0, u, Zh, first_iter, xv, axv, la, sp, m1, m2,
-                                S);
-        row_phase1<H, W, false>(lb, Rb, ro, md, e0, u, Zh, first_iter, xv, axv, la, sp, m1, m2,
-                                S);
+        row_phase1<0, H, false>(smem, lb, rv, md, u, Z, xv, axv, la, m1, m2, S);
+        // keep the halves apart: the scheduler would otherwise issue every
+        // read of the row up front and hold both halves' registers at once
+        __builtin_amdgcn_sched_barrier(0);
+        row_phase1<H, W, false>(smem, lb, rv, md, u, Z, xv, axv, la, m1, m2, S);
     } else {
-        row_phase1<0, W, true>(lb, Rb, ro, md, e0, u, Zh, first_iter, xv, axv, la, sp, m1, m2, S);
+        row_phase1<0, W, true>(smem, lb, rv, md, u, Z, xv, axv, la, m1, m2, S);
     }
     const u16x2 a1 = normalise(m1, off16, wgt);
     const u16x2 a2 = normalise(m2, off16, wgt);
@@ -191,217 +186,272 @@ __device__ __forceinline__ void row_update_w(uint8_t *__restrict__ lb,
         const s16x2 Rn = (b ^ sx) - sx;
         const s16x2 Ln = __builtin_elementwise_max(__builtin_elementwise_add_sat(x, Rn),
                                                    (s16x2){-127 * 256, -127 * 256});
-        if (kWide) {
-            const Gather g = gather(md[k], u, 2 * Zh);
-            lds_st16(lb, g.off, perm(bits_of(Ln), g.sel_pack));
-        } else {
-            lds_st16(lb, la[k], perm(bits_of(Ln), sp[k]));
-        }
-        msg_st(Rb, e0 + k, Zh, ro, perm(bits_of(Rn), kPack));
+        const uint32_t a = kWide ? gather(md[k], lb, u, (uint32_t)Z) : la[k];
+        lds_st16(smem, a, perm(bits_of(Ln), kPack));
+        R.st(k, Z, perm(bits_of(Rn), kPack));
     }
 }
 
-// Parity of lane u's two rows over a row of exactly W blocks, as sign bits
-// 15 and 31 (hard decision [L_v < 0]).
+// Parity of check row u over a row of exactly W blocks for both codewords:
+// the XOR of the raw pair words, whose bits 7 and 15 are the hard decisions
+// [L_v < 0] of the two codewords.
 template <int W>
-__device__ __forceinline__ uint32_t row_parity_w(const uint8_t *__restrict__ lb,
-                                                 cmeta_t meta, int e0, int u,
-                                                 int Zh) {
-    uint32_t md[W], raw[W], su[W];
+__device__ __forceinline__ uint32_t row_parity_w(const uint8_t *__restrict__ smem, uint32_t lb,
+                                                 cmeta_t meta, int e0, uint32_t u, int Z) {
+    uint32_t md[W], raw[W];
 #pragma unroll
     for (int k = 0; k < W; ++k) md[k] = meta[e0 + k];
 #pragma unroll
-    for (int k = 0; k < W; ++k) {
-        const Gather g = gather(md[k], u, 2 * Zh);
-        su[k] = g.sel_unpack;
-        raw[k] = lds_ld16(lb, g.off);
-    }
+    for (int k = 0; k < W; ++k) raw[k] = lds_ld16(smem, gather(md[k], lb, u, (uint32_t)Z));
     uint32_t acc = 0;
 #pragma unroll
-    for (int k = 0; k < W; ++k) acc ^= perm(raw[k], su[k]);
+    for (int k = 0; k < W; ++k) acc ^= raw[k];
     return acc;
 }
 
 // Scalar dispatch on the row weight w in [W, WMAX].
-template <int W, int WMAX>
-__device__ __forceinline__ void row_update(int w, uint8_t *lb, uint16_t *Rb, int ro,
-                                           cmeta_t meta, int e0, int u, int Zh,
-                                           bool first_iter, u16x2 wgt, u16x2 off16) {
+template <int W, int WMAX, bool IN_LDS, bool FIRST>
+__device__ __forceinline__ void row_update(int w, uint8_t *smem, uint32_t lb,
+                                           const MsgRow<IN_LDS> &R, cmeta_t meta, int e0,
+                                           uint32_t u, int Z, u16x2 wgt, u16x2 off16) {
     if constexpr (W <= WMAX) {
         if (w == W) {
-            row_update_w<W>(lb, Rb, ro, meta, e0, u, Zh, first_iter, wgt, off16);
+            row_update_w<W, IN_LDS, FIRST>(smem, lb, R, meta, e0, u, Z, wgt, off16);
             return;
         }
-        row_update<W + 1, WMAX>(w, lb, Rb, ro, meta, e0, u, Zh, first_iter, wgt, off16);
+        row_update<W + 1, WMAX, IN_LDS, FIRST>(w, smem, lb, R, meta, e0, u, Z, wgt, off16);
     }
 }
 
 template <int W, int WMAX>
-__device__ __forceinline__ uint32_t row_parity(int w, const uint8_t *lb, cmeta_t meta,
-                                               int e0, int u, int Zh) {
+__device__ __forceinline__ uint32_t row_parity(int w, const uint8_t *smem, uint32_t lb,
+                                               cmeta_t meta, int e0, uint32_t u, int Z) {
     if constexpr (W <= WMAX) {
-        if (w == W) return row_parity_w<W>(lb, meta, e0, u, Zh);
-        return row_parity<W + 1, WMAX>(w, lb, meta, e0, u, Zh);
+        if (w == W) return row_parity_w<W>(smem, lb, meta, e0, u, Z);
+        return row_parity<W + 1, WMAX>(w, smem, lb, meta, e0, u, Z);
     }
     return 0;
 }
 
-// Nonzero if some check of lane u's two rows fails on the current hard
-// decisions.
+// Syndrome check of the pair's unfinished codewords (needA: codeword 2p,
+// needB: 2p+1): a failing check of row u marks its codeword in fl[0] /
+// fl[1] (the pair's LDS flags, zero on entry; every marking lane stores the
+// same 1). One failing check decides a codeword, so a wave stops sweeping
+// the rows as soon as every codeword its lanes serve is decided (marked by
+// any wave) -- only codewords whose checks all hold need the full sweep,
+// which keeps the check cheap in the iterations before convergence.
 template <int WMAX>
-__device__ inline uint32_t syndrome_fails(const uint8_t *__restrict__ lb,
-                                          crow_t row_ptr, cmeta_t meta, int rows, int u,
-                                          int Zh) {
-    uint32_t bad = 0;
+__device__ inline void syndrome_mark(const uint8_t *__restrict__ smem, uint32_t lb,
+                                     crow_t row_ptr, cmeta_t meta, int rows, uint32_t u, int Z,
+                                     volatile int *fl, bool needA, bool needB) {
     for (int r = 0; r < rows; ++r) {
         const int e0 = row_ptr[r], w = row_ptr[r + 1] - e0;
-        bad |= row_parity<2, WMAX>(w, lb, meta, e0, u, Zh);
+        const uint32_t par = row_parity<2, WMAX>(w, smem, lb, meta, e0, u, Z);
+        if (needA && (par & 0x80u)) fl[0] = 1;
+        if (needB && (par & 0x8000u)) fl[1] = 1;
+        const bool open = (needA && fl[0] == 0) || (needB && fl[1] == 0);
+        if (__ballot(open) == 0) break;
     }
-    return bad & 0x80008000u;
 }
 
-// Decodes `bw.n` codewords of one shape in this workgroup: codeword `slot`
-// is held by lanes [slot*Z/2, (slot+1)*Z/2); lanes beyond n*Z/2 only join
-// the barriers. Every thread of the workgroup must call it.
-// MSG_IN_LDS: the check-to-variable messages live next to the posteriors in
-// LDS (one BG1-shaped Z = 384 codeword fills a CU); otherwise they stream
-// through device memory (bw.msg, [n][E][Z/2] pair words) and only the
-// posteriors occupy LDS, so several codewords share a CU (§IV's placement
-// of L_v in shared memory and L_{c->v} in main memory).
-template <int WMAX, bool MSG_IN_LDS>
+// Outputs of the pair's codewords selected by `which` (bit 0: codeword 2p,
+// bit 1: 2p+1) from the current posteriors: hard decisions of the K
+// information bits packed LSB first (byte j of a column covers variables
+// 8j..8j+7, one 16-byte LDS read of pair words), iteration count, syndrome
+// flag and optionally the posteriors. Lanes of the pair share the work.
+__device__ inline void write_outputs(const BlockWork &bw, const uint8_t *Lp, int pair,
+                                     uint32_t u, int which, int iters, int okA, int okB) {
+    const int Z = bw.Z, bpc = Z / 8, nbytes = bw.kb * bpc;
+    const int kbytes = bw.kb * Z / 8;
+    const int cw0 = 2 * pair;
+#pragma unroll 1
+    for (int i = (int)u; i < nbytes; i += Z) {
+        const int c = i / bpc, j = i - c * bpc;
+        const uint2 *w2 = reinterpret_cast<const uint2 *>(Lp + 2 * (c * Z + 8 * j));
+        uint32_t ba = 0, bb = 0;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const uint2 w = w2[h];
+            const uint32_t d0 = w.x, d1 = w.y;
+            ba |= (((d0 >> 7) & 1u) | ((d0 >> 22) & 2u) | ((d1 << 2) >> 7 & 4u) |
+                   ((d1 >> 20) & 8u)) << (4 * h);
+            bb |= (((d0 >> 15) & 1u) | ((d0 >> 30) & 2u) | ((d1 >> 13) & 4u) |
+                   ((d1 >> 28) & 8u)) << (4 * h);
+        }
+        if (which & 1) bw.out_bits[(size_t)cw0 * kbytes + i] = (uint8_t)ba;
+        if (which & 2) bw.out_bits[(size_t)(cw0 + 1) * kbytes + i] = (uint8_t)bb;
+    }
+    if (u == 0) {
+        if (which & 1) {
+            bw.out_iters[cw0] = iters;
+            if (bw.out_ok) bw.out_ok[cw0] = (uint8_t)okA;
+        }
+        if (which & 2) {
+            bw.out_iters[cw0 + 1] = iters;
+            if (bw.out_ok) bw.out_ok[cw0 + 1] = (uint8_t)okB;
+        }
+    }
+    if (bw.out_llr) {
+        const int Nc = bw.n_cols * Z;
+        const uint16_t *Lw = reinterpret_cast<const uint16_t *>(Lp);
+#pragma unroll 1
+        for (int c = 0; c < bw.n_cols; ++c) {
+            const uint16_t v = Lw[c * Z + u];
+            if (which & 1) bw.out_llr[(size_t)cw0 * Nc + c * Z + u] = (int8_t)(v & 0xFF);
+            if (which & 2) bw.out_llr[(size_t)(cw0 + 1) * Nc + c * Z + u] = (int8_t)(v >> 8);
+        }
+    }
+}
+
+typedef const __attribute__((address_space(4))) uint32_t *cw32_t;
+
+// Q1.7 weight of row r from a per-row byte table in the constant address
+// space, read as the aligned dword that holds it (a scalar load; the dword
+// never crosses the page of the byte it holds).
+__device__ inline int row_weight(const uint8_t *wrow, int r) {
+    const uintptr_t a = reinterpret_cast<uintptr_t>(wrow + r);
+    const uint32_t word = *reinterpret_cast<cw32_t>(a & ~(uintptr_t)3);
+    return (int)((word >> (8u * (uint32_t)(a & 3u))) & 0xFFu);
+}
+
+template <bool IN_LDS>
+__device__ inline MsgRow<IN_LDS> msg_row(uint8_t *smem, uint32_t ro,
+                                         __amdgpu_buffer_rsrc_t rsrc, int e0, int Z) {
+    MsgRow<IN_LDS> R{rsrc, nullptr, 0u, 0u};
+    if (IN_LDS) {
+        R.lds = smem;
+        R.ro = ro + 2u * (uint32_t)(e0 * Z);
+    } else {
+        R.ro = ro;
+        R.row = 2u * (uint32_t)(e0 * Z);
+    }
+    return R;
+}
+
+// One iteration's sweep over the block rows (layers) in order, one
+// workgroup barrier per layer. wrow: this iteration's per-row Q1.7 weights
+// or null (bw.beta for every row).
+template <int WMAX, bool IN_LDS, bool FIRST>
+__device__ __forceinline__ void layer_pass(const BlockWork &bw, uint8_t *smem, uint32_t lb,
+                                           uint32_t ro, __amdgpu_buffer_rsrc_t rsrc,
+                                           crow_t row_ptr, cmeta_t meta, const uint8_t *wrow,
+                                           uint32_t u, bool busy, u16x2 off16) {
+    const int Z = bw.Z;
+    for (int r = 0; r < bw.rows; ++r) {
+        const int e0 = row_ptr[r], w = row_ptr[r + 1] - e0;
+        const int wt = wrow ? row_weight(wrow, r) : bw.beta;
+        const u16x2 wgt = {(unsigned short)wt, (unsigned short)wt};
+        const MsgRow<IN_LDS> R = msg_row<IN_LDS>(smem, ro, rsrc, e0, Z);
+        if (busy) row_update<2, WMAX, IN_LDS, FIRST>(w, smem, lb, R, meta, e0, u, Z, wgt, off16);
+        __syncthreads();
+    }
+}
+
+// Decodes `bw.n` codewords of one shape in this workgroup as bw.slots pairs
+// (lanes beyond the last valid pair only join the barriers; the partner of
+// an odd last codeword decodes all-zero inputs and writes nothing). Every
+// thread of the workgroup must call it.
+// IN_LDS: the check-to-variable messages live next to the posteriors in
+// LDS; otherwise they stream through device memory (bw.msg, [pair][E][Z]
+// pair words) and only the posteriors occupy LDS, so several pairs share a
+// CU (§IV's placement of L_v in shared and L_{c->v} in main memory).
+template <int WMAX, bool IN_LDS>
 __device__ __forceinline__ void decode_block(const BlockWork &bw, uint8_t *smem, crow_t row_ptr,
                                              cmeta_t meta) {
     static_assert(WMAX <= kMetaPad, "row metadata window exceeds the table padding");
-    const int Z = bw.Z, Zh = Z >> 1;
+    const int Z = bw.Z;
     const int N = bw.n_cols, E = bw.E, T = (N - 2) * Z;
-    const int slot_bytes = MSG_IN_LDS ? lds_bytes_i8(N, E, Z) : lds_bytes_i8_post(N, Z);
-    const int slot = threadIdx.x / Zh;
-    const int u = threadIdx.x - slot * Zh;
-    const bool valid = slot < bw.n;
-    const int sl = valid ? slot : 0;  // keeps idle lanes' pointers in range
-    uint16_t *Lw = reinterpret_cast<uint16_t *>(smem + sl * slot_bytes);
-    // Lane base for gathers: the codeword's posteriors plus 2u bytes.
-    uint8_t *lb = reinterpret_cast<uint8_t *>(Lw) + 2 * u;
-    // Messages: uniform base plus a 32-bit lane offset (see row_update_w).
-    uint16_t *Rb;
-    int ro;
-    if (MSG_IN_LDS) {
-        Rb = reinterpret_cast<uint16_t *>(smem) + N * Zh;
-        ro = sl * (slot_bytes / 2) + u;
-    } else {
-        Rb = bw.msg;
-        ro = sl * E * Zh + u;
-    }
-    int *flags = reinterpret_cast<int *>(smem + bw.slots * slot_bytes);
+    const int pair_bytes = IN_LDS ? lds_bytes_i8_pair(N, E, Z) : lds_bytes_i8_pair_post(N, Z);
+    const int p = threadIdx.x / Z;
+    const uint32_t u = threadIdx.x - p * Z;
+    const bool validA = 2 * p < bw.n, validB = 2 * p + 1 < bw.n;
+    const int ps = validA ? p : 0;  // keeps idle lanes' addresses in range
+    uint8_t *Lp = smem + ps * pair_bytes;
+    uint16_t *Lw = reinterpret_cast<uint16_t *>(Lp);
+    const uint32_t lb = (uint32_t)(ps * pair_bytes) + 2u * u;
+    uint32_t ro;
+    if (IN_LDS)
+        ro = (uint32_t)(ps * pair_bytes + 2 * N * Z) + 2u * u;
+    else
+        ro = 2u * ((uint32_t)(ps * E * Z) + u);
+    int *flags = reinterpret_cast<int *>(smem + bw.slots * pair_bytes);
+    // The workgroup's message region as a raw buffer (dword 3 = 0x00020000:
+    // untyped 32-bit data format for gfx9 raw buffer access).
+    const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+        bw.msg, 0, IN_LDS ? 0 : 2 * bw.slots * E * Z, 0x00020000);
 
     // Initialisation: punctured columns 0 and 1 carry no channel LLR.
-    if (valid) {
+    if (validA) {
         Lw[u] = 0;
-        Lw[Zh + u] = 0;
-        const int8_t *q = bw.llr + (size_t)slot * T;
+        Lw[Z + u] = 0;
+        const int8_t *qa = bw.llr + (size_t)(2 * p) * T;
+        const int8_t *qb = bw.llr + (size_t)(2 * p + 1) * T;
 #pragma unroll 1
         for (int c = 2; c < N; ++c) {
-            int lo = q[(c - 2) * Z + u], hi = q[(c - 2) * Z + u + Zh];
-            lo = lo < -127 ? -127 : lo;
-            hi = hi < -127 ? -127 : hi;
-            Lw[c * Zh + u] = (uint16_t)((lo & 0xFF) | ((hi & 0xFF) << 8));
+            int a = qa[(c - 2) * Z + u];
+            int b = validB ? qb[(c - 2) * Z + u] : 0;
+            a = a < -127 ? -127 : a;
+            b = b < -127 ? -127 : b;
+            Lw[c * Z + u] = (uint16_t)((a & 0xFF) | ((b & 0xFF) << 8));
         }
     }
     __syncthreads();
 
     const u16x2 off16 = {(unsigned short)(bw.offset << 8), (unsigned short)(bw.offset << 8)};
-    bool done = !valid;
-    int iters = bw.max_iter, ok = 0;
+    bool doneA = !validA, doneB = !validB;
     for (int t = 1; t <= bw.max_iter; ++t) {
-        int wt = bw.beta;
-        // weights through the constant address space: a scalar load per row
-        typedef const __attribute__((address_space(4))) uint8_t *cw8_t;
-        cw8_t wrow = nullptr;
-        if (bw.wq)
-            wrow = (cw8_t)(bw.wq + (size_t)((t < bw.w_iters ? t : bw.w_iters) - 1) * bw.w_stride);
-        for (int r = 0; r < bw.rows; ++r) {
-            const int e0 = row_ptr[r], w = row_ptr[r + 1] - e0;
-            if (wrow) wt = wrow[r];
-            const u16x2 wgt = {(unsigned short)wt, (unsigned short)wt};
-            if (!done) row_update<2, WMAX>(w, lb, Rb, ro, meta, e0, u, Zh, t == 1, wgt, off16);
-            __syncthreads();
-        }
+        const uint8_t *wrow = nullptr;
+        if (bw.wq) wrow = bw.wq + (size_t)((t < bw.w_iters ? t : bw.w_iters) - 1) * bw.w_stride;
+        const bool busy = !(doneA && doneB);
+        // the first iteration has no check-to-variable messages yet
+        if (t == 1)
+            layer_pass<WMAX, IN_LDS, true>(bw, smem, lb, ro, rsrc, row_ptr, meta, wrow, u, busy,
+                                           off16);
+        else
+            layer_pass<WMAX, IN_LDS, false>(bw, smem, lb, ro, rsrc, row_ptr, meta, wrow, u, busy,
+                                            off16);
         if (bw.early_exit || t == bw.max_iter) {
-            if ((int)threadIdx.x < bw.slots) flags[threadIdx.x] = 0;
+            if ((int)threadIdx.x < 2 * bw.slots) flags[threadIdx.x] = 0;
             __syncthreads();
-            if (!done && syndrome_fails<WMAX>(lb, row_ptr, meta, bw.rows, u, Zh))
-                atomicOr(&flags[slot], 1);
+            if (busy)
+                syndrome_mark<WMAX>(smem, lb, row_ptr, meta, bw.rows, u, Z, flags + 2 * p, !doneA,
+                                    !doneB);
             __syncthreads();
-            const bool holds = flags[sl] == 0;
-            if (!done) {
-                if (bw.early_exit && holds) {
-                    done = true;
-                    iters = t;
-                    ok = 1;
-                } else if (t == bw.max_iter) {
-                    ok = holds;
-                }
+            const bool holdsA = flags[2 * ps] == 0, holdsB = flags[2 * ps + 1] == 0;
+            bool finA = false, finB = false;
+            if (t == bw.max_iter) {
+                finA = !doneA;
+                finB = !doneB;
+            } else {
+                finA = !doneA && holdsA;
+                finB = !doneB && holdsB;
             }
-            if (bw.early_exit && __syncthreads_and(done)) break;
-            __syncthreads();
-        }
-    }
-    if (valid) {
-        // Outputs: hard decisions of the K information bits packed LSB
-        // first. Byte j of a codeword covers bits 8j..8j+7, all in one block
-        // column since Z is a multiple of 8; lane u packs byte u of each
-        // column.
-        const uint8_t *Lb = reinterpret_cast<const uint8_t *>(Lw);
-        const int bytes_per_col = Z / 8;
-        uint8_t *ob = bw.out_bits + (size_t)slot * (bw.kb * bytes_per_col);
-#pragma unroll 1
-        for (int c = 0; c < bw.kb; ++c) {
-#pragma unroll 1
-            for (int j = u; j < bytes_per_col; j += Zh) {
-                uint32_t byte = 0;
-#pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    const int z = 8 * j + i;
-                    const int hi = z >= Zh;
-                    const int8_t L = (int8_t)Lb[2 * (c * Zh + z - hi * Zh) + hi];
-                    byte |= (uint32_t)(L < 0) << i;
-                }
-                ob[c * bytes_per_col + j] = (uint8_t)byte;
-            }
-        }
-        if (u == 0) {
-            bw.out_iters[slot] = iters;
-            if (bw.out_ok) bw.out_ok[slot] = (uint8_t)ok;
-        }
-        if (bw.out_llr) {
-            int8_t *o = bw.out_llr + (size_t)slot * N * Z;
-#pragma unroll 1
-            for (int c = 0; c < N; ++c) {
-                const uint16_t w = Lw[c * Zh + u];
-                o[c * Z + u] = (int8_t)(w & 0xFF);
-                o[c * Z + u + Zh] = (int8_t)(w >> 8);
-            }
+            if (finA || finB)
+                write_outputs(bw, Lp, p, u, (finA ? 1 : 0) | (finB ? 2 : 0), t, holdsA, holdsB);
+            doneA = doneA || finA;
+            doneB = doneB || finB;
+            if (__syncthreads_and(doneA && doneB)) break;
         }
     }
 }
 
-template <int WMAX, bool MSG_IN_LDS>
-__global__ __launch_bounds__(512) void decode_i8_kernel(DecodeLaunch p,
+template <int WMAX, bool IN_LDS>
+__global__ __launch_bounds__(768) __attribute__((amdgpu_waves_per_eu(5))) void decode_i8_kernel(DecodeLaunch p,
                                                          const int32_t *__restrict__ row_ptr,
                                                          const uint32_t *__restrict__ meta) {
     extern __shared__ __align__(16) uint8_t smem[];
-    const int Zh = p.Z >> 1, T = (p.n_cols - 2) * p.Z, first = blockIdx.x * p.cpw;
+    const int T = (p.n_cols - 2) * p.Z, first = blockIdx.x * p.cpw;
     BlockWork bw;
     bw.n = p.n_cw - first < p.cpw ? p.n_cw - first : p.cpw;
-    bw.slots = p.cpw;
+    bw.slots = p.cpw / 2;
     bw.llr = p.llr + (size_t)first * T;
     bw.out_bits = p.out_bits + (size_t)first * (p.kb * p.Z / 8);
     bw.out_iters = p.out_iters + first;
     bw.out_ok = p.out_ok ? p.out_ok + first : nullptr;
     bw.out_llr = p.out_llr ? static_cast<int8_t *>(p.out_llr) + (size_t)first * p.n_cols * p.Z
                            : nullptr;
-    bw.msg = MSG_IN_LDS ? nullptr
-                        : reinterpret_cast<uint16_t *>(p.msg) + (size_t)first * p.E * Zh;
+    bw.msg = IN_LDS ? nullptr
+                    : reinterpret_cast<uint16_t *>(p.msg) + (size_t)(first / 2) * p.E * p.Z;
     bw.wq = p.wq;
     bw.w_iters = p.w_iters;
     bw.w_stride = p.rows;
@@ -414,55 +464,56 @@ __global__ __launch_bounds__(512) void decode_i8_kernel(DecodeLaunch p,
     bw.early_exit = p.early_exit;
     bw.beta = p.beta;
     bw.offset = p.offset;
-    decode_block<WMAX, MSG_IN_LDS>(bw, smem, (crow_t)row_ptr, (cmeta_t)meta);
+    decode_block<WMAX, IN_LDS>(bw, smem, (crow_t)row_ptr, (cmeta_t)meta);
 }
 
-template <int WMAX, bool MSG_IN_LDS>
+template <int WMAX, bool IN_LDS>
 hipError_t launch_w(const DecodeLaunch &p, hipStream_t stream) {
-    const int Zh = p.Z / 2;
-    const int per_cw = MSG_IN_LDS ? lds_bytes_i8(p.n_cols, p.E, p.Z)
-                                  : lds_bytes_i8_post(p.n_cols, p.Z);
-    const int lds = p.cpw * per_cw + p.cpw * (int)sizeof(int);
+    const int per_pair = IN_LDS ? lds_bytes_i8_pair(p.n_cols, p.E, p.Z)
+                                : lds_bytes_i8_pair_post(p.n_cols, p.Z);
+    const int pairs = p.cpw / 2;
+    const int lds = pairs * per_pair + p.cpw * (int)sizeof(int);
     static bool attr_set = false;
     if (!attr_set) {
         // Opt in to more than the default 64 KiB of dynamic LDS.
         const hipError_t e = hipFuncSetAttribute(
-            reinterpret_cast<const void *>(&decode_i8_kernel<WMAX, MSG_IN_LDS>),
+            reinterpret_cast<const void *>(&decode_i8_kernel<WMAX, IN_LDS>),
             hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes());
         if (e != hipSuccess) note_hip_error("hipFuncSetAttribute(decode_i8_kernel)", e);
         attr_set = true;
+    }
+    if (p.cpw < 2 || (p.cpw & 1) || pairs * p.Z > 768) {
+        note_hip_error("decode_i8_kernel: bad workgroup shape", hipErrorInvalidValue);
+        return hipErrorInvalidValue;
     }
     const int blocks = (p.n_cw + p.cpw - 1) / p.cpw;
     // hipGetLastError reports the last error of ANY earlier runtime call on
     // this thread; clear it so the check below sees this launch only.
     (void)hipGetLastError();
-    hipLaunchKernelGGL((decode_i8_kernel<WMAX, MSG_IN_LDS>), dim3(blocks), dim3(p.cpw * Zh), lds,
+    hipLaunchKernelGGL((decode_i8_kernel<WMAX, IN_LDS>), dim3(blocks), dim3(pairs * p.Z), lds,
                        stream, p, p.row_ptr, p.meta);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) note_hip_error("launch decode_i8_kernel", e);
     return e;
 }
 
-template <bool MSG_IN_LDS>
+template <bool IN_LDS>
 hipError_t launch_placed(const DecodeLaunch &p, hipStream_t stream) {
-    if (p.wmax <= 10) return launch_w<10, MSG_IN_LDS>(p, stream);
-    if (p.wmax <= 20) return launch_w<20, MSG_IN_LDS>(p, stream);
-    return launch_w<32, MSG_IN_LDS>(p, stream);
+    if (p.wmax <= 10) return launch_w<10, IN_LDS>(p, stream);
+    if (p.wmax <= 20) return launch_w<20, IN_LDS>(p, stream);
+    return launch_w<32, IN_LDS>(p, stream);
 }
 
-
 // Persistent mixed-shape decode: each workgroup takes tasks (up to a
-// workgroup's worth of codewords of one shape) from a device counter until
-// none are left, so every wave reaches the exit once the counter passes
-// n_tasks. Messages use the device placement with one region per
+// workgroup's worth of codeword pairs of one shape) from a device counter
+// until none are left, so every wave reaches the exit once the counter
+// passes n_tasks. Messages use the device placement with one region per
 // workgroup, reused from task to task.
 template <int WMAX>
-__global__ __launch_bounds__(256) void decode_batch_kernel(const BatchTask *__restrict__ tasks,
-                                                            const BatchJob *__restrict__ jobs,
-                                                            int n_tasks, unsigned *counter,
-                                                            uint16_t *msg_ws, int msg_per_block,
-                                                            int max_iter, int early_exit,
-                                                            int beta, int offset) {
+__global__ __launch_bounds__(kBatchLanes) __attribute__((amdgpu_waves_per_eu(5))) void decode_batch_kernel(
+    const BatchTask *__restrict__ tasks, const BatchJob *__restrict__ jobs, int n_tasks,
+    unsigned *counter, uint16_t *msg_ws, int msg_per_block, int max_iter, int early_exit,
+    int beta, int offset) {
     extern __shared__ __align__(16) uint8_t smem[];
     __shared__ int task_id;
     for (;;) {
@@ -476,7 +527,7 @@ __global__ __launch_bounds__(256) void decode_batch_kernel(const BatchTask *__re
         const int T = (jb.n_cols - 2) * jb.Z;
         BlockWork bw;
         bw.n = tk.n;
-        bw.slots = jb.slots;
+        bw.slots = jb.slots / 2;
         bw.llr = jb.llr + (size_t)tk.first * T;
         bw.out_bits = jb.out_bits + (size_t)tk.first * (jb.kb * jb.Z / 8);
         bw.out_iters = jb.out_iters + tk.first;
@@ -509,6 +560,10 @@ hipError_t launch_decode_i8(const DecodeLaunch &p, hipStream_t stream) {
 }
 
 hipError_t launch_decode_batch(const BatchLaunch &b, hipStream_t stream) {
+    if (b.lanes != kBatchLanes) {
+        note_hip_error("decode_batch_kernel: bad workgroup size", hipErrorInvalidValue);
+        return hipErrorInvalidValue;
+    }
     (void)hipGetLastError();
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, stream, b.counter);
     hipError_t e = hipGetLastError();

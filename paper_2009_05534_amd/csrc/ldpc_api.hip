@@ -25,6 +25,7 @@ struct DevTables {
     int32_t *row_ptr = nullptr;   // [m_rows + 1]
     uint32_t *meta = nullptr;     // [E_full + kMetaPad] row-pair layout
     uint32_t *meta_row = nullptr; // [E_full + kMetaPad] one row per lane
+    uint32_t *meta_i8 = nullptr;  // [E_full + kMetaPad] int8 codeword pairs
 };
 
 std::mutex g_mu;
@@ -46,9 +47,11 @@ void free_tables(DevTables &t) {
     if (t.row_ptr) (void)hipFree(t.row_ptr);
     if (t.meta) (void)hipFree(t.meta);
     if (t.meta_row) (void)hipFree(t.meta_row);
+    if (t.meta_i8) (void)hipFree(t.meta_i8);
     t.row_ptr = nullptr;
     t.meta = nullptr;
     t.meta_row = nullptr;
+    t.meta_i8 = nullptr;
 }
 
 // Device tables of graph (bg, Z) on the current device; caller holds g_mu.
@@ -64,20 +67,25 @@ int tables_for(const HostGraph &g, DevTables **out) {
     }
     const int Zh = g.Z / 2;
     const int E = g.row_ptr.back();
-    std::vector<uint32_t> meta(E + kMetaPad, 0u), meta_row(E + kMetaPad, 0u);
+    std::vector<uint32_t> meta(E + kMetaPad, 0u), meta_row(E + kMetaPad, 0u),
+        meta_i8(E + kMetaPad, 0u);
     for (int e2 = 0; e2 < E; ++e2) {
         meta[e2] = pack_meta(g.col[e2], g.shift[e2], Zh);
         meta_row[e2] = pack_meta_row(g.col[e2], g.shift[e2], g.Z);
+        meta_i8[e2] = pack_meta_i8(g.col[e2], g.shift[e2], g.Z);
     }
     DevTables t;
     if ((e = hipMalloc(&t.row_ptr, sizeof(int32_t) * g.row_ptr.size())) != hipSuccess ||
         (e = hipMalloc(&t.meta, sizeof(uint32_t) * meta.size())) != hipSuccess ||
         (e = hipMalloc(&t.meta_row, sizeof(uint32_t) * meta_row.size())) != hipSuccess ||
+        (e = hipMalloc(&t.meta_i8, sizeof(uint32_t) * meta_i8.size())) != hipSuccess ||
         (e = hipMemcpy(t.row_ptr, g.row_ptr.data(), sizeof(int32_t) * g.row_ptr.size(),
                        hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(t.meta, meta.data(), sizeof(uint32_t) * meta.size(),
                        hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(t.meta_row, meta_row.data(), sizeof(uint32_t) * meta_row.size(),
+                       hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(t.meta_i8, meta_i8.data(), sizeof(uint32_t) * meta_i8.size(),
                        hipMemcpyHostToDevice)) != hipSuccess) {
         free_tables(t);
         return hip_fail(e);
@@ -209,7 +217,7 @@ int ldpc_decode_ex(const ldpc_args *a) {
             if (w > wmax) wmax = w;
         }
         p.row_ptr = t->row_ptr;
-        p.meta = t->meta;
+        p.meta = a->precision == LDPC_I8 ? t->meta_i8 : t->meta;
         p.rows = a->rows;
         p.n_cols = g.kb + a->rows;
         p.kb = g.kb;
@@ -228,34 +236,39 @@ int ldpc_decode_ex(const ldpc_args *a) {
     p.early_exit = a->early_exit ? 1 : 0;
     const int Zh = p.Z / 2;
     const bool i8 = a->precision == LDPC_I8;
-    // int8 message placement: LDS when at least four codewords' full state
-    // fits a CU, else device memory so that several codewords share a CU.
+    int cpw = 0;
     bool msg_in_lds = false;
     if (i8) {
+        // Codewords go in pairs of Z lanes. Message placement: LDS when two
+        // pairs' full state fits a CU, else device memory so that several
+        // pairs share a CU.
+        const int full = lds_bytes_i8_pair(p.n_cols, p.E, p.Z) + 8;
         if (a->msg_placement == LDPC_MSG_LDS)
             msg_in_lds = true;
         else if (a->msg_placement == LDPC_MSG_DEVICE)
             msg_in_lds = false;
         else
-            msg_in_lds = 4 * (lds_bytes_i8(p.n_cols, p.E, p.Z) + 4) <= lds_cap;
+            msg_in_lds = 2 * full <= lds_cap;
+        const int per_pair = msg_in_lds ? full : lds_bytes_i8_pair_post(p.n_cols, p.Z) + 8;
+        int pairs = (a->cw_per_block + 1) / 2;
+        // Default: about 256 lanes per workgroup with the whole state in LDS,
+        // else about 384 (one pair per workgroup at the largest lifts).
+        if (pairs == 0) pairs = std::max(1, (msg_in_lds ? 256 : 384) / p.Z);
+        pairs = std::min(pairs, lds_cap / per_pair);
+        pairs = std::min(pairs, 768 / p.Z);
+        pairs = std::min(pairs, (a->n_cw + 1) / 2);
+        if (pairs < 1) return LDPC_EINVAL;  // a single pair does not fit
+        cpw = 2 * pairs;
+    } else {
+        const int per_cw = lds_bytes_f16(p.n_cols, p.Z) + 4;
+        cpw = a->cw_per_block;
+        // Default: about 128 lanes (Z/2 per codeword) per workgroup.
+        if (cpw == 0) cpw = std::max(1, 128 / Zh);
+        cpw = std::min(cpw, lds_cap / per_cw);
+        cpw = std::min(cpw, 512 / Zh);
+        cpw = std::min(cpw, a->n_cw);
+        if (cpw < 1) return LDPC_EINVAL;  // a single codeword does not fit
     }
-    const int per_cw = (i8 ? (msg_in_lds ? lds_bytes_i8(p.n_cols, p.E, p.Z)
-                                         : lds_bytes_i8_post(p.n_cols, p.Z))
-                           : lds_bytes_f16(p.n_cols, p.Z)) + 4;
-    const int cap_lds = lds_cap / per_cw;
-    const int cap_threads = 512 / Zh;
-    int cpw = a->cw_per_block;
-    if (cpw == 0) {
-        // Default: up to 256 lanes per workgroup when the whole state is in
-        // LDS; otherwise about 128 lanes (one codeword per workgroup at
-        // large lifts) so that several workgroups share a CU.
-        cpw = (msg_in_lds ? 256 : 128) / Zh;
-        if (cpw < 1) cpw = 1;
-    }
-    if (cpw > cap_lds) cpw = cap_lds;
-    if (cpw > cap_threads) cpw = cap_threads;
-    if (cpw > a->n_cw) cpw = a->n_cw;
-    if (cpw < 1) return LDPC_EINVAL;  // a single codeword does not fit
     p.cpw = cpw;
     hipStream_t stream = static_cast<hipStream_t>(a->stream);
     if (i8) {
@@ -272,7 +285,8 @@ int ldpc_decode_ex(const ldpc_args *a) {
     void *msg = nullptr;
     hipError_t e;
     if (!msg_in_lds) {
-        const size_t msg_bytes = (size_t)a->n_cw * p.E * Zh * (i8 ? 2 : 4);
+        const size_t msg_bytes = i8 ? (size_t)((a->n_cw + 1) / 2) * p.E * p.Z * 2
+                                    : (size_t)a->n_cw * p.E * Zh * 4;
         e = hipMallocAsync(&msg, msg_bytes, stream);
         if (e != hipSuccess) return hip_fail(e, "hipMallocAsync(messages)");
     }
@@ -345,8 +359,6 @@ struct ldpc_plan {
 };
 
 namespace {
-constexpr int kBatchLanes = 192;  // Z/2 lanes per codeword at the largest lift
-
 // Device job table entries for `jobs` (registered graphs, kept rows).
 int batch_jobs(const ldpc_job *jobs, int n_jobs, std::vector<BatchJob> &bj,
                std::vector<int> &job_cw, int &wmax, int &lds_cap) {
@@ -358,7 +370,7 @@ int batch_jobs(const ldpc_job *jobs, int n_jobs, std::vector<BatchJob> &bj,
         if (it == g_graphs.end()) return LDPC_ENOGRAPH;
         const HostGraph &g = it->second;
         int E = 0;
-        if (jb.n_cw < 1 || !jb.llr || !jb.out_bits || !jb.out_iters || g.Z > 2 * kBatchLanes ||
+        if (jb.n_cw < 1 || !jb.llr || !jb.out_bits || !jb.out_iters || g.Z > kBatchLanes ||
             (jb.wq && jb.wq_iters < 1) ||
             sub_sizes(g, jb.rows, nullptr, nullptr, nullptr, &E) != LDPC_OK)
             return LDPC_EINVAL;
@@ -373,7 +385,7 @@ int batch_jobs(const ldpc_job *jobs, int n_jobs, std::vector<BatchJob> &bj,
         b.out_iters = jb.out_iters;
         b.out_ok = jb.out_ok;
         b.row_ptr = t->row_ptr;
-        b.meta = t->meta;
+        b.meta = t->meta_i8;
         b.wq = jb.wq;
         b.w_iters = jb.wq ? jb.wq_iters : 0;
         b.w_stride = jb.rows;
@@ -382,7 +394,7 @@ int batch_jobs(const ldpc_job *jobs, int n_jobs, std::vector<BatchJob> &bj,
         b.kb = g.kb;
         b.Z = g.Z;
         b.E = E;
-        b.slots = std::max(1, kBatchLanes / (g.Z / 2));
+        b.slots = 2 * (kBatchLanes / g.Z);
         bj.push_back(b);
         job_cw.push_back(jb.n_cw);
     }

@@ -9,7 +9,7 @@
 
 namespace ldpc {
 
-// Packed per-block metadata for the row-pair layout used by both kernels.
+// Packed per-block metadata for the binary16 kernel's row-pair layout.
 // With Zh = Z/2, lane u of a codeword owns check rows u and u + Zh of the
 // current block row; block column c of the posteriors is stored as Zh
 // "pair words", word p holding the variables p and p + Zh of that column.
@@ -20,8 +20,9 @@ namespace ldpc {
 //   bits [0, 16)  c * Zh + s_lo   (pair word before the wrap)
 //   bits [16, 24) T = Zh - s_lo   (1..Zh)
 //   bit  24       s_hi
-// The device copy of the table carries kMetaPad zero entries after the last
-// block so that a kernel may read a fixed-size window from any row start.
+// The device copy of every table carries kMetaPad zero entries after the
+// last block so that a kernel may read a fixed-size window from any row
+// start.
 constexpr int kMetaPad = 64;
 
 __host__ __device__ inline uint32_t pack_meta(int c, int s, int Zh) {
@@ -42,38 +43,42 @@ struct DecodeLaunch {
     uint8_t *out_ok;          // [n_cw] or null
     void *out_llr;            // [n_cw][Nc] or null
     const int32_t *row_ptr;   // device [rows + 1]
-    const uint32_t *meta;     // device [E]
+    const uint32_t *meta;     // device [E]: int8 pack_meta_i8, binary16 pack_meta
     const uint8_t *wq;        // int8 path per-(iteration,row) weights or null
     const uint16_t *wh;       // binary16 path weights or null
-    uint32_t *msg;            // check-to-variable messages in device memory,
-                              // [n_cw][E][Zh] pair words (binary16: always;
-                              // int8: when not kept in LDS, else null)
+    uint32_t *msg;            // check-to-variable messages in device memory
+                              // (binary16: always, [n_cw][E][Zh] words; int8:
+                              // when not kept in LDS, [ceil(n_cw/2)][E][Z]
+                              // pair words; else null)
     int w_iters;
     int n_cw, rows, n_cols, kb, Z, E;
     int max_iter, early_exit;
     int beta, offset;         // int8: Q1.7 beta and offset; f16: bit patterns
-    int cpw;                  // codewords per workgroup
+    int cpw;                  // codewords per workgroup (int8: even, two per pair)
     int wmax;                 // max row weight over the kept rows
 };
 
-// A workgroup's share of an int8 decode: n codewords of one shape, each with
-// its own input, outputs and (device placement) message region.
+// A workgroup's share of an int8 decode: n codewords of one shape held as
+// `slots` codeword pairs (Z lanes per pair), each pair with its own
+// (device placement) message region.
 struct BlockWork {
     const int8_t *llr;        // first codeword's LLRs, [n][T]
     uint8_t *out_bits;        // [n][K/8]
     int32_t *out_iters;       // [n]
     uint8_t *out_ok;          // [n] or null
     int8_t *out_llr;          // [n][Nc] or null
-    uint16_t *msg;            // [n][E][Z/2] pair words (device placement)
+    uint16_t *msg;            // [slots][E][Z] pair words (device placement)
     const uint8_t *wq;        // per-(iteration, row) weights or null
     int w_iters, w_stride;    // weight rows and row stride
-    int n, slots;             // codewords here; codeword slots of the block
+    int n, slots;             // codewords here; codeword pairs of the block
     int rows, n_cols, kb, Z, E;
     int max_iter, early_exit, beta, offset;
 };
 
 // Mixed-shape batch: one job per (shape, buffers), tasks of up to `slots`
-// codewords of one job.
+// codewords (an even number: slots/2 pairs of Z lanes within kBatchLanes)
+// of one job.
+constexpr int kBatchLanes = 384;
 struct BatchJob {
     const int8_t *llr;
     uint8_t *out_bits;
@@ -114,13 +119,24 @@ int batch_async(const std::vector<BatchJob> &jobs, const std::vector<int> &job_c
                 int max_iter, int early_exit, int wmax, int lds_cap, hipStream_t stream,
                 size_t *bytes_in_flight);
 
-// Bytes of LDS one codeword needs in each kernel.
-__host__ __device__ inline int lds_bytes_i8(int n_cols, int E, int Z) { return (n_cols + E) * Z; }
-__host__ __device__ inline int lds_bytes_i8_post(int n_cols, int Z) { return n_cols * Z; }
+// Bytes of LDS one int8 codeword pair needs (posteriors and messages, or
+// posteriors only) and one binary16 codeword.
+__host__ __device__ inline int lds_bytes_i8_pair(int n_cols, int E, int Z) {
+    return 2 * (n_cols + E) * Z;
+}
+__host__ __device__ inline int lds_bytes_i8_pair_post(int n_cols, int Z) { return 2 * n_cols * Z; }
 __host__ __device__ inline int lds_bytes_f16(int n_cols, int Z) { return n_cols * Z * 2; }
 
-// Per-block metadata for one-row-per-lane kernels (the learned min-sum):
-// bits [0, 16) c * Z, bits [16, 25) shift. Padded like the pair table.
+// Per-block metadata for the int8 pair kernel: bits [0, 16) the byte offset
+// 2(c*Z + s) of variable s of column c in a pair's posteriors, bits
+// [16, 25) the wrap threshold Z - s (lane u reads variable (u + s) mod Z,
+// which wraps for u >= Z - s).
+__host__ __device__ inline uint32_t pack_meta_i8(int c, int s, int Z) {
+    return (uint32_t)(2 * (c * Z + s)) | ((uint32_t)(Z - s) << 16);
+}
+
+// Per-block metadata for the one-check-row-per-lane learned min-sum:
+// bits [0, 16) c * Z, bits [16, 25) shift.
 __host__ __device__ inline uint32_t pack_meta_row(int c, int s, int Z) {
     return (uint32_t)(c * Z) | ((uint32_t)s << 16);
 }
