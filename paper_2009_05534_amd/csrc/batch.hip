@@ -67,7 +67,7 @@ int plan_build(Plan *p, const std::vector<BatchJob> &jobs, const std::vector<int
         const BatchJob &jb = jobs[j];
         const int per_pair = lds_bytes_i8_pair_post(jb.n_cols, jb.Z);
         lds = std::max(lds, jb.slots / 2 * per_pair + jb.slots * (int)sizeof(int));
-        msg_per_block = std::max(msg_per_block, jb.slots / 2 * jb.E * jb.Z);
+        msg_per_block = std::max(msg_per_block, jb.slots / 2 * jb.E_pad * jb.Z);
         for (int f = 0; f < job_cw[j]; f += jb.slots)
             tasks.push_back(BatchTask{(int)j, f, std::min(jb.slots, job_cw[j] - f), 0});
     }
@@ -201,7 +201,7 @@ int batch_async(const std::vector<BatchJob> &jobs, const std::vector<int> &job_c
         const BatchJob &jb = jobs[j];
         lds = std::max(lds, jb.slots / 2 * lds_bytes_i8_pair_post(jb.n_cols, jb.Z) +
                                 jb.slots * (int)sizeof(int));
-        msg_per_block = std::max(msg_per_block, jb.slots / 2 * jb.E * jb.Z);
+        msg_per_block = std::max(msg_per_block, jb.slots / 2 * jb.E_pad * jb.Z);
         for (int f = 0; f < job_cw[j]; f += jb.slots)
             tasks.push_back(BatchTask{(int)j, f, std::min(jb.slots, job_cw[j] - f), 0});
     }

@@ -71,40 +71,102 @@ __device__ inline void lds_st16(uint8_t *smem, uint32_t a, uint32_t v) {
     *reinterpret_cast<uint16_t *>(smem + a) = (uint16_t)v;
 }
 
-// Check-to-variable messages of one block row: pair words [k][Z] from the
-// row start. Device placement: a raw buffer over the pair's message region
-// with the lane's byte offset as the vector offset and the row and block
-// offsets as the scalar offset, so no address arithmetic runs per edge.
-// LDS placement: ro is the lane's LDS byte address of the row's first
-// message.
+// Check-to-variable messages of one block row, moved as dwords of two pair
+// words (messages 2j and 2j+1 of the lane in dword j).
+// Device placement: row r of the pair's region holds Wp (the row weight
+// rounded up to even) messages per lane, lane u's contiguous, so a lane
+// moves its whole row in one to three dwordx4 / x2 / x1 raw-buffer
+// accesses: the vector offset is the lane's (pair base + u * 2Wp), the
+// scalar offset the row's.
+// LDS placement: [e][Z] pair words (lane-contiguous per edge, conflict
+// free); the two halves of a dword move as separate 16-bit accesses.
 template <bool IN_LDS>
 struct MsgRow {
     __amdgpu_buffer_rsrc_t rsrc;  // device placement
-    uint8_t *lds;                 // LDS placement
-    uint32_t ro;                  // lane byte offset
-    uint32_t row;                 // byte offset of the row (device placement)
-    __device__ inline uint32_t ld(int k, int Z) const {
-        const uint32_t off = 2u * (uint32_t)(k * Z);
-        if constexpr (IN_LDS)
-            return *reinterpret_cast<const uint16_t *>(lds + (ro + off));
-        else
-            return __builtin_amdgcn_raw_buffer_load_b16(rsrc, ro, row + off, 0);
+    uint8_t *lds;                 // LDS placement: the LDS array
+    uint32_t ro;                  // device: pair base; LDS: lane's edge-0 byte address
+    uint32_t row;                 // device: byte offset of the row in the pair region
+
+    // Loads the row's (W + 1) / 2 message dwords into d.
+    template <int W>
+    __device__ inline void load(uint32_t *d, uint32_t u, int Z) const {
+        constexpr int ND = (W + 1) / 2;
+        if constexpr (IN_LDS) {
+#pragma unroll
+            for (int j = 0; j < ND; ++j) {
+                const uint32_t a = ro + 4u * (uint32_t)(j * Z);
+                const uint32_t lo = *reinterpret_cast<const uint16_t *>(lds + a);
+                const uint32_t hi =
+                    2 * j + 1 < W ? *reinterpret_cast<const uint16_t *>(lds + a + 2u * Z) : 0u;
+                d[j] = lo | hi << 16;
+            }
+        } else {
+            const uint32_t v = ro + u * (4u * ND);
+#pragma unroll
+            for (int c = 0; c < ND; c += 4) {
+                const uint32_t so = row + 4u * c;
+                if (ND - c >= 4) {
+                    const auto q = __builtin_amdgcn_raw_buffer_load_b128(rsrc, v, so, 0);
+                    d[c] = q[0], d[c + 1] = q[1], d[c + 2] = q[2], d[c + 3] = q[3];
+                } else if (ND - c == 3) {
+                    const auto q = __builtin_amdgcn_raw_buffer_load_b96(rsrc, v, so, 0);
+                    d[c] = q[0], d[c + 1] = q[1], d[c + 2] = q[2];
+                } else if (ND - c == 2) {
+                    const auto q = __builtin_amdgcn_raw_buffer_load_b64(rsrc, v, so, 0);
+                    d[c] = q[0], d[c + 1] = q[1];
+                } else {
+                    d[c] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, v, so, 0);
+                }
+            }
+        }
     }
-    __device__ inline void st(int k, int Z, uint32_t v) const {
-        const uint32_t off = 2u * (uint32_t)(k * Z);
-        if constexpr (IN_LDS)
-            *reinterpret_cast<uint16_t *>(lds + (ro + off)) = (uint16_t)v;
-        else
-            __builtin_amdgcn_raw_buffer_store_b16((uint16_t)v, rsrc, ro, row + off, 0);
+    // Stores the n (1..4) message dwords d[c .. c+n) of the row (c and n are
+    // constants once the caller's loop is unrolled).
+    template <int W>
+    __device__ inline void store(const uint32_t *d, uint32_t u, int Z, int c, int n) const {
+        constexpr int ND = (W + 1) / 2;
+        if constexpr (IN_LDS) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int j = c + i;
+                if (i >= n) break;
+                const uint32_t a = ro + 4u * (uint32_t)(j * Z);
+                *reinterpret_cast<uint16_t *>(lds + a) = (uint16_t)d[j];
+                if (2 * j + 1 < W)
+                    *reinterpret_cast<uint16_t *>(lds + a + 2u * Z) = (uint16_t)(d[j] >> 16);
+            }
+        } else {
+            typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+            typedef uint32_t v3u __attribute__((ext_vector_type(3)));
+            typedef uint32_t v2u __attribute__((ext_vector_type(2)));
+            const uint32_t v = ro + u * (4u * ND), so = row + 4u * c;
+            if (n == 4) {
+                const v4u q = {d[c], d[c + 1], d[c + 2], d[c + 3]};
+                __builtin_amdgcn_raw_buffer_store_b128(q, rsrc, v, so, 0);
+            } else if (n == 3) {
+                const v3u q = {d[c], d[c + 1], d[c + 2]};
+                __builtin_amdgcn_raw_buffer_store_b96(q, rsrc, v, so, 0);
+            } else if (n == 2) {
+                const v2u q = {d[c], d[c + 1]};
+                __builtin_amdgcn_raw_buffer_store_b64(q, rsrc, v, so, 0);
+            } else {
+                __builtin_amdgcn_raw_buffer_store_b32(d[c], rsrc, v, so, 0);
+            }
+        }
     }
 };
 
+// v_perm selectors for the second pair word of a dword (bytes 2, 3) and for
+// packing two messages into one dword.
+constexpr uint32_t kUnpackHi = 0x030c020cu;  // dword -> (b2 << 8, b3 << 24)
+constexpr uint32_t kPack2 = 0x07050301u;     // (R_k, R_k+1) -> pair words k, k+1
+
 // Variable-to-check messages of blocks K0..K1-1 of the row from the
-// check-to-variable messages rv (already loaded), the posterior reads
+// check-to-variable message dwords rd (already loaded), the posterior reads
 // issued first, then x = sat(L - R), folded into m1 / m2 / S.
 template <int K0, int K1, bool KEEP_GATHER>
 __device__ __forceinline__ void row_phase1(const uint8_t *__restrict__ smem, uint32_t lb,
-                                           const uint32_t *rv, const uint32_t *md, uint32_t u,
+                                           const uint32_t *rd, const uint32_t *md, uint32_t u,
                                            int Z, uint32_t *xv, uint32_t *axv, uint32_t *la,
                                            u16x2 &m1, u16x2 &m2, uint32_t &S) {
     constexpr int n = K1 - K0;
@@ -118,7 +180,8 @@ __device__ __forceinline__ void row_phase1(const uint8_t *__restrict__ smem, uin
 #pragma unroll
     for (int i = 0; i < n; ++i) {
         const s16x2 L = as_s(perm(lraw[i], kUnpack));
-        const s16x2 Rm = as_s(perm(rv[K0 + i], kUnpack));
+        const int k = K0 + i;
+        const s16x2 Rm = as_s(perm(rd[k >> 1], (k & 1) ? kUnpackHi : kUnpack));
         s16x2 x = __builtin_elementwise_sub_sat(L, Rm);
         x = __builtin_elementwise_max(x, (s16x2){-127 * 256, -127 * 256});
         const s16x2 ax = __builtin_elementwise_max(x, (s16x2){0, 0} - x);
@@ -148,21 +211,26 @@ __device__ __forceinline__ void row_update_w(uint8_t *__restrict__ smem, uint32_
 #pragma unroll
     for (int k = 0; k < W; ++k) md[k] = meta[e0 + k];
     // This row's check-to-variable messages (none in the first iteration).
-    uint32_t rv[W];
+    constexpr int ND = (W + 1) / 2;
+    uint32_t rd[ND];
+    if (FIRST) {
 #pragma unroll
-    for (int k = 0; k < W; ++k) rv[k] = FIRST ? 0u : R.ld(k, Z);
+        for (int j = 0; j < ND; ++j) rd[j] = 0;
+    } else {
+        R.template load<W>(rd, u, Z);
+    }
     uint32_t xv[W], axv[W], la[W];
     u16x2 m1 = {0x7FFF, 0x7FFF}, m2 = {0x7FFF, 0x7FFF};
     uint32_t S = 0;
     if constexpr (kWide) {
         constexpr int H = (W + 1) / 2;
-        row_phase1<0, H, false>(smem, lb, rv, md, u, Z, xv, axv, la, m1, m2, S);
+        row_phase1<0, H, false>(smem, lb, rd, md, u, Z, xv, axv, la, m1, m2, S);
         // keep the halves apart: the scheduler would otherwise issue every
         // read of the row up front and hold both halves' registers at once
         __builtin_amdgcn_sched_barrier(0);
-        row_phase1<H, W, false>(smem, lb, rv, md, u, Z, xv, axv, la, m1, m2, S);
+        row_phase1<H, W, false>(smem, lb, rd, md, u, Z, xv, axv, la, m1, m2, S);
     } else {
-        row_phase1<0, W, true>(smem, lb, rv, md, u, Z, xv, axv, la, m1, m2, S);
+        row_phase1<0, W, true>(smem, lb, rd, md, u, Z, xv, axv, la, m1, m2, S);
     }
     const u16x2 a1 = normalise(m1, off16, wgt);
     const u16x2 a2 = normalise(m2, off16, wgt);
@@ -173,6 +241,8 @@ __device__ __forceinline__ void row_update_w(uint8_t *__restrict__ smem, uint32_
     const s16x2 b2 = (as_s(bits_of(a2)) ^ Sm) - Sm;
     const u16x2 d21 = as_u(bits_of(b2 - b1));
     const u16x2 m1p = m1 + (u16x2){1, 1};
+    uint32_t sd[ND];
+    uint32_t rprev = 0;
 #pragma unroll
     for (int k = 0; k < W; ++k) {
         const s16x2 x = as_s(xv[k]);
@@ -188,7 +258,20 @@ __device__ __forceinline__ void row_update_w(uint8_t *__restrict__ smem, uint32_
                                                    (s16x2){-127 * 256, -127 * 256});
         const uint32_t a = kWide ? gather(md[k], lb, u, (uint32_t)Z) : la[k];
         lds_st16(smem, a, perm(bits_of(Ln), kPack));
-        R.st(k, Z, perm(bits_of(Rn), kPack));
+        // messages k-1 and k share a dword (an odd row's last dword pads
+        // with a zero pair word); store each group of 4 dwords once complete
+        if (k & 1) {
+            sd[k >> 1] = __builtin_amdgcn_perm(bits_of(Rn), rprev, kPack2);
+        } else if (k == W - 1) {
+            sd[k >> 1] = perm(bits_of(Rn), kPack);
+        } else {
+            rprev = bits_of(Rn);
+        }
+        const int j = k >> 1;
+        if ((k & 1) || k == W - 1) {
+            if ((j & 3) == 3) R.template store<W>(sd, u, Z, j & ~3, 4);
+            else if (j == ND - 1) R.template store<W>(sd, u, Z, j & ~3, ND - (j & ~3));
+        }
     }
 }
 
@@ -261,6 +344,10 @@ __device__ inline void syndrome_mark(const uint8_t *__restrict__ smem, uint32_t 
 // flag and optionally the posteriors. Lanes of the pair share the work.
 __device__ inline void write_outputs(const BlockWork &bw, const uint8_t *Lp, int pair,
                                      uint32_t u, int which, int iters, int okA, int okB) {
+    // An opaque copy of the pair index: keeps the compiler from hoisting
+    // this (rarely run) output addressing out of the iteration loop, where
+    // it would hold registers through every layer.
+    __asm__ volatile("" : "+v"(pair), "+v"(u));
     const int Z = bw.Z, bpc = Z / 8, nbytes = bw.kb * bpc;
     const int kbytes = bw.kb * Z / 8;
     const int cw0 = 2 * pair;
@@ -314,16 +401,18 @@ __device__ inline int row_weight(const uint8_t *wrow, int r) {
     return (int)((word >> (8u * (uint32_t)(a & 3u))) & 0xFFu);
 }
 
+// Message row of block row r: LDS placement from the row's first edge e0,
+// device placement from its padded start p0.
 template <bool IN_LDS>
 __device__ inline MsgRow<IN_LDS> msg_row(uint8_t *smem, uint32_t ro,
-                                         __amdgpu_buffer_rsrc_t rsrc, int e0, int Z) {
+                                         __amdgpu_buffer_rsrc_t rsrc, int e0, int p0, int Z) {
     MsgRow<IN_LDS> R{rsrc, nullptr, 0u, 0u};
     if (IN_LDS) {
         R.lds = smem;
         R.ro = ro + 2u * (uint32_t)(e0 * Z);
     } else {
         R.ro = ro;
-        R.row = 2u * (uint32_t)(e0 * Z);
+        R.row = 2u * (uint32_t)(p0 * Z);
     }
     return R;
 }
@@ -341,7 +430,8 @@ __device__ __forceinline__ void layer_pass(const BlockWork &bw, uint8_t *smem, u
         const int e0 = row_ptr[r], w = row_ptr[r + 1] - e0;
         const int wt = wrow ? row_weight(wrow, r) : bw.beta;
         const u16x2 wgt = {(unsigned short)wt, (unsigned short)wt};
-        const MsgRow<IN_LDS> R = msg_row<IN_LDS>(smem, ro, rsrc, e0, Z);
+        const MsgRow<IN_LDS> R =
+            msg_row<IN_LDS>(smem, ro, rsrc, e0, IN_LDS ? 0 : ((crow_t)bw.row_pad)[r], Z);
         if (busy) row_update<2, WMAX, IN_LDS, FIRST>(w, smem, lb, R, meta, e0, u, Z, wgt, off16);
         __syncthreads();
     }
@@ -373,12 +463,12 @@ __device__ __forceinline__ void decode_block(const BlockWork &bw, uint8_t *smem,
     if (IN_LDS)
         ro = (uint32_t)(ps * pair_bytes + 2 * N * Z) + 2u * u;
     else
-        ro = 2u * ((uint32_t)(ps * E * Z) + u);
+        ro = 2u * (uint32_t)(ps * bw.E_pad * Z);
     int *flags = reinterpret_cast<int *>(smem + bw.slots * pair_bytes);
     // The workgroup's message region as a raw buffer (dword 3 = 0x00020000:
     // untyped 32-bit data format for gfx9 raw buffer access).
     const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
-        bw.msg, 0, IN_LDS ? 0 : 2 * bw.slots * E * Z, 0x00020000);
+        bw.msg, 0, IN_LDS ? 0 : 2 * bw.slots * bw.E_pad * Z, 0x00020000);
 
     // Initialisation: punctured columns 0 and 1 carry no channel LLR.
     if (validA) {
@@ -451,7 +541,9 @@ __global__ __launch_bounds__(768) __attribute__((amdgpu_waves_per_eu(5))) void d
     bw.out_llr = p.out_llr ? static_cast<int8_t *>(p.out_llr) + (size_t)first * p.n_cols * p.Z
                            : nullptr;
     bw.msg = IN_LDS ? nullptr
-                    : reinterpret_cast<uint16_t *>(p.msg) + (size_t)(first / 2) * p.E * p.Z;
+                    : reinterpret_cast<uint16_t *>(p.msg) + (size_t)(first / 2) * p.E_pad * p.Z;
+    bw.row_pad = p.row_pad;
+    bw.E_pad = p.E_pad;
     bw.wq = p.wq;
     bw.w_iters = p.w_iters;
     bw.w_stride = p.rows;
@@ -534,6 +626,8 @@ __global__ __launch_bounds__(kBatchLanes) __attribute__((amdgpu_waves_per_eu(5))
         bw.out_ok = jb.out_ok ? jb.out_ok + tk.first : nullptr;
         bw.out_llr = nullptr;
         bw.msg = msg_ws + (size_t)blockIdx.x * msg_per_block;
+        bw.row_pad = jb.row_pad;
+        bw.E_pad = jb.E_pad;
         bw.wq = jb.wq;
         bw.w_iters = jb.w_iters;
         bw.w_stride = jb.w_stride;

@@ -26,6 +26,7 @@ struct DevTables {
     uint32_t *meta = nullptr;     // [E_full + kMetaPad] row-pair layout
     uint32_t *meta_row = nullptr; // [E_full + kMetaPad] one row per lane
     uint32_t *meta_i8 = nullptr;  // [E_full + kMetaPad] int8 codeword pairs
+    int32_t *row_pad = nullptr;   // [m_rows + 1] prefix of even-padded row weights
 };
 
 std::mutex g_mu;
@@ -48,10 +49,23 @@ void free_tables(DevTables &t) {
     if (t.meta) (void)hipFree(t.meta);
     if (t.meta_row) (void)hipFree(t.meta_row);
     if (t.meta_i8) (void)hipFree(t.meta_i8);
+    if (t.row_pad) (void)hipFree(t.row_pad);
     t.row_ptr = nullptr;
     t.meta = nullptr;
     t.meta_row = nullptr;
     t.meta_i8 = nullptr;
+    t.row_pad = nullptr;
+}
+
+// Row starts of the int8 device message layout: each row's weight rounded
+// up to even, so that a lane's messages of a row fill whole dwords.
+std::vector<int32_t> padded_row_ptr(const HostGraph &g) {
+    std::vector<int32_t> rp(g.row_ptr.size(), 0);
+    for (size_t r = 0; r + 1 < g.row_ptr.size(); ++r) {
+        const int w = g.row_ptr[r + 1] - g.row_ptr[r];
+        rp[r + 1] = rp[r] + w + (w & 1);
+    }
+    return rp;
 }
 
 // Device tables of graph (bg, Z) on the current device; caller holds g_mu.
@@ -74,8 +88,12 @@ int tables_for(const HostGraph &g, DevTables **out) {
         meta_row[e2] = pack_meta_row(g.col[e2], g.shift[e2], g.Z);
         meta_i8[e2] = pack_meta_i8(g.col[e2], g.shift[e2], g.Z);
     }
+    const std::vector<int32_t> row_pad = padded_row_ptr(g);
     DevTables t;
     if ((e = hipMalloc(&t.row_ptr, sizeof(int32_t) * g.row_ptr.size())) != hipSuccess ||
+        (e = hipMalloc(&t.row_pad, sizeof(int32_t) * row_pad.size())) != hipSuccess ||
+        (e = hipMemcpy(t.row_pad, row_pad.data(), sizeof(int32_t) * row_pad.size(),
+                       hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMalloc(&t.meta, sizeof(uint32_t) * meta.size())) != hipSuccess ||
         (e = hipMalloc(&t.meta_row, sizeof(uint32_t) * meta_row.size())) != hipSuccess ||
         (e = hipMalloc(&t.meta_i8, sizeof(uint32_t) * meta_i8.size())) != hipSuccess ||
@@ -217,6 +235,8 @@ int ldpc_decode_ex(const ldpc_args *a) {
             if (w > wmax) wmax = w;
         }
         p.row_ptr = t->row_ptr;
+        p.row_pad = t->row_pad;
+        p.E_pad = padded_row_ptr(g)[a->rows];
         p.meta = a->precision == LDPC_I8 ? t->meta_i8 : t->meta;
         p.rows = a->rows;
         p.n_cols = g.kb + a->rows;
@@ -285,7 +305,7 @@ int ldpc_decode_ex(const ldpc_args *a) {
     void *msg = nullptr;
     hipError_t e;
     if (!msg_in_lds) {
-        const size_t msg_bytes = i8 ? (size_t)((a->n_cw + 1) / 2) * p.E * p.Z * 2
+        const size_t msg_bytes = i8 ? (size_t)((a->n_cw + 1) / 2) * p.E_pad * p.Z * 2
                                     : (size_t)a->n_cw * p.E * Zh * 4;
         e = hipMallocAsync(&msg, msg_bytes, stream);
         if (e != hipSuccess) return hip_fail(e, "hipMallocAsync(messages)");
@@ -385,6 +405,8 @@ int batch_jobs(const ldpc_job *jobs, int n_jobs, std::vector<BatchJob> &bj,
         b.out_iters = jb.out_iters;
         b.out_ok = jb.out_ok;
         b.row_ptr = t->row_ptr;
+        b.row_pad = t->row_pad;
+        b.E_pad = padded_row_ptr(g)[jb.rows];
         b.meta = t->meta_i8;
         b.wq = jb.wq;
         b.w_iters = jb.wq ? jb.wq_iters : 0;

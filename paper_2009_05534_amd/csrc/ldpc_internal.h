@@ -43,15 +43,16 @@ struct DecodeLaunch {
     uint8_t *out_ok;          // [n_cw] or null
     void *out_llr;            // [n_cw][Nc] or null
     const int32_t *row_ptr;   // device [rows + 1]
+    const int32_t *row_pad;   // device [rows + 1] even-padded row starts (int8)
     const uint32_t *meta;     // device [E]: int8 pack_meta_i8, binary16 pack_meta
     const uint8_t *wq;        // int8 path per-(iteration,row) weights or null
     const uint16_t *wh;       // binary16 path weights or null
     uint32_t *msg;            // check-to-variable messages in device memory
                               // (binary16: always, [n_cw][E][Zh] words; int8:
-                              // when not kept in LDS, [ceil(n_cw/2)][E][Z]
-                              // pair words; else null)
+                              // when not kept in LDS, [ceil(n_cw/2)][E_pad*Z]
+                              // pair words, see BlockWork; else null)
     int w_iters;
-    int n_cw, rows, n_cols, kb, Z, E;
+    int n_cw, rows, n_cols, kb, Z, E, E_pad;
     int max_iter, early_exit;
     int beta, offset;         // int8: Q1.7 beta and offset; f16: bit patterns
     int cpw;                  // codewords per workgroup (int8: even, two per pair)
@@ -67,11 +68,16 @@ struct BlockWork {
     int32_t *out_iters;       // [n]
     uint8_t *out_ok;          // [n] or null
     int8_t *out_llr;          // [n][Nc] or null
-    uint16_t *msg;            // [slots][E][Z] pair words (device placement)
+    uint16_t *msg;            // device placement: [slots][E_pad*Z] pair words;
+                              // row r of a pair occupies pair words
+                              // [row_pad[r]*Z, row_pad[r+1]*Z), lane u's Wp
+                              // (the row weight rounded up to even) messages
+                              // contiguous at u*Wp
+    const int32_t *row_pad;   // even-padded row starts
     const uint8_t *wq;        // per-(iteration, row) weights or null
     int w_iters, w_stride;    // weight rows and row stride
     int n, slots;             // codewords here; codeword pairs of the block
-    int rows, n_cols, kb, Z, E;
+    int rows, n_cols, kb, Z, E, E_pad;
     int max_iter, early_exit, beta, offset;
 };
 
@@ -85,10 +91,11 @@ struct BatchJob {
     int32_t *out_iters;
     uint8_t *out_ok;
     const int32_t *row_ptr;
+    const int32_t *row_pad;
     const uint32_t *meta;
     const uint8_t *wq;
     int w_iters, w_stride;
-    int rows, n_cols, kb, Z, E, slots;
+    int rows, n_cols, kb, Z, E, E_pad, slots;
 };
 struct BatchTask {
     int job, first, n, pad;
