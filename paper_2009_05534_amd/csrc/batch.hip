@@ -66,7 +66,7 @@ int plan_build(Plan *p, const std::vector<BatchJob> &jobs, const std::vector<int
     for (size_t j = 0; j < jobs.size(); ++j) {
         const BatchJob &jb = jobs[j];
         const int per_pair = lds_bytes_i8_pair_post(jb.n_cols, jb.Z);
-        lds = std::max(lds, jb.slots / 2 * per_pair + jb.slots * (int)sizeof(int));
+        lds = std::max(lds, jb.slots / 2 * per_pair + lds_flags_bytes_i8(jb.slots / 2));
         msg_per_block = std::max(msg_per_block, jb.slots / 2 * jb.E_pad * jb.Z);
         for (int f = 0; f < job_cw[j]; f += jb.slots)
             tasks.push_back(BatchTask{(int)j, f, std::min(jb.slots, job_cw[j] - f), 0});
@@ -200,7 +200,7 @@ int batch_async(const std::vector<BatchJob> &jobs, const std::vector<int> &job_c
     for (size_t j = 0; j < jobs.size(); ++j) {
         const BatchJob &jb = jobs[j];
         lds = std::max(lds, jb.slots / 2 * lds_bytes_i8_pair_post(jb.n_cols, jb.Z) +
-                                jb.slots * (int)sizeof(int));
+                                lds_flags_bytes_i8(jb.slots / 2));
         msg_per_block = std::max(msg_per_block, jb.slots / 2 * jb.E_pad * jb.Z);
         for (int f = 0; f < job_cw[j]; f += jb.slots)
             tasks.push_back(BatchTask{(int)j, f, std::min(jb.slots, job_cw[j] - f), 0});

@@ -87,23 +87,26 @@ struct MsgRow {
     uint32_t ro;                  // device: pair base; LDS: lane's edge-0 byte address
     uint32_t row;                 // device: byte offset of the row in the pair region
 
-    // Loads the row's (W + 1) / 2 message dwords into d.
-    template <int W>
-    __device__ inline void load(uint32_t *d, uint32_t u, int Z) const {
+    // Loads the row's message dwords d[C0 .. (W + 1) / 2) (device placement;
+    // LDS placement loads them all).
+    template <int W, int C0 = 0>
+    __device__ inline void load(uint32_t *d, uint32_t u, int Z, int wr = W) const {
         constexpr int ND = (W + 1) / 2;
         if constexpr (IN_LDS) {
+            // wr (<= W): the row's weight; messages from wr on are not read
 #pragma unroll
             for (int j = 0; j < ND; ++j) {
                 const uint32_t a = ro + 4u * (uint32_t)(j * Z);
-                const uint32_t lo = *reinterpret_cast<const uint16_t *>(lds + a);
+                const uint32_t lo =
+                    2 * j < wr ? *reinterpret_cast<const uint16_t *>(lds + a) : 0u;
                 const uint32_t hi =
-                    2 * j + 1 < W ? *reinterpret_cast<const uint16_t *>(lds + a + 2u * Z) : 0u;
+                    2 * j + 1 < wr ? *reinterpret_cast<const uint16_t *>(lds + a + 2u * Z) : 0u;
                 d[j] = lo | hi << 16;
             }
         } else {
             const uint32_t v = ro + u * (4u * ND);
 #pragma unroll
-            for (int c = 0; c < ND; c += 4) {
+            for (int c = C0; c < ND; c += 4) {
                 const uint32_t so = row + 4u * c;
                 if (ND - c >= 4) {
                     const auto q = __builtin_amdgcn_raw_buffer_load_b128(rsrc, v, so, 0);
@@ -120,20 +123,74 @@ struct MsgRow {
             }
         }
     }
+    // Device placement, rows of nd (runtime) dwords: loads the chunks of four
+    // dwords [C0, MAXD) that start below nd (a chunk may run past the row;
+    // those dwords are not used).
+    template <int MAXD, int C0>
+    __device__ inline void load_rt(uint32_t *d, uint32_t u, int nd) const {
+        const uint32_t v = ro + u * (4u * (uint32_t)nd);
+#pragma unroll
+        for (int c = C0; c < MAXD; c += 4) {
+            if (c >= nd) continue;
+            const uint32_t so = row + 4u * c;
+            if (MAXD - c >= 4) {
+                const auto q = __builtin_amdgcn_raw_buffer_load_b128(rsrc, v, so, 0);
+                d[c] = q[0], d[c + 1] = q[1], d[c + 2] = q[2], d[c + 3] = q[3];
+            } else if (MAXD - c == 3) {
+                const auto q = __builtin_amdgcn_raw_buffer_load_b96(rsrc, v, so, 0);
+                d[c] = q[0], d[c + 1] = q[1], d[c + 2] = q[2];
+            } else if (MAXD - c == 2) {
+                const auto q = __builtin_amdgcn_raw_buffer_load_b64(rsrc, v, so, 0);
+                d[c] = q[0], d[c + 1] = q[1];
+            } else {
+                d[c] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, v, so, 0);
+            }
+        }
+    }
+    // Device placement, rows of nd (runtime) dwords: stores dwords
+    // [c, c + n) with n in 1..4 decided at run time.
+    __device__ inline void store_rt(const uint32_t *d, uint32_t u, int nd, int c, int n) const {
+        typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+        typedef uint32_t v3u __attribute__((ext_vector_type(3)));
+        typedef uint32_t v2u __attribute__((ext_vector_type(2)));
+        const uint32_t v = ro + u * (4u * (uint32_t)nd), so = row + 4u * c;
+        if (n >= 4) {
+            const v4u q = {d[c], d[c + 1], d[c + 2], d[c + 3]};
+            __builtin_amdgcn_raw_buffer_store_b128(q, rsrc, v, so, 0);
+        } else if (n == 3) {
+            const v3u q = {d[c], d[c + 1], d[c + 2]};
+            __builtin_amdgcn_raw_buffer_store_b96(q, rsrc, v, so, 0);
+        } else if (n == 2) {
+            const v2u q = {d[c], d[c + 1]};
+            __builtin_amdgcn_raw_buffer_store_b64(q, rsrc, v, so, 0);
+        } else {
+            __builtin_amdgcn_raw_buffer_store_b32(d[c], rsrc, v, so, 0);
+        }
+    }
+    // Device placement: the first four message dwords of a row of nd dwords
+    // (whatever follows the row fills the rest; a read past the region's end
+    // returns zero).
+    __device__ inline void load4(uint32_t *d, uint32_t u, int nd) const {
+        const auto q =
+            __builtin_amdgcn_raw_buffer_load_b128(rsrc, ro + u * (4u * (uint32_t)nd), row, 0);
+        d[0] = q[0], d[1] = q[1], d[2] = q[2], d[3] = q[3];
+    }
     // Stores the n (1..4) message dwords d[c .. c+n) of the row (c and n are
     // constants once the caller's loop is unrolled).
     template <int W>
-    __device__ inline void store(const uint32_t *d, uint32_t u, int Z, int c, int n) const {
+    __device__ inline void store(const uint32_t *d, uint32_t u, int Z, int c, int n,
+                                 int wr = W) const {
         constexpr int ND = (W + 1) / 2;
         if constexpr (IN_LDS) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int j = c + i;
-                if (i >= n) break;
-                const uint32_t a = ro + 4u * (uint32_t)(j * Z);
-                *reinterpret_cast<uint16_t *>(lds + a) = (uint16_t)d[j];
-                if (2 * j + 1 < W)
-                    *reinterpret_cast<uint16_t *>(lds + a + 2u * Z) = (uint16_t)(d[j] >> 16);
+                if (i < n && j < ND) {
+                    const uint32_t a = ro + 4u * (uint32_t)(j * Z);
+                    *reinterpret_cast<uint16_t *>(lds + a) = (uint16_t)d[j];
+                    if (2 * j + 1 < wr)
+                        *reinterpret_cast<uint16_t *>(lds + a + 2u * Z) = (uint16_t)(d[j] >> 16);
+                }
             }
         } else {
             typedef uint32_t v4u __attribute__((ext_vector_type(4)));
@@ -156,6 +213,12 @@ struct MsgRow {
     }
 };
 
+// Device placement prefetches the first four message dwords (eight
+// messages) of the next row right after the current row: their memory
+// latency then overlaps the layer barrier and the next row's metadata and
+// posterior reads.
+constexpr int kPreDwords = 4;
+
 // v_perm selectors for the second pair word of a dword (bytes 2, 3) and for
 // packing two messages into one dword.
 constexpr uint32_t kUnpackHi = 0x030c020cu;  // dword -> (b2 << 8, b3 << 24)
@@ -167,34 +230,38 @@ constexpr uint32_t kPack2 = 0x07050301u;     // (R_k, R_k+1) -> pair words k, k+
 template <int K0, int K1, bool KEEP_GATHER>
 __device__ __forceinline__ void row_phase1(const uint8_t *__restrict__ smem, uint32_t lb,
                                            const uint32_t *rd, const uint32_t *md, uint32_t u,
-                                           int Z, uint32_t *xv, uint32_t *axv, uint32_t *la,
-                                           u16x2 &m1, u16x2 &m2, uint32_t &S) {
+                                           int Z, int wr, uint32_t *xv, uint32_t *axv,
+                                           uint32_t *la, u16x2 &m1, u16x2 &m2, uint32_t &S) {
     constexpr int n = K1 - K0;
     uint32_t lraw[n];
 #pragma unroll
     for (int i = 0; i < n; ++i) {
-        const uint32_t a = gather(md[K0 + i], lb, u, (uint32_t)Z);
-        if (KEEP_GATHER) la[K0 + i] = a;
-        lraw[i] = lds_ld16(smem, a);
+        if (K0 + i < wr) {  // wr: the row's weight (below K1 in the generic path)
+            const uint32_t a = gather(md[K0 + i], lb, u, (uint32_t)Z);
+            if (KEEP_GATHER) la[K0 + i] = a;
+            lraw[i] = lds_ld16(smem, a);
+        }
     }
 #pragma unroll
     for (int i = 0; i < n; ++i) {
-        const s16x2 L = as_s(perm(lraw[i], kUnpack));
         const int k = K0 + i;
-        const s16x2 Rm = as_s(perm(rd[k >> 1], (k & 1) ? kUnpackHi : kUnpack));
-        s16x2 x = __builtin_elementwise_sub_sat(L, Rm);
-        x = __builtin_elementwise_max(x, (s16x2){-127 * 256, -127 * 256});
-        const s16x2 ax = __builtin_elementwise_max(x, (s16x2){0, 0} - x);
-        const u16x2 axu = as_u(bits_of(ax));
-        m2 = __builtin_elementwise_min(m2, __builtin_elementwise_max(m1, axu));
-        m1 = __builtin_elementwise_min(m1, axu);
-        S ^= bits_of(x);
-        xv[K0 + i] = bits_of(x);
-        if (KEEP_GATHER) axv[K0 + i] = bits_of(ax);
+        if (k < wr) {
+            const s16x2 L = as_s(perm(lraw[i], kUnpack));
+            const s16x2 Rm = as_s(perm(rd[k >> 1], (k & 1) ? kUnpackHi : kUnpack));
+            s16x2 x = __builtin_elementwise_sub_sat(L, Rm);
+            x = __builtin_elementwise_max(x, (s16x2){-127 * 256, -127 * 256});
+            const s16x2 ax = __builtin_elementwise_max(x, (s16x2){0, 0} - x);
+            const u16x2 axu = as_u(bits_of(ax));
+            m2 = __builtin_elementwise_min(m2, __builtin_elementwise_max(m1, axu));
+            m1 = __builtin_elementwise_min(m1, axu);
+            S ^= bits_of(x);
+            xv[k] = bits_of(x);
+            if (KEEP_GATHER) axv[k] = bits_of(ax);
+        }
     }
 }
 
-// One block row of exactly W blocks for lane u: variable-to-check messages,
+// One block row of W blocks for lane u: variable-to-check messages,
 // min / second min / sign product, normalisation, check-to-variable
 // messages and posterior write-back, for both codewords of the pair.
 // Specialising on W keeps the row free of branches: the row's metadata
@@ -202,35 +269,47 @@ __device__ __forceinline__ void row_phase1(const uint8_t *__restrict__ smem, uin
 // any arithmetic. Rows wider than 10 blocks read in two halves and
 // recompute |x| and their gathers for the write-back, which keeps the
 // register count low enough for several pairs per CU.
-template <int W, bool IN_LDS, bool FIRST>
+// GEN: W is only an upper bound and wr the row's weight; blocks k >= wr are
+// skipped by scalar branches.
+template <int W, bool IN_LDS, bool FIRST, bool GEN = false>
 __device__ __forceinline__ void row_update_w(uint8_t *__restrict__ smem, uint32_t lb,
                                              const MsgRow<IN_LDS> &R, cmeta_t meta, int e0,
-                                             uint32_t u, int Z, u16x2 wgt, u16x2 off16) {
+                                             uint32_t u, int Z, u16x2 wgt, u16x2 off16,
+                                             const uint32_t *pre, int wr = W) {
     constexpr bool kWide = W > 10;
+    const int wrow = GEN ? wr : W;
     uint32_t md[W];
 #pragma unroll
-    for (int k = 0; k < W; ++k) md[k] = meta[e0 + k];
+    for (int k = 0; k < W; ++k) md[k] = meta[e0 + k];  // the table is padded
     // This row's check-to-variable messages (none in the first iteration).
     constexpr int ND = (W + 1) / 2;
+    const int nd = GEN ? (wr + 1) / 2 : ND;
     uint32_t rd[ND];
     if (FIRST) {
 #pragma unroll
         for (int j = 0; j < ND; ++j) rd[j] = 0;
+    } else if (IN_LDS) {
+        R.template load<W>(rd, u, Z, wrow);
     } else {
-        R.template load<W>(rd, u, Z);
+#pragma unroll
+        for (int j = 0; j < ND && j < kPreDwords; ++j) rd[j] = pre[j];
+        if (GEN)
+            R.template load_rt<ND, kPreDwords>(rd, u, nd);
+        else if (ND > kPreDwords)
+            R.template load<W, kPreDwords>(rd, u, Z);
     }
     uint32_t xv[W], axv[W], la[W];
     u16x2 m1 = {0x7FFF, 0x7FFF}, m2 = {0x7FFF, 0x7FFF};
     uint32_t S = 0;
     if constexpr (kWide) {
         constexpr int H = (W + 1) / 2;
-        row_phase1<0, H, false>(smem, lb, rd, md, u, Z, xv, axv, la, m1, m2, S);
+        row_phase1<0, H, false>(smem, lb, rd, md, u, Z, wrow, xv, axv, la, m1, m2, S);
         // keep the halves apart: the scheduler would otherwise issue every
         // read of the row up front and hold both halves' registers at once
         __builtin_amdgcn_sched_barrier(0);
-        row_phase1<H, W, false>(smem, lb, rd, md, u, Z, xv, axv, la, m1, m2, S);
+        row_phase1<H, W, false>(smem, lb, rd, md, u, Z, wrow, xv, axv, la, m1, m2, S);
     } else {
-        row_phase1<0, W, true>(smem, lb, rd, md, u, Z, xv, axv, la, m1, m2, S);
+        row_phase1<0, W, true>(smem, lb, rd, md, u, Z, wrow, xv, axv, la, m1, m2, S);
     }
     const u16x2 a1 = normalise(m1, off16, wgt);
     const u16x2 a2 = normalise(m2, off16, wgt);
@@ -245,6 +324,7 @@ __device__ __forceinline__ void row_update_w(uint8_t *__restrict__ smem, uint32_
     uint32_t rprev = 0;
 #pragma unroll
     for (int k = 0; k < W; ++k) {
+        if (k >= wrow) continue;
         const s16x2 x = as_s(xv[k]);
         const s16x2 ax = kWide ? __builtin_elementwise_max(x, (s16x2){0, 0} - x) : as_s(axv[k]);
         // t = 1 on the argmin edge (|x| == m1), else 0.
@@ -260,15 +340,21 @@ __device__ __forceinline__ void row_update_w(uint8_t *__restrict__ smem, uint32_
         lds_st16(smem, a, perm(bits_of(Ln), kPack));
         // messages k-1 and k share a dword (an odd row's last dword pads
         // with a zero pair word); store each group of 4 dwords once complete
+        const int j = k >> 1;
         if (k & 1) {
-            sd[k >> 1] = __builtin_amdgcn_perm(bits_of(Rn), rprev, kPack2);
-        } else if (k == W - 1) {
-            sd[k >> 1] = perm(bits_of(Rn), kPack);
+            sd[j] = __builtin_amdgcn_perm(bits_of(Rn), rprev, kPack2);
         } else {
             rprev = bits_of(Rn);
+            if (k == wrow - 1) sd[j] = perm(bits_of(Rn), kPack);
         }
-        const int j = k >> 1;
-        if ((k & 1) || k == W - 1) {
+        if (GEN && IN_LDS) {
+            if ((k & 1) || k == wrow - 1) R.template store<W>(sd, u, Z, j, 1, wrow);
+        } else if (GEN) {
+            if ((k & 1) || k == wrow - 1) {
+                if ((j & 3) == 3) R.store_rt(sd, u, nd, j & ~3, 4);
+                else if (j == nd - 1) R.store_rt(sd, u, nd, j & ~3, nd - (j & ~3));
+            }
+        } else if ((k & 1) || k == W - 1) {
             if ((j & 3) == 3) R.template store<W>(sd, u, Z, j & ~3, 4);
             else if (j == ND - 1) R.template store<W>(sd, u, Z, j & ~3, ND - (j & ~3));
         }
@@ -296,13 +382,37 @@ __device__ __forceinline__ uint32_t row_parity_w(const uint8_t *__restrict__ sme
 template <int W, int WMAX, bool IN_LDS, bool FIRST>
 __device__ __forceinline__ void row_update(int w, uint8_t *smem, uint32_t lb,
                                            const MsgRow<IN_LDS> &R, cmeta_t meta, int e0,
-                                           uint32_t u, int Z, u16x2 wgt, u16x2 off16) {
+                                           uint32_t u, int Z, u16x2 wgt, u16x2 off16,
+                                           const uint32_t *pre) {
     if constexpr (W <= WMAX) {
         if (w == W) {
-            row_update_w<W, IN_LDS, FIRST>(smem, lb, R, meta, e0, u, Z, wgt, off16);
+            row_update_w<W, IN_LDS, FIRST>(smem, lb, R, meta, e0, u, Z, wgt, off16, pre);
             return;
         }
-        row_update<W + 1, WMAX, IN_LDS, FIRST>(w, smem, lb, R, meta, e0, u, Z, wgt, off16);
+        row_update<W + 1, WMAX, IN_LDS, FIRST>(w, smem, lb, R, meta, e0, u, Z, wgt, off16, pre);
+    }
+}
+
+// Row update for any weight up to WMAX: exact code for weights up to 10
+// (and 19, the core rows of BG1-shaped graphs); other wide rows run through
+// one bound-WMAX body with scalar guards, which keeps the kernel's register
+// allocation to a few row shapes.
+template <int WMAX, bool IN_LDS, bool FIRST>
+__device__ __forceinline__ void row_update_any(int w, uint8_t *smem, uint32_t lb,
+                                               const MsgRow<IN_LDS> &R, cmeta_t meta, int e0,
+                                               uint32_t u, int Z, u16x2 wgt, u16x2 off16,
+                                               const uint32_t *pre) {
+    if constexpr (WMAX <= 10) {
+        row_update<2, WMAX, IN_LDS, FIRST>(w, smem, lb, R, meta, e0, u, Z, wgt, off16, pre);
+    } else {
+        constexpr int kCore = WMAX >= 19 ? 19 : WMAX;
+        if (w <= 10)
+            row_update<2, 10, IN_LDS, FIRST>(w, smem, lb, R, meta, e0, u, Z, wgt, off16, pre);
+        else if (w == kCore)
+            row_update_w<kCore, IN_LDS, FIRST>(smem, lb, R, meta, e0, u, Z, wgt, off16, pre);
+        else
+            row_update_w<WMAX, IN_LDS, FIRST, true>(smem, lb, R, meta, e0, u, Z, wgt, off16,
+                                                    pre, w);
     }
 }
 
@@ -347,8 +457,9 @@ __device__ inline void write_outputs(const BlockWork &bw, const uint8_t *Lp, int
     // An opaque copy of the pair index: keeps the compiler from hoisting
     // this (rarely run) output addressing out of the iteration loop, where
     // it would hold registers through every layer.
-    __asm__ volatile("" : "+v"(pair), "+v"(u));
-    const int Z = bw.Z, bpc = Z / 8, nbytes = bw.kb * bpc;
+    int Z = bw.Z;
+    __asm__ volatile("" : "+v"(pair), "+v"(u), "+s"(Z));
+    const int bpc = Z / 8, nbytes = bw.kb * bpc;
     const int kbytes = bw.kb * Z / 8;
     const int cw0 = 2 * pair;
 #pragma unroll 1
@@ -424,15 +535,24 @@ template <int WMAX, bool IN_LDS, bool FIRST>
 __device__ __forceinline__ void layer_pass(const BlockWork &bw, uint8_t *smem, uint32_t lb,
                                            uint32_t ro, __amdgpu_buffer_rsrc_t rsrc,
                                            crow_t row_ptr, cmeta_t meta, const uint8_t *wrow,
-                                           uint32_t u, bool busy, u16x2 off16) {
+                                           uint32_t u, bool busy, u16x2 off16, uint32_t *pre) {
     const int Z = bw.Z;
+    crow_t row_pad = (crow_t)bw.row_pad;
     for (int r = 0; r < bw.rows; ++r) {
         const int e0 = row_ptr[r], w = row_ptr[r + 1] - e0;
         const int wt = wrow ? row_weight(wrow, r) : bw.beta;
         const u16x2 wgt = {(unsigned short)wt, (unsigned short)wt};
-        const MsgRow<IN_LDS> R =
-            msg_row<IN_LDS>(smem, ro, rsrc, e0, IN_LDS ? 0 : ((crow_t)bw.row_pad)[r], Z);
-        if (busy) row_update<2, WMAX, IN_LDS, FIRST>(w, smem, lb, R, meta, e0, u, Z, wgt, off16);
+        const MsgRow<IN_LDS> R = msg_row<IN_LDS>(smem, ro, rsrc, e0, IN_LDS ? 0 : row_pad[r], Z);
+        // the next row: r + 1, or row 0 of the next iteration; its messages
+        // exist once this is not the first iteration, or for row 0
+        const bool last = r + 1 == bw.rows;
+        const int rn = last ? 0 : r + 1;
+        if (busy) {
+            row_update_any<WMAX, IN_LDS, FIRST>(w, smem, lb, R, meta, e0, u, Z, wgt, off16, pre);
+            if (!IN_LDS && (last || !FIRST))
+                msg_row<IN_LDS>(smem, ro, rsrc, 0, row_pad[rn], Z)
+                    .load4(pre, u, (row_pad[rn + 1] - row_pad[rn]) / 2);
+        }
         __syncthreads();
     }
 }
@@ -489,6 +609,7 @@ __device__ __forceinline__ void decode_block(const BlockWork &bw, uint8_t *smem,
 
     const u16x2 off16 = {(unsigned short)(bw.offset << 8), (unsigned short)(bw.offset << 8)};
     bool doneA = !validA, doneB = !validB;
+    uint32_t pre[kPreDwords] = {0u, 0u, 0u, 0u};
     for (int t = 1; t <= bw.max_iter; ++t) {
         const uint8_t *wrow = nullptr;
         if (bw.wq) wrow = bw.wq + (size_t)((t < bw.w_iters ? t : bw.w_iters) - 1) * bw.w_stride;
@@ -496,12 +617,14 @@ __device__ __forceinline__ void decode_block(const BlockWork &bw, uint8_t *smem,
         // the first iteration has no check-to-variable messages yet
         if (t == 1)
             layer_pass<WMAX, IN_LDS, true>(bw, smem, lb, ro, rsrc, row_ptr, meta, wrow, u, busy,
-                                           off16);
+                                           off16, pre);
         else
             layer_pass<WMAX, IN_LDS, false>(bw, smem, lb, ro, rsrc, row_ptr, meta, wrow, u, busy,
-                                            off16);
+                                            off16, pre);
         if (bw.early_exit || t == bw.max_iter) {
-            if ((int)threadIdx.x < 2 * bw.slots) flags[threadIdx.x] = 0;
+            // flags[0, 2*slots): a failing check per codeword; flags[2*slots]:
+            // stays 1 while every codeword of the workgroup is finished
+            if ((int)threadIdx.x <= 2 * bw.slots) flags[threadIdx.x] = (int)threadIdx.x == 2 * bw.slots;
             __syncthreads();
             if (busy)
                 syndrome_mark<WMAX>(smem, lb, row_ptr, meta, bw.rows, u, Z, flags + 2 * p, !doneA,
@@ -520,7 +643,9 @@ __device__ __forceinline__ void decode_block(const BlockWork &bw, uint8_t *smem,
                 write_outputs(bw, Lp, p, u, (finA ? 1 : 0) | (finB ? 2 : 0), t, holdsA, holdsB);
             doneA = doneA || finA;
             doneB = doneB || finB;
-            if (__syncthreads_and(doneA && doneB)) break;
+            if (!(doneA && doneB)) flags[2 * bw.slots] = 0;
+            __syncthreads();
+            if (flags[2 * bw.slots]) break;
         }
     }
 }
@@ -564,7 +689,7 @@ hipError_t launch_w(const DecodeLaunch &p, hipStream_t stream) {
     const int per_pair = IN_LDS ? lds_bytes_i8_pair(p.n_cols, p.E, p.Z)
                                 : lds_bytes_i8_pair_post(p.n_cols, p.Z);
     const int pairs = p.cpw / 2;
-    const int lds = pairs * per_pair + p.cpw * (int)sizeof(int);
+    const int lds = pairs * per_pair + lds_flags_bytes_i8(pairs);
     static bool attr_set = false;
     if (!attr_set) {
         // Opt in to more than the default 64 KiB of dynamic LDS.

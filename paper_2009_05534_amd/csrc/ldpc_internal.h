@@ -132,6 +132,9 @@ __host__ __device__ inline int lds_bytes_i8_pair(int n_cols, int E, int Z) {
     return 2 * (n_cols + E) * Z;
 }
 __host__ __device__ inline int lds_bytes_i8_pair_post(int n_cols, int Z) { return 2 * n_cols * Z; }
+// The int8 workgroup's flag words after its pairs: one syndrome flag per
+// codeword and one workgroup-wide "all finished" word (plus padding).
+__host__ __device__ inline int lds_flags_bytes_i8(int pairs) { return 4 * (2 * pairs + 2); }
 __host__ __device__ inline int lds_bytes_f16(int n_cols, int Z) { return n_cols * Z * 2; }
 
 // Per-block metadata for the int8 pair kernel: bits [0, 16) the byte offset

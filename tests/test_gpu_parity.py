@@ -5,6 +5,8 @@ int8: bit-exact hard decisions, final posteriors, iteration counts and
 success flags. binary16: identical hard decisions, iteration counts and
 flags, posteriors within 1e-2 relative error (denominator max(|ref|, 1)).
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -228,4 +230,44 @@ def test_i8_message_placements_agree(bg, Z, rows):
                     gpu_decode(bg, Z, rows, b.q, msg_placement=placement, cw_per_block=cpw)
                 continue
             got = gpu_decode(bg, Z, rows, b.q, msg_placement=placement, cw_per_block=cpw)
+            assert_i8_equal(got, ref)
+
+
+def _wide_graph(Z, weights, kb, seed):
+    """Random base graph with the given row weights (columns and shifts from
+    the seed), registered as (bg=1, Z) with a lift the other tests do not
+    use. Rows wider than 10 blocks other than 19 take the decoder's
+    bound-weight path; weights above 20 its widest kernel."""
+    from synth import make_toy_graph
+    from paper_2009_05534_amd import ldpc
+    rng = np.random.default_rng(seed)
+    M, N = len(weights), kb + len(weights)
+    base = -np.ones((M, N), np.int64)
+    for r, w in enumerate(weights):
+        # row r may use the information columns and parity columns up to its
+        # own (the core rows share the first four): nested sub-codes
+        n_avail = kb + max(r + 1, 4)
+        base[r, rng.choice(n_avail, size=w, replace=False)] = rng.integers(0, Z, size=w)
+    g = dataclasses.replace(make_toy_graph(base, Z, kb, n_punct=2), bg=1)
+    ldpc.register(g)
+    return g
+
+
+@pytest.mark.parametrize("Z,weights,kb", [
+    (40, [11, 12, 13, 14, 15, 16, 17, 18, 20, 19, 3, 10], 20),
+    (24, [21, 25, 32, 8, 30, 2], 28),
+])
+def test_i8_wide_rows(Z, weights, kb):
+    g = _wide_graph(Z, weights, kb, seed=Z)
+    rng = np.random.default_rng(Z + 1)
+    # random channel values (no codeword: run to the iteration limit) and,
+    # in the first codewords, noisy observations of the all-zero codeword
+    # (a codeword of every graph), which settle after a few iterations
+    q = np.clip(rng.normal(0, 40, (13, g.T)), -128, 127).astype(np.int8)
+    mean = np.array([25, 30, 40, 50, 60])[:, None]
+    q[:5] = np.clip(rng.normal(mean, 16, (5, g.T)), -128, 127).astype(np.int8)
+    for placement in ("lds", "device"):
+        for early in (True, False):
+            ref = oracle_i8(g, q, early_exit=early)
+            got = gpu_decode(1, Z, g.M, q, msg_placement=placement, early_exit=early)
             assert_i8_equal(got, ref)
