@@ -204,17 +204,21 @@ __device__ __forceinline__ uint32_t row_parity(int w, const uint32_t *Lw, const 
     return 0;
 }
 
-// Nonzero if some check of lane u's rows fails.
+// Syndrome check of an unfinished codeword: a failing check of lane u's rows
+// marks the codeword in *fl (its LDS flag, zero on entry; every marking lane
+// stores the same 1). One failing check decides the codeword, so a wave stops
+// sweeping the rows once every codeword its lanes serve is marked; only a
+// codeword whose checks all hold needs the full sweep.
 template <int WMAX>
-__device__ inline bool syndrome_fails(const uint32_t *__restrict__ Lw,
-                                      const int32_t *__restrict__ row_ptr,
-                                      const uint32_t *__restrict__ meta, int rows, int u, int Zh) {
-    uint32_t bad = 0;
+__device__ inline void syndrome_mark(const uint32_t *__restrict__ Lw,
+                                     const int32_t *__restrict__ row_ptr,
+                                     const uint32_t *__restrict__ meta, int rows, int u, int Zh,
+                                     volatile int *fl) {
     for (int r = 0; r < rows; ++r) {
         const int e0 = row_ptr[r], w = row_ptr[r + 1] - e0;
-        bad |= row_parity<2, WMAX>(w, Lw, meta, e0, u, Zh);
+        if (row_parity<2, WMAX>(w, Lw, meta, e0, u, Zh)) *fl = 1;
+        if (__ballot(*fl == 0) == 0) break;
     }
-    return bad != 0;
 }
 
 template <int WMAX>
@@ -268,8 +272,7 @@ __global__ __launch_bounds__(512) void decode_f16_kernel(DecodeLaunch p,
         if (p.early_exit || t == p.max_iter) {
             if ((int)threadIdx.x < p.cpw) flags[threadIdx.x] = 0;
             __syncthreads();
-            if (!done && syndrome_fails<WMAX>(Lw, row_ptr, meta, p.rows, u, Zh))
-                atomicOr(&flags[slot], 1);
+            if (!done) syndrome_mark<WMAX>(Lw, row_ptr, meta, p.rows, u, Zh, flags + slot);
             __syncthreads();
             const bool holds = flags[slot] == 0;
             if (!done) {

@@ -528,8 +528,8 @@ __device__ inline MsgRow<IN_LDS> msg_row(uint8_t *smem, uint32_t ro,
     return R;
 }
 
-// One iteration's sweep over the block rows (layers) in order, one
-// workgroup barrier per layer. wrow: this iteration's per-row Q1.7 weights
+// One iteration's sweep over the block rows (layers) in order, a workgroup
+// barrier between layers that share a block column. wrow: this iteration's per-row Q1.7 weights
 // or null (bw.beta for every row).
 template <int WMAX, bool IN_LDS, bool FIRST>
 __device__ __forceinline__ void layer_pass(const BlockWork &bw, uint8_t *smem, uint32_t lb,
@@ -538,6 +538,9 @@ __device__ __forceinline__ void layer_pass(const BlockWork &bw, uint8_t *smem, u
                                            uint32_t u, bool busy, u16x2 off16, uint32_t *pre) {
     const int Z = bw.Z;
     crow_t row_pad = (crow_t)bw.row_pad;
+    // a barrier only where the next row shares a column with the rows since
+    // the last one (layer groups), and after the last row
+    const uint64_t bar = (bw.groups >> 1) | (1ull << (bw.rows - 1));
     for (int r = 0; r < bw.rows; ++r) {
         const int e0 = row_ptr[r], w = row_ptr[r + 1] - e0;
         const int wt = wrow ? row_weight(wrow, r) : bw.beta;
@@ -553,7 +556,7 @@ __device__ __forceinline__ void layer_pass(const BlockWork &bw, uint8_t *smem, u
                 msg_row<IN_LDS>(smem, ro, rsrc, 0, row_pad[rn], Z)
                     .load4(pre, u, (row_pad[rn + 1] - row_pad[rn]) / 2);
         }
-        __syncthreads();
+        if ((bar >> r) & 1) __syncthreads();
     }
 }
 
@@ -669,6 +672,7 @@ __global__ __launch_bounds__(768) __attribute__((amdgpu_waves_per_eu(5))) void d
                     : reinterpret_cast<uint16_t *>(p.msg) + (size_t)(first / 2) * p.E_pad * p.Z;
     bw.row_pad = p.row_pad;
     bw.E_pad = p.E_pad;
+    bw.groups = p.groups;
     bw.wq = p.wq;
     bw.w_iters = p.w_iters;
     bw.w_stride = p.rows;
@@ -753,6 +757,7 @@ __global__ __launch_bounds__(kBatchLanes) __attribute__((amdgpu_waves_per_eu(5))
         bw.msg = msg_ws + (size_t)blockIdx.x * msg_per_block;
         bw.row_pad = jb.row_pad;
         bw.E_pad = jb.E_pad;
+        bw.groups = jb.groups;
         bw.wq = jb.wq;
         bw.w_iters = jb.w_iters;
         bw.w_stride = jb.w_stride;

@@ -244,6 +244,7 @@ int ldpc_decode_ex(const ldpc_args *a) {
         p.Z = g.Z;
         p.E = E;
         p.wmax = wmax;
+        p.groups = layer_groups(g.row_ptr.data(), g.col.data(), a->rows);
         lds_cap = max_lds_bytes();
     }
     p.llr = a->llr_in;
@@ -407,6 +408,7 @@ int batch_jobs(const ldpc_job *jobs, int n_jobs, std::vector<BatchJob> &bj,
         b.row_ptr = t->row_ptr;
         b.row_pad = t->row_pad;
         b.E_pad = padded_row_ptr(g)[jb.rows];
+        b.groups = layer_groups(g.row_ptr.data(), g.col.data(), jb.rows);
         b.meta = t->meta_i8;
         b.wq = jb.wq;
         b.w_iters = jb.wq ? jb.wq_iters : 0;

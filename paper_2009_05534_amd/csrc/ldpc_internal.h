@@ -57,6 +57,8 @@ struct DecodeLaunch {
     int beta, offset;         // int8: Q1.7 beta and offset; f16: bit patterns
     int cpw;                  // codewords per workgroup (int8: even, two per pair)
     int wmax;                 // max row weight over the kept rows
+    uint64_t groups;          // int8: bit r set = row r starts a new layer
+                              // group (see layer_groups)
 };
 
 // A workgroup's share of an int8 decode: n codewords of one shape held as
@@ -74,6 +76,7 @@ struct BlockWork {
                               // (the row weight rounded up to even) messages
                               // contiguous at u*Wp
     const int32_t *row_pad;   // even-padded row starts
+    uint64_t groups;          // bit r: row r needs a barrier before it
     const uint8_t *wq;        // per-(iteration, row) weights or null
     int w_iters, w_stride;    // weight rows and row stride
     int n, slots;             // codewords here; codeword pairs of the block
@@ -94,6 +97,7 @@ struct BatchJob {
     const int32_t *row_pad;
     const uint32_t *meta;
     const uint8_t *wq;
+    uint64_t groups;
     int w_iters, w_stride;
     int rows, n_cols, kb, Z, E, E_pad, slots;
 };
@@ -136,6 +140,26 @@ __host__ __device__ inline int lds_bytes_i8_pair_post(int n_cols, int Z) { retur
 // codeword and one workgroup-wide "all finished" word (plus padding).
 __host__ __device__ inline int lds_flags_bytes_i8(int pairs) { return 4 * (2 * pairs + 2); }
 __host__ __device__ inline int lds_bytes_f16(int n_cols, int Z) { return n_cols * Z * 2; }
+
+// Layer groups: consecutive block rows that share no block column read and
+// write disjoint posteriors, so they may follow each other without a
+// workgroup barrier and the result is the one of the strictly sequential
+// layered schedule. Greedy from row 0: bit r is set when row r shares a
+// column with a row of the current group (row 0 always starts one).
+inline uint64_t layer_groups(const int32_t *row_ptr, const int16_t *col, int rows) {
+    uint64_t bits = 1, used[2] = {0, 0};  // columns < 128 as a bit set
+    for (int r = 0; r < rows; ++r) {
+        uint64_t cur[2] = {0, 0};
+        for (int e = row_ptr[r]; e < row_ptr[r + 1]; ++e) cur[col[e] >> 6] |= 1ull << (col[e] & 63);
+        if (r > 0 && ((cur[0] & used[0]) | (cur[1] & used[1]))) {
+            bits |= 1ull << r;
+            used[0] = used[1] = 0;
+        }
+        used[0] |= cur[0];
+        used[1] |= cur[1];
+    }
+    return bits;
+}
 
 // Per-block metadata for the int8 pair kernel: bits [0, 16) the byte offset
 // 2(c*Z + s) of variable s of column c in a pair's posteriors, bits

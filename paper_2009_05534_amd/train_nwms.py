@@ -31,9 +31,9 @@ TRAIN_SEED, HELDOUT_SEED = 4, 5
 
 
 def _train_chunk(args):
-    bg, Z, start, n = args
+    bg, Z, start, n, lo, hi = args
     g = make_graph(bg, Z)
-    ebn0 = stream(TRAIN_SEED, 9, start).uniform(0.5, 2.0, n)
+    ebn0 = stream(TRAIN_SEED, 9, start).uniform(lo, hi, n)
     b = make_batch(g, n, ebn0, TRAIN_SEED, start=start)
     return b.q, b.c
 
@@ -80,6 +80,8 @@ def main():
     ap.add_argument("--n-train", type=int, default=200_000)
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--lr", type=float, default=1e-2)
+    ap.add_argument("--ebn0-lo", type=float, default=0.5, help="training Eb/N0 range (dB)")
+    ap.add_argument("--ebn0-hi", type=float, default=2.0)
     ap.add_argument("--eval-n", type=int, default=20_000, help="held-out codewords per point")
     ap.add_argument("--eval-points", default="1.0,1.25,1.5,1.75,2.0")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
@@ -102,7 +104,8 @@ def main():
     chunk = args.batch * 8
     starts = list(range(0, args.n_train, chunk))
     t0 = time.time()
-    futs = [pool.submit(_train_chunk, (args.bg, args.Z, s, min(chunk, args.n_train - s)))
+    rng_db = (args.ebn0_lo, args.ebn0_hi)
+    futs = [pool.submit(_train_chunk, (args.bg, args.Z, s, min(chunk, args.n_train - s), *rng_db))
             for s in starts[:2]]
     nxt = 2
     seen = 0
@@ -111,7 +114,7 @@ def main():
         if nxt < len(starts):
             s = starts[nxt]
             futs.append(pool.submit(_train_chunk, (args.bg, args.Z, s,
-                                                   min(chunk, args.n_train - s))))
+                                                   min(chunk, args.n_train - s), *rng_db)))
             nxt += 1
         for i in range(0, q.shape[0], args.batch):
             loss = tr.step(q[i:i + args.batch], c[i:i + args.batch])
@@ -121,12 +124,13 @@ def main():
                       f"w[mean] {tr.w.mean():.4f} {time.time() - t0:.0f}s", flush=True)
     train_s = time.time() - t0
     tr.save(args.out, g.digest(), extra={"n_train": seen, "batch": args.batch,
-                                          "train_seconds": train_s})
+                                          "train_seconds": train_s, "ebn0_db": list(rng_db)})
     print(f"[train] saved {args.out} after {seen} codewords in {train_s:.0f}s", flush=True)
     points = [float(x) for x in args.eval_points.split(",")]
     t1 = time.time()
     ev = evaluate(pool, args.bg, args.Z, args.rows, tr.wq, points, args.eval_n, 2048)
     summary = {"n_train": seen, "steps": tr.opt.t, "train_seconds": round(train_s, 1),
+               "train_ebn0_db": list(rng_db), "lr": args.lr,
                "eval_seconds": round(time.time() - t1, 1), "eval": ev,
                "loss_first": tr.history[0]["loss"], "loss_last": tr.history[-1]["loss"]}
     with open(os.path.splitext(args.out)[0] + "_eval.json", "w") as f:
