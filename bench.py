@@ -286,9 +286,12 @@ def main():
         log("serving sweep")
         from paper_2009_05534_amd import serve, nwms
         wpath = os.path.join(ROOT, "paper_2009_05534_amd", "weights", "nwms_bg1_z384.npz")
-        wq = nwms.load_weights(wpath)[0] if os.path.exists(wpath) else None
+        wq, shapes = None, None
+        if os.path.exists(wpath):
+            wq, meta = nwms.load_weights(wpath)
+            shapes = [(meta["Z"], meta["rows"])]
         blocks = serve.make_trace(600, seed=6)
-        srv = serve.Server(weights_bg1=wq, n_slots=4, mem_budget=256 << 20)
+        srv = serve.Server(weights_bg1=wq, n_slots=4, mem_budget=256 << 20, learned_shapes=shapes)
         srv.run(serve.rescale(blocks[:100], 1e4))
         result["serving"] = [srv.run(serve.rescale(blocks, r)) for r in (2e4, 1e5)]
 

@@ -541,22 +541,33 @@ __device__ __forceinline__ void layer_pass(const BlockWork &bw, uint8_t *smem, u
     // a barrier only where the next row shares a column with the rows since
     // the last one (layer groups), and after the last row
     const uint64_t bar = (bw.groups >> 1) | (1ull << (bw.rows - 1));
+    // Row bounds travel one row ahead in scalar registers, so a row's block
+    // metadata loads need not wait for its bounds after the barrier.
+    int e0 = row_ptr[0], e1 = row_ptr[1], p0 = IN_LDS ? 0 : row_pad[0];
+    int p1 = IN_LDS ? 0 : row_pad[1];
     for (int r = 0; r < bw.rows; ++r) {
-        const int e0 = row_ptr[r], w = row_ptr[r + 1] - e0;
-        const int wt = wrow ? row_weight(wrow, r) : bw.beta;
-        const u16x2 wgt = {(unsigned short)wt, (unsigned short)wt};
-        const MsgRow<IN_LDS> R = msg_row<IN_LDS>(smem, ro, rsrc, e0, IN_LDS ? 0 : row_pad[r], Z);
         // the next row: r + 1, or row 0 of the next iteration; its messages
         // exist once this is not the first iteration, or for row 0
         const bool last = r + 1 == bw.rows;
         const int rn = last ? 0 : r + 1;
+        const int e2 = last ? row_ptr[1] : row_ptr[r + 2];
+        const int p2 = IN_LDS ? 0 : (last ? row_pad[1] : row_pad[r + 2]);
+        const int en = last ? row_ptr[0] : e1, pn = IN_LDS ? 0 : (last ? row_pad[0] : p1);
+        const int w = e1 - e0;
+        const int wt = wrow ? row_weight(wrow, r) : bw.beta;
+        const u16x2 wgt = {(unsigned short)wt, (unsigned short)wt};
+        const MsgRow<IN_LDS> R = msg_row<IN_LDS>(smem, ro, rsrc, e0, p0, Z);
         if (busy) {
             row_update_any<WMAX, IN_LDS, FIRST>(w, smem, lb, R, meta, e0, u, Z, wgt, off16, pre);
             if (!IN_LDS && (last || !FIRST))
-                msg_row<IN_LDS>(smem, ro, rsrc, 0, row_pad[rn], Z)
-                    .load4(pre, u, (row_pad[rn + 1] - row_pad[rn]) / 2);
+                msg_row<IN_LDS>(smem, ro, rsrc, 0, pn, Z).load4(pre, u, (p2 - pn) / 2);
         }
         if ((bar >> r) & 1) __syncthreads();
+        e0 = en;
+        e1 = e2;
+        p0 = pn;
+        p1 = p2;
+        (void)rn;
     }
 }
 

@@ -68,6 +68,10 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built; run paper_2009_05534_amd/build.py")
+        # torch first: the library then binds to the HIP runtime torch has
+        # loaded, so the process runs one runtime whichever module is
+        # imported first (two runtimes do not share the device).
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         P, I = ctypes.c_void_p, ctypes.c_int
         L.ldpc_set_graph.argtypes = [I, I, I, I, P, P, P]

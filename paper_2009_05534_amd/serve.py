@@ -9,9 +9,9 @@ order for as long as the device-memory budget for check-to-variable
 messages allows, and launches them as ONE persistent mixed-shape decode
 (ldpc.decode_batch_async). Blocks that arrive while other launches run are
 admitted as soon as a slot and memory free up, so their work overlaps on the
-device. BG1 blocks are decoded with the learned per-(iteration, row) weights
-when given; codewords whose checks fail are decoded again with plain
-normalised min-sum (beta = 3/4) as the fallback. A block's latency runs from
+device. Blocks of the shape the learned per-(iteration, row) weights were
+trained for are decoded with them; their codewords whose checks fail are
+decoded again with plain normalised min-sum (beta = 3/4) as the fallback. A block's latency runs from
 its arrival to the host seeing its last launch complete.
 """
 from __future__ import annotations
@@ -83,7 +83,10 @@ def message_bytes(bg: int, Z: int, rows: int, n_cw: int) -> int:
 class Server:
     def __init__(self, weights_bg1: np.ndarray | None = None, n_slots: int = 4,
                  mem_budget: int = 256 << 20, max_iter: int = 10, max_blocks_per_launch: int = 256,
-                 device: str = "cuda:0"):
+                 device: str = "cuda:0", learned_shapes=None):
+        """learned_shapes: the (Z, rows) BG1 shapes the weights apply to (the
+        shape they were trained on); None applies them to every BG1 block
+        (first `rows` columns)."""
         import torch
         from . import ldpc
         self.ldpc = ldpc
@@ -96,9 +99,12 @@ class Server:
         self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(n_slots)]
         self._w_full = None if weights_bg1 is None else np.ascontiguousarray(weights_bg1, np.uint8)
         self._w_dev: dict[int, object] = {}
+        self._learned = None if learned_shapes is None else set(map(tuple, learned_shapes))
 
-    def _weights(self, bg: int, rows: int):
+    def _weights(self, bg: int, rows: int, Z: int | None = None):
         if self._w_full is None or bg != 1:
+            return None
+        if self._learned is not None and (Z, rows) not in self._learned:
             return None
         if rows not in self._w_dev:
             w = np.ascontiguousarray(self._w_full[:, :rows])
@@ -124,7 +130,7 @@ class Server:
         ldpc = self.ldpc
         jobs = []
         for b in batch:
-            w = None if plain else self._weights(b.bg, b.rows)
+            w = None if plain else self._weights(b.bg, b.rows, b.Z)
             jobs.append(ldpc.BatchJob(b._llr, b.bg, b.Z, b.rows, weights=w, out_bits=b._bits,
                                       out_iters=b._iters, out_ok=b._ok))
         return jobs
@@ -160,7 +166,8 @@ class Server:
                         # the flags were copied to pinned memory on the
                         # launch's stream before its event: no device sync
                         ok = b._ok_host.numpy().astype(bool)
-                        if not plain and self._weights(b.bg, b.rows) is not None and not ok.all():
+                        if (not plain and self._weights(b.bg, b.rows, b.Z) is not None
+                                and not ok.all()):
                             b.fallback = True
                             fallback.append(b)
                         else:
@@ -224,7 +231,7 @@ class Server:
         for failures), for checking results against the mixed run."""
         ldpc, torch = self.ldpc, self.torch
         llr = torch.from_numpy(b.q).to(self.dev)
-        w = self._weights(b.bg, b.rows)
+        w = self._weights(b.bg, b.rows, b.Z)
         bits, iters, ok, _ = ldpc.decode(llr, b.bg, b.Z, b.rows, max_iter=self.max_iter,
                                          weights=w, msg_placement="device")
         if w is not None and not bool(ok.all()):
@@ -249,14 +256,16 @@ def main():
     ap.add_argument("--seed", type=int, default=6)
     args = ap.parse_args()
     from . import ldpc, nwms
-    wq = None
+    wq, shapes = None, None
     if args.weights and os.path.exists(args.weights):
-        wq, _ = nwms.load_weights(args.weights)
+        wq, meta = nwms.load_weights(args.weights)
+        shapes = [(meta["Z"], meta["rows"])]
     blocks = make_trace(args.blocks, seed=args.seed)
     for bg in (1, 2):
         for Z in LIFTS:
             ldpc.register(make_graph(bg, Z))
-    srv = Server(weights_bg1=wq, n_slots=args.slots, mem_budget=args.mem_mib << 20)
+    srv = Server(weights_bg1=wq, n_slots=args.slots, mem_budget=args.mem_mib << 20,
+                 learned_shapes=shapes)
     srv.run(rescale(blocks[:200], 1e4))  # warm-up
     for r in [float(x) for x in args.rates.split(",")]:
         st = srv.run(rescale(blocks, r))
