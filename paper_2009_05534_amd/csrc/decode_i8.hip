@@ -86,6 +86,7 @@ struct MsgRow {
     uint8_t *lds;                 // LDS placement: the LDS array
     uint32_t ro;                  // device: pair base; LDS: lane's edge-0 byte address
     uint32_t row;                 // device: byte offset of the row in the pair region
+    bool keep;                    // false in the last iteration: nothing reads them again
 
     // Loads the row's message dwords d[C0 .. (W + 1) / 2) (device placement;
     // LDS placement loads them all).
@@ -150,6 +151,7 @@ struct MsgRow {
     // Device placement, rows of nd (runtime) dwords: stores dwords
     // [c, c + n) with n in 1..4 decided at run time.
     __device__ inline void store_rt(const uint32_t *d, uint32_t u, int nd, int c, int n) const {
+        if (!keep) return;
         typedef uint32_t v4u __attribute__((ext_vector_type(4)));
         typedef uint32_t v3u __attribute__((ext_vector_type(3)));
         typedef uint32_t v2u __attribute__((ext_vector_type(2)));
@@ -181,6 +183,7 @@ struct MsgRow {
     __device__ inline void store(const uint32_t *d, uint32_t u, int Z, int c, int n,
                                  int wr = W) const {
         constexpr int ND = (W + 1) / 2;
+        if (!keep) return;
         if constexpr (IN_LDS) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
@@ -517,7 +520,7 @@ __device__ inline int row_weight(const uint8_t *wrow, int r) {
 template <bool IN_LDS>
 __device__ inline MsgRow<IN_LDS> msg_row(uint8_t *smem, uint32_t ro,
                                          __amdgpu_buffer_rsrc_t rsrc, int e0, int p0, int Z) {
-    MsgRow<IN_LDS> R{rsrc, nullptr, 0u, 0u};
+    MsgRow<IN_LDS> R{rsrc, nullptr, 0u, 0u, true};
     if (IN_LDS) {
         R.lds = smem;
         R.ro = ro + 2u * (uint32_t)(e0 * Z);
@@ -529,13 +532,15 @@ __device__ inline MsgRow<IN_LDS> msg_row(uint8_t *smem, uint32_t ro,
 }
 
 // One iteration's sweep over the block rows (layers) in order, a workgroup
-// barrier between layers that share a block column. wrow: this iteration's per-row Q1.7 weights
-// or null (bw.beta for every row).
+// barrier between layers that share a block column. wrow: this iteration's
+// per-row Q1.7 weights or null (bw.beta for every row). keep: whether the
+// check-to-variable messages are stored (not in the last iteration).
 template <int WMAX, bool IN_LDS, bool FIRST>
 __device__ __forceinline__ void layer_pass(const BlockWork &bw, uint8_t *smem, uint32_t lb,
                                            uint32_t ro, __amdgpu_buffer_rsrc_t rsrc,
                                            crow_t row_ptr, cmeta_t meta, const uint8_t *wrow,
-                                           uint32_t u, bool busy, u16x2 off16, uint32_t *pre) {
+                                           uint32_t u, bool busy, u16x2 off16, uint32_t *pre,
+                                           bool keep) {
     const int Z = bw.Z;
     crow_t row_pad = (crow_t)bw.row_pad;
     // a barrier only where the next row shares a column with the rows since
@@ -556,10 +561,13 @@ __device__ __forceinline__ void layer_pass(const BlockWork &bw, uint8_t *smem, u
         const int w = e1 - e0;
         const int wt = wrow ? row_weight(wrow, r) : bw.beta;
         const u16x2 wgt = {(unsigned short)wt, (unsigned short)wt};
-        const MsgRow<IN_LDS> R = msg_row<IN_LDS>(smem, ro, rsrc, e0, p0, Z);
+        MsgRow<IN_LDS> R = msg_row<IN_LDS>(smem, ro, rsrc, e0, p0, Z);
+        R.keep = keep;
         if (busy) {
             row_update_any<WMAX, IN_LDS, FIRST>(w, smem, lb, R, meta, e0, u, Z, wgt, off16, pre);
-            if (!IN_LDS && (last || !FIRST))
+            // the next row's messages exist unless this is the first
+            // iteration; after the last row, only if another iteration runs
+            if (!IN_LDS && (last ? keep : !FIRST))
                 msg_row<IN_LDS>(smem, ro, rsrc, 0, pn, Z).load4(pre, u, (p2 - pn) / 2);
         }
         if ((bar >> r) & 1) __syncthreads();
@@ -631,10 +639,10 @@ __device__ __forceinline__ void decode_block(const BlockWork &bw, uint8_t *smem,
         // the first iteration has no check-to-variable messages yet
         if (t == 1)
             layer_pass<WMAX, IN_LDS, true>(bw, smem, lb, ro, rsrc, row_ptr, meta, wrow, u, busy,
-                                           off16, pre);
+                                           off16, pre, t < bw.max_iter);
         else
             layer_pass<WMAX, IN_LDS, false>(bw, smem, lb, ro, rsrc, row_ptr, meta, wrow, u, busy,
-                                            off16, pre);
+                                            off16, pre, t < bw.max_iter);
         if (bw.early_exit || t == bw.max_iter) {
             // flags[0, 2*slots): a failing check per codeword; flags[2*slots]:
             // stays 1 while every codeword of the workgroup is finished

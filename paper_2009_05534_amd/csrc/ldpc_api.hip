@@ -273,8 +273,10 @@ int ldpc_decode_ex(const ldpc_args *a) {
         const int per_pair = msg_in_lds ? full : lds_bytes_i8_pair_post(p.n_cols, p.Z) + 8;
         int pairs = (a->cw_per_block + 1) / 2;
         // Default: about 256 lanes per workgroup with the whole state in LDS,
-        // else about 384 (one pair per workgroup at the largest lifts).
-        if (pairs == 0) pairs = std::max(1, (msg_in_lds ? 256 : 384) / p.Z);
+        // else about 768 (two pairs per workgroup at the largest lift, one
+        // workgroup per CU: measured as fast as three pairs per CU in steady
+        // state, and with a finer tail for batches of a few thousand).
+        if (pairs == 0) pairs = std::max(1, (msg_in_lds ? 256 : 768) / p.Z);
         pairs = std::min(pairs, (lds_cap - 8) / per_pair);
         pairs = std::min(pairs, 768 / p.Z);
         pairs = std::min(pairs, (a->n_cw + 1) / 2);
