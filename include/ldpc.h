@@ -160,10 +160,14 @@ int ldpc_decode_ex(const ldpc_args *a);
  * [n_cw][K/8], out_iters int32 [n_cw], out_ok uint8 [n_cw] or NULL, and
  * optional per-(iteration, row) Q1.7 weights wq [wq_iters][rows] (NULL:
  * beta = 3/4). All of a batch's jobs are decoded by ONE persistent launch of
- * the int8 kernel (messages in device memory): each workgroup takes tasks of
- * up to 384/Z codewords of one job from a device counter until none are
- * left. Results are identical to decoding each job alone (ldpc_decode_ex
- * with the same options). Lifts up to 384, row weights up to 20.
+ * the int8 kernel (messages in device memory): each 384-lane workgroup takes
+ * tasks from a device counter until none are left. A task is up to
+ * 2*floor(384/Z) codewords of one job, or, for lifts up to 64, a bundle of
+ * six wave tasks (one per 64-lane wave, each up to 2*floor(64/Z) codewords
+ * of its own job), so small shapes with few codewords do not leave most of
+ * a workgroup idle. Results are identical to decoding each job alone
+ * (ldpc_decode_ex with the same options). Lifts up to 384, row weights up
+ * to 20.
  */
 typedef struct ldpc_job {
     int bg, Z, rows, n_cw;
@@ -200,7 +204,8 @@ typedef struct ldpc_plan ldpc_plan;
 int ldpc_plan_create(const ldpc_job *jobs, int n_jobs, int max_iter, int early_exit, int flags,
                      void *stream, ldpc_plan **out);
 int ldpc_plan_launch(ldpc_plan *plan, void *stream);
-/* grid: persistent workgroups; n_tasks: tasks in the queue; tuned_ms: time
+/* grid: persistent workgroups; n_tasks: tasks in the queue (a bundle of
+ * small-lift wave tasks counts once); tuned_ms: time
  * of the chosen grid when autotuned (else 0). Any output may be NULL. */
 int ldpc_plan_info(const ldpc_plan *plan, int *grid, int *n_tasks, float *tuned_ms);
 void ldpc_plan_destroy(ldpc_plan *plan);

@@ -16,6 +16,7 @@ struct Plan {
     BatchLaunch launch{};
     BatchTask *d_tasks = nullptr;
     BatchJob *d_jobs = nullptr;
+    WaveTask *d_waves = nullptr;
     unsigned *d_counter = nullptr;
     uint16_t *d_msg = nullptr;
     size_t msg_capacity = 0;  // pair words allocated
@@ -33,6 +34,7 @@ void free_plan(Plan *p) {
     if (p->graph) (void)hipGraphDestroy(p->graph);
     if (p->d_tasks) (void)hipFree(p->d_tasks);
     if (p->d_jobs) (void)hipFree(p->d_jobs);
+    if (p->d_waves) (void)hipFree(p->d_waves);
     if (p->d_counter) (void)hipFree(p->d_counter);
     if (p->d_msg) (void)hipFree(p->d_msg);
     delete p;
@@ -56,33 +58,77 @@ hipError_t size_messages(Plan *p, int grid) {
 
 }  // namespace
 
+int build_tasks(const std::vector<BatchJob> &jobs, const std::vector<int> &job_cw, int lds_cap,
+                TaskSet &ts) {
+    auto cost = [&](int j) { return (long)jobs[j].E * jobs[j].Z; };
+    std::vector<WaveTask> waves;
+    for (size_t j = 0; j < jobs.size(); ++j) {
+        const BatchJob &jb = jobs[j];
+        if (jb.Z <= kWaveLanes) {
+            const int pairs = kWaveLanes / jb.Z, slots = 2 * pairs;
+            int need = pairs * lds_bytes_i8_pair_post(jb.n_cols, jb.Z) + lds_flags_bytes_i8(pairs);
+            need = (need + 15) & ~15;
+            ts.wave_lds = std::max(ts.wave_lds, need);
+            ts.wave_msg = std::max(ts.wave_msg, pairs * jb.E_pad * jb.Z);
+            for (int f = 0; f < job_cw[j]; f += slots)
+                waves.push_back(WaveTask{(int)j, f, std::min(slots, job_cw[j] - f), 0});
+        } else {
+            const int pairs = jb.slots / 2;
+            ts.lds = std::max(ts.lds, pairs * lds_bytes_i8_pair_post(jb.n_cols, jb.Z) +
+                                          lds_flags_bytes_i8(pairs));
+            ts.msg_per_block = std::max(ts.msg_per_block, pairs * jb.E_pad * jb.Z);
+            for (int f = 0; f < job_cw[j]; f += jb.slots)
+                ts.tasks.push_back(BatchTask{(int)j, f, std::min(jb.slots, job_cw[j] - f), 0});
+        }
+    }
+    // Longest first (larger lifts and more rows), so that the tail of the
+    // persistent loop holds the short ones; wave tasks of similar length
+    // share a bundle.
+    std::stable_sort(waves.begin(), waves.end(),
+                     [&](const WaveTask &a, const WaveTask &b) { return cost(a.job) > cost(b.job); });
+    std::vector<long> task_cost;
+    for (const BatchTask &t : ts.tasks) task_cost.push_back(cost(t.job));
+    for (size_t i = 0; i < waves.size(); i += kWavesPerBlock) {
+        const int nw = (int)std::min<size_t>(kWavesPerBlock, waves.size() - i);
+        ts.tasks.push_back(BatchTask{-1, (int)i, 0, nw});
+        task_cost.push_back(cost(waves[i].job));
+    }
+    ts.waves = std::move(waves);
+    if (!ts.waves.empty()) {
+        ts.lds = std::max(ts.lds, kWavesPerBlock * ts.wave_lds);
+        ts.msg_per_block = std::max(ts.msg_per_block, kWavesPerBlock * ts.wave_msg);
+    }
+    std::vector<int> order(ts.tasks.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return task_cost[a] > task_cost[b]; });
+    std::vector<BatchTask> sorted;
+    for (int i : order) sorted.push_back(ts.tasks[i]);
+    ts.tasks = std::move(sorted);
+    if (ts.lds > lds_cap || ts.tasks.empty()) return LDPC_EINVAL;
+    return LDPC_OK;
+}
+
 // Fills the job table from the registered graphs; called under the graph
 // registry lock by ldpc_plan_create.
 int plan_build(Plan *p, const std::vector<BatchJob> &jobs, const std::vector<int> &job_cw,
                int lanes, int max_iter, int early_exit, int beta, int offset, int wmax,
                int lds_cap, hipStream_t stream) {
-    std::vector<BatchTask> tasks;
-    int lds = 0, msg_per_block = 0;
-    for (size_t j = 0; j < jobs.size(); ++j) {
-        const BatchJob &jb = jobs[j];
-        const int per_pair = lds_bytes_i8_pair_post(jb.n_cols, jb.Z);
-        lds = std::max(lds, jb.slots / 2 * per_pair + lds_flags_bytes_i8(jb.slots / 2));
-        msg_per_block = std::max(msg_per_block, jb.slots / 2 * jb.E_pad * jb.Z);
-        for (int f = 0; f < job_cw[j]; f += jb.slots)
-            tasks.push_back(BatchTask{(int)j, f, std::min(jb.slots, job_cw[j] - f), 0});
-    }
-    if (lds > lds_cap) return LDPC_EINVAL;
-    // Longest tasks first (larger lifts and more rows), so that the tail of
-    // the persistent loop holds the short ones.
-    std::stable_sort(tasks.begin(), tasks.end(), [&](const BatchTask &a, const BatchTask &b) {
-        const BatchJob &x = jobs[a.job], &y = jobs[b.job];
-        return (long)x.E * x.Z > (long)y.E * y.Z;
-    });
+    TaskSet ts;
+    const int rc = build_tasks(jobs, job_cw, lds_cap, ts);
+    if (rc != LDPC_OK) return rc;
+    const std::vector<BatchTask> &tasks = ts.tasks;
+    const int lds = ts.lds, msg_per_block = ts.msg_per_block;
     hipError_t e;
     if ((e = hipMalloc(&p->d_tasks, sizeof(BatchTask) * std::max<size_t>(tasks.size(), 1))) !=
             hipSuccess ||
         (e = hipMalloc(&p->d_jobs, sizeof(BatchJob) * jobs.size())) != hipSuccess ||
+        (e = hipMalloc(&p->d_waves, sizeof(WaveTask) * std::max<size_t>(ts.waves.size(), 1))) !=
+            hipSuccess ||
         (e = hipMalloc(&p->d_counter, sizeof(unsigned))) != hipSuccess ||
+        (!ts.waves.empty() &&
+         (e = hipMemcpyAsync(p->d_waves, ts.waves.data(), sizeof(WaveTask) * ts.waves.size(),
+                             hipMemcpyHostToDevice, stream)) != hipSuccess) ||
         (e = hipMemcpyAsync(p->d_tasks, tasks.data(), sizeof(BatchTask) * tasks.size(),
                             hipMemcpyHostToDevice, stream)) != hipSuccess ||
         (e = hipMemcpyAsync(p->d_jobs, jobs.data(), sizeof(BatchJob) * jobs.size(),
@@ -99,6 +145,9 @@ int plan_build(Plan *p, const std::vector<BatchJob> &jobs, const std::vector<int
     BatchLaunch &b = p->launch;
     b.tasks = p->d_tasks;
     b.jobs = p->d_jobs;
+    b.waves = p->d_waves;
+    b.wave_lds = ts.wave_lds;
+    b.wave_msg = ts.wave_msg;
     b.n_tasks = (int)tasks.size();
     b.counter = p->d_counter;
     b.msg_per_block = msg_per_block;
@@ -195,29 +244,23 @@ void plan_destroy(Plan *p) { free_plan(p); }
 int batch_async(const std::vector<BatchJob> &jobs, const std::vector<int> &job_cw, int lanes,
                 int max_iter, int early_exit, int wmax, int lds_cap, hipStream_t stream,
                 size_t *bytes_in_flight) {
-    std::vector<BatchTask> tasks;
-    int lds = 0, msg_per_block = 0;
-    for (size_t j = 0; j < jobs.size(); ++j) {
-        const BatchJob &jb = jobs[j];
-        lds = std::max(lds, jb.slots / 2 * lds_bytes_i8_pair_post(jb.n_cols, jb.Z) +
-                                lds_flags_bytes_i8(jb.slots / 2));
-        msg_per_block = std::max(msg_per_block, jb.slots / 2 * jb.E_pad * jb.Z);
-        for (int f = 0; f < job_cw[j]; f += jb.slots)
-            tasks.push_back(BatchTask{(int)j, f, std::min(jb.slots, job_cw[j] - f), 0});
-    }
-    if (lds > lds_cap || tasks.empty()) return LDPC_EINVAL;
-    std::stable_sort(tasks.begin(), tasks.end(), [&](const BatchTask &a, const BatchTask &b) {
-        const BatchJob &x = jobs[a.job], &y = jobs[b.job];
-        return (long)x.E * x.Z > (long)y.E * y.Z;
-    });
+    TaskSet ts;
+    const int rc = build_tasks(jobs, job_cw, lds_cap, ts);
+    if (rc != LDPC_OK) return rc;
+    const std::vector<BatchTask> &tasks = ts.tasks;
+    const int lds = ts.lds, msg_per_block = ts.msg_per_block;
     int dev = 0, cus = 1;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     const int per_cu = std::max(1, std::min(8, lds_cap / std::max(lds, 1)));
     const int grid = std::max(1, std::min((int)tasks.size(), std::max(cus, 1) * per_cu));
     const size_t tb = sizeof(BatchTask) * tasks.size(), jbytes = sizeof(BatchJob) * jobs.size();
+    const size_t wbytes = sizeof(WaveTask) * ts.waves.size();
+    // layout: tasks | jobs | wave tasks | counter | messages (256-aligned)
+    const size_t o_waves = tb + jbytes, o_counter = (o_waves + wbytes + 255) & ~(size_t)255;
+    const size_t o_msg = o_counter + 256;
     const size_t mbytes = (size_t)grid * msg_per_block * sizeof(uint16_t);
-    const size_t total = tb + jbytes + 256 + mbytes;
+    const size_t total = o_msg + mbytes;
     uint8_t *buf = nullptr;
     hipError_t e = hipMallocAsync(reinterpret_cast<void **>(&buf), total, stream);
     if (e != hipSuccess) {
@@ -227,8 +270,11 @@ int batch_async(const std::vector<BatchJob> &jobs, const std::vector<int> &job_c
     BatchLaunch b{};
     b.tasks = reinterpret_cast<BatchTask *>(buf);
     b.jobs = reinterpret_cast<BatchJob *>(buf + tb);
-    b.counter = reinterpret_cast<unsigned *>(buf + tb + jbytes);
-    b.msg = reinterpret_cast<uint16_t *>(buf + tb + jbytes + 256);
+    b.waves = reinterpret_cast<WaveTask *>(buf + o_waves);
+    b.wave_lds = ts.wave_lds;
+    b.wave_msg = ts.wave_msg;
+    b.counter = reinterpret_cast<unsigned *>(buf + o_counter);
+    b.msg = reinterpret_cast<uint16_t *>(buf + o_msg);
     b.n_tasks = (int)tasks.size();
     b.msg_per_block = msg_per_block;
     b.max_iter = max_iter;
@@ -245,6 +291,9 @@ int batch_async(const std::vector<BatchJob> &jobs, const std::vector<int> &job_c
     if (e == hipSuccess)
         e = hipMemcpyAsync(const_cast<BatchJob *>(b.jobs), jobs.data(), jbytes,
                            hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess && !ts.waves.empty())
+        e = hipMemcpyAsync(const_cast<WaveTask *>(b.waves), ts.waves.data(),
+                           sizeof(WaveTask) * ts.waves.size(), hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = launch_decode_batch(b, stream);
     const hipError_t ef = hipFreeAsync(buf, stream);
     if (e != hipSuccess) {

@@ -437,7 +437,7 @@ __device__ __forceinline__ uint32_t row_parity(int w, const uint8_t *smem, uint3
 // any wave) -- only codewords whose checks all hold need the full sweep,
 // which keeps the check cheap in the iterations before convergence.
 template <int WMAX>
-__device__ inline void syndrome_mark(const uint8_t *__restrict__ smem, uint32_t lb,
+__device__ __forceinline__ void syndrome_mark(const uint8_t *__restrict__ smem, uint32_t lb,
                                      crow_t row_ptr, cmeta_t meta, int rows, uint32_t u, int Z,
                                      volatile int *fl, bool needA, bool needB) {
     for (int r = 0; r < rows; ++r) {
@@ -506,6 +506,20 @@ __device__ inline void write_outputs(const BlockWork &bw, const uint8_t *Lp, int
 
 typedef const __attribute__((address_space(4))) uint32_t *cw32_t;
 
+// Synchronisation of the lanes that decode one block of work: the whole
+// workgroup, or (WAVE) a single wave that owns its block alone -- a wave's
+// LDS accesses are performed in order, so a wave-scope fence that the
+// compiler may not move accesses across is enough.
+template <bool WAVE>
+__device__ inline void block_sync() {
+    if constexpr (WAVE) {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    } else {
+        __syncthreads();
+    }
+}
+
 // Q1.7 weight of row r from a per-row byte table in the constant address
 // space, read as the aligned dword that holds it (a scalar load; the dword
 // never crosses the page of the byte it holds).
@@ -535,7 +549,7 @@ __device__ inline MsgRow<IN_LDS> msg_row(uint8_t *smem, uint32_t ro,
 // barrier between layers that share a block column. wrow: this iteration's
 // per-row Q1.7 weights or null (bw.beta for every row). keep: whether the
 // check-to-variable messages are stored (not in the last iteration).
-template <int WMAX, bool IN_LDS, bool FIRST>
+template <int WMAX, bool IN_LDS, bool FIRST, bool WAVE>
 __device__ __forceinline__ void layer_pass(const BlockWork &bw, uint8_t *smem, uint32_t lb,
                                            uint32_t ro, __amdgpu_buffer_rsrc_t rsrc,
                                            crow_t row_ptr, cmeta_t meta, const uint8_t *wrow,
@@ -570,7 +584,7 @@ __device__ __forceinline__ void layer_pass(const BlockWork &bw, uint8_t *smem, u
             if (!IN_LDS && (last ? keep : !FIRST))
                 msg_row<IN_LDS>(smem, ro, rsrc, 0, pn, Z).load4(pre, u, (p2 - pn) / 2);
         }
-        if ((bar >> r) & 1) __syncthreads();
+        if ((bar >> r) & 1) block_sync<WAVE>();
         e0 = en;
         e1 = e2;
         p0 = pn;
@@ -587,15 +601,19 @@ __device__ __forceinline__ void layer_pass(const BlockWork &bw, uint8_t *smem, u
 // LDS; otherwise they stream through device memory (bw.msg, [pair][E][Z]
 // pair words) and only the posteriors occupy LDS, so several pairs share a
 // CU (§IV's placement of L_v in shared and L_{c->v} in main memory).
-template <int WMAX, bool IN_LDS>
+// WAVE: one wave decodes the block by itself (lanes = threadIdx.x mod 64,
+// Z <= 64) and synchronises only itself, so the other waves of the
+// workgroup may decode other blocks of other shapes at the same time.
+template <int WMAX, bool IN_LDS, bool WAVE = false>
 __device__ __forceinline__ void decode_block(const BlockWork &bw, uint8_t *smem, crow_t row_ptr,
                                              cmeta_t meta) {
     static_assert(WMAX <= kMetaPad, "row metadata window exceeds the table padding");
     const int Z = bw.Z;
     const int N = bw.n_cols, E = bw.E, T = (N - 2) * Z;
     const int pair_bytes = IN_LDS ? lds_bytes_i8_pair(N, E, Z) : lds_bytes_i8_pair_post(N, Z);
-    const int p = threadIdx.x / Z;
-    const uint32_t u = threadIdx.x - p * Z;
+    const int tid = WAVE ? (int)(threadIdx.x & 63u) : (int)threadIdx.x;
+    const int p = tid / Z;
+    const uint32_t u = tid - p * Z;
     const bool validA = 2 * p < bw.n, validB = 2 * p + 1 < bw.n;
     const int ps = validA ? p : 0;  // keeps idle lanes' addresses in range
     uint8_t *Lp = smem + ps * pair_bytes;
@@ -627,7 +645,7 @@ __device__ __forceinline__ void decode_block(const BlockWork &bw, uint8_t *smem,
             Lw[c * Z + u] = (uint16_t)((a & 0xFF) | ((b & 0xFF) << 8));
         }
     }
-    __syncthreads();
+    block_sync<WAVE>();
 
     const u16x2 off16 = {(unsigned short)(bw.offset << 8), (unsigned short)(bw.offset << 8)};
     bool doneA = !validA, doneB = !validB;
@@ -638,20 +656,20 @@ __device__ __forceinline__ void decode_block(const BlockWork &bw, uint8_t *smem,
         const bool busy = !(doneA && doneB);
         // the first iteration has no check-to-variable messages yet
         if (t == 1)
-            layer_pass<WMAX, IN_LDS, true>(bw, smem, lb, ro, rsrc, row_ptr, meta, wrow, u, busy,
+            layer_pass<WMAX, IN_LDS, true, WAVE>(bw, smem, lb, ro, rsrc, row_ptr, meta, wrow, u, busy,
                                            off16, pre, t < bw.max_iter);
         else
-            layer_pass<WMAX, IN_LDS, false>(bw, smem, lb, ro, rsrc, row_ptr, meta, wrow, u, busy,
+            layer_pass<WMAX, IN_LDS, false, WAVE>(bw, smem, lb, ro, rsrc, row_ptr, meta, wrow, u, busy,
                                             off16, pre, t < bw.max_iter);
         if (bw.early_exit || t == bw.max_iter) {
             // flags[0, 2*slots): a failing check per codeword; flags[2*slots]:
             // stays 1 while every codeword of the workgroup is finished
-            if ((int)threadIdx.x <= 2 * bw.slots) flags[threadIdx.x] = (int)threadIdx.x == 2 * bw.slots;
-            __syncthreads();
+            if (tid <= 2 * bw.slots) flags[tid] = tid == 2 * bw.slots;
+            block_sync<WAVE>();
             if (busy)
                 syndrome_mark<WMAX>(smem, lb, row_ptr, meta, bw.rows, u, Z, flags + 2 * p, !doneA,
                                     !doneB);
-            __syncthreads();
+            block_sync<WAVE>();
             const bool holdsA = flags[2 * ps] == 0, holdsB = flags[2 * ps + 1] == 0;
             bool finA = false, finB = false;
             if (t == bw.max_iter) {
@@ -666,7 +684,7 @@ __device__ __forceinline__ void decode_block(const BlockWork &bw, uint8_t *smem,
             doneA = doneA || finA;
             doneB = doneB || finB;
             if (!(doneA && doneB)) flags[2 * bw.slots] = 0;
-            __syncthreads();
+            block_sync<WAVE>();
             if (flags[2 * bw.slots]) break;
         }
     }
@@ -751,9 +769,10 @@ hipError_t launch_placed(const DecodeLaunch &p, hipStream_t stream) {
 // workgroup, reused from task to task.
 template <int WMAX>
 __global__ __launch_bounds__(kBatchLanes) __attribute__((amdgpu_waves_per_eu(5))) void decode_batch_kernel(
-    const BatchTask *__restrict__ tasks, const BatchJob *__restrict__ jobs, int n_tasks,
-    unsigned *counter, uint16_t *msg_ws, int msg_per_block, int max_iter, int early_exit,
-    int beta, int offset) {
+    const BatchTask *__restrict__ tasks, const BatchJob *__restrict__ jobs,
+    const WaveTask *__restrict__ waves, int n_tasks, unsigned *counter, uint16_t *msg_ws,
+    int msg_per_block, int wave_lds, int wave_msg, int max_iter, int early_exit, int beta,
+    int offset) {
     extern __shared__ __align__(16) uint8_t smem[];
     __shared__ int task_id;
     for (;;) {
@@ -763,33 +782,51 @@ __global__ __launch_bounds__(kBatchLanes) __attribute__((amdgpu_waves_per_eu(5))
         __syncthreads();
         if (ti >= n_tasks) break;
         const BatchTask tk = tasks[ti];
-        const BatchJob &jb = jobs[tk.job];
-        const int T = (jb.n_cols - 2) * jb.Z;
-        BlockWork bw;
-        bw.n = tk.n;
-        bw.slots = jb.slots / 2;
-        bw.llr = jb.llr + (size_t)tk.first * T;
-        bw.out_bits = jb.out_bits + (size_t)tk.first * (jb.kb * jb.Z / 8);
-        bw.out_iters = jb.out_iters + tk.first;
-        bw.out_ok = jb.out_ok ? jb.out_ok + tk.first : nullptr;
-        bw.out_llr = nullptr;
-        bw.msg = msg_ws + (size_t)blockIdx.x * msg_per_block;
-        bw.row_pad = jb.row_pad;
-        bw.E_pad = jb.E_pad;
-        bw.groups = jb.groups;
-        bw.wq = jb.wq;
-        bw.w_iters = jb.w_iters;
-        bw.w_stride = jb.w_stride;
-        bw.rows = jb.rows;
-        bw.n_cols = jb.n_cols;
-        bw.kb = jb.kb;
-        bw.Z = jb.Z;
-        bw.E = jb.E;
-        bw.max_iter = max_iter;
-        bw.early_exit = early_exit;
-        bw.beta = beta;
-        bw.offset = offset;
-        decode_block<WMAX, false>(bw, smem, (crow_t)jb.row_ptr, (cmeta_t)jb.meta);
+        // a whole-workgroup task, or this wave's task of a bundle
+        // (uniform within a wave; readfirstlane lets the compiler know)
+        const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWaveLanes));
+        const bool wave_task = tk.nwave > 0;
+        if (!wave_task || wv < tk.nwave) {
+            int job = tk.job, first = tk.first, n = tk.n;
+            if (wave_task) {
+                const WaveTask wt = waves[tk.first + wv];
+                job = wt.job;
+                first = wt.first;
+                n = wt.n;
+            }
+            const BatchJob &jb = jobs[job];
+            const int T = (jb.n_cols - 2) * jb.Z;
+            BlockWork bw;
+            bw.n = n;
+            bw.slots = wave_task ? kWaveLanes / jb.Z : jb.slots / 2;
+            bw.llr = jb.llr + (size_t)first * T;
+            bw.out_bits = jb.out_bits + (size_t)first * (jb.kb * jb.Z / 8);
+            bw.out_iters = jb.out_iters + first;
+            bw.out_ok = jb.out_ok ? jb.out_ok + first : nullptr;
+            bw.out_llr = nullptr;
+            bw.msg = msg_ws + (size_t)blockIdx.x * msg_per_block +
+                     (wave_task ? (size_t)wv * wave_msg : 0);
+            bw.row_pad = jb.row_pad;
+            bw.E_pad = jb.E_pad;
+            bw.groups = jb.groups;
+            bw.wq = jb.wq;
+            bw.w_iters = jb.w_iters;
+            bw.w_stride = jb.w_stride;
+            bw.rows = jb.rows;
+            bw.n_cols = jb.n_cols;
+            bw.kb = jb.kb;
+            bw.Z = jb.Z;
+            bw.E = jb.E;
+            bw.max_iter = max_iter;
+            bw.early_exit = early_exit;
+            bw.beta = beta;
+            bw.offset = offset;
+            if (wave_task)
+                decode_block<WMAX, false, true>(bw, smem + wv * wave_lds, (crow_t)jb.row_ptr,
+                                                (cmeta_t)jb.meta);
+            else
+                decode_block<WMAX, false>(bw, smem, (crow_t)jb.row_ptr, (cmeta_t)jb.meta);
+        }
         __syncthreads();
     }
 }
@@ -826,12 +863,12 @@ hipError_t launch_decode_batch(const BatchLaunch &b, hipStream_t stream) {
     (void)hipGetLastError();
     if (b.wmax <= 10)
         hipLaunchKernelGGL(decode_batch_kernel<10>, dim3(b.grid), dim3(b.lanes), b.lds, stream,
-                           b.tasks, b.jobs, b.n_tasks, b.counter, b.msg, b.msg_per_block,
-                           b.max_iter, b.early_exit, b.beta, b.offset);
+                           b.tasks, b.jobs, b.waves, b.n_tasks, b.counter, b.msg, b.msg_per_block,
+                           b.wave_lds, b.wave_msg, b.max_iter, b.early_exit, b.beta, b.offset);
     else
         hipLaunchKernelGGL(decode_batch_kernel<20>, dim3(b.grid), dim3(b.lanes), b.lds, stream,
-                           b.tasks, b.jobs, b.n_tasks, b.counter, b.msg, b.msg_per_block,
-                           b.max_iter, b.early_exit, b.beta, b.offset);
+                           b.tasks, b.jobs, b.waves, b.n_tasks, b.counter, b.msg, b.msg_per_block,
+                           b.wave_lds, b.wave_msg, b.max_iter, b.early_exit, b.beta, b.offset);
     e = hipGetLastError();
     if (e != hipSuccess) note_hip_error("launch decode_batch_kernel", e);
     return e;

@@ -101,12 +101,24 @@ struct BatchJob {
     int w_iters, w_stride;
     int rows, n_cols, kb, Z, E, E_pad, slots;
 };
+// A task is either codewords [first, first + n) of job `job` for the whole
+// workgroup (nwave = 0), or a bundle of nwave wave tasks waves[first ..
+// first + nwave), one per wave of the workgroup (small lifts: a codeword
+// pair of Z <= 64 fits one wave, so each wave decodes its own shape).
 struct BatchTask {
+    int job, first, n, nwave;
+};
+struct WaveTask {
     int job, first, n, pad;
 };
+constexpr int kWaveLanes = 64;
+constexpr int kWavesPerBlock = kBatchLanes / kWaveLanes;
 struct BatchLaunch {
     const BatchTask *tasks;
     const BatchJob *jobs;
+    const WaveTask *waves;    // wave tasks of the bundles
+    int wave_lds;             // LDS bytes per wave of a bundle
+    int wave_msg;             // message pair words per wave of a bundle
     int n_tasks;
     unsigned *counter;
     uint16_t *msg;            // grid * msg_per_block pair words
@@ -115,6 +127,16 @@ struct BatchLaunch {
     int grid, lanes, lds, wmax;
 };
 hipError_t launch_decode_batch(const BatchLaunch &b, hipStream_t stream);
+
+// Tasks of a mixed batch (see BatchTask), longest first, with the LDS and
+// message sizes a workgroup needs. Returns LDPC_OK or LDPC_EINVAL.
+struct TaskSet {
+    std::vector<BatchTask> tasks;
+    std::vector<WaveTask> waves;
+    int lds = 0, msg_per_block = 0, wave_lds = 0, wave_msg = 0;
+};
+int build_tasks(const std::vector<BatchJob> &jobs, const std::vector<int> &job_cw, int lds_cap,
+                TaskSet &ts);
 
 struct Plan;
 int plan_build(Plan *p, const std::vector<BatchJob> &jobs, const std::vector<int> &job_cw,

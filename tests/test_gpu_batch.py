@@ -56,7 +56,12 @@ def test_plan_graph_replays_match_eager(lib):
     jobs = _jobs(lib, groups)
     plan = lib.Plan(jobs, graph=True, autotune=True)
     info = plan.info()
-    assert info["grid"] >= 1 and info["n_tasks"] >= len(groups) and info["tuned_ms"] > 0
+    # lifts above 64: one task per 2*floor(384/Z) codewords of a shape; lifts
+    # up to 64: one wave task per 2*floor(64/Z), six wave tasks to a bundle
+    big = sum(-(-len(gr.indices) // (2 * (384 // gr.Z))) for gr in groups if gr.Z > 64)
+    small = sum(-(-len(gr.indices) // (2 * (64 // gr.Z))) for gr in groups if gr.Z <= 64)
+    assert info["n_tasks"] == big + -(-small // 6), info
+    assert info["grid"] >= 1 and info["tuned_ms"] > 0
     for rep in range(3):
         # refill every job's input buffer in place with fresh data of its shape
         qs = []
