@@ -245,6 +245,51 @@ __device__ __forceinline__ void row_phase1(const uint8_t *__restrict__ smem, uin
             lraw[i] = lds_ld16(smem, a);
         }
     }
+    if constexpr (KEEP_GATHER) {
+        // Narrow rows (every edge present, K0 = 0): each step over all
+        // edges at once, and the two smallest magnitudes by a pairwise tree,
+        // so dependent packed operations are rarely adjacent.
+        s16x2 x[n];
+#pragma unroll
+        for (int k = 0; k < n; ++k)
+            x[k] = __builtin_elementwise_sub_sat(as_s(perm(lraw[k], kUnpack)),
+                                                 as_s(perm(rd[k >> 1], (k & 1) ? kUnpackHi : kUnpack)));
+#pragma unroll
+        for (int k = 0; k < n; ++k)
+            x[k] = __builtin_elementwise_max(x[k], (s16x2){-127 * 256, -127 * 256});
+#pragma unroll
+        for (int k = 0; k < n; ++k) {
+            axv[k] = bits_of(__builtin_elementwise_max(x[k], (s16x2){0, 0} - x[k]));
+            xv[k] = bits_of(x[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < n; ++k) S ^= xv[k];
+        // (lo, hi) of edge pairs, then merged: the smallest of a merge is
+        // min(lo1, lo2), the second min(max(lo1, lo2), min(hi1, hi2)).
+        constexpr int NP = (n + 1) / 2;
+        u16x2 lo[NP], hi[NP];
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+            const u16x2 a = as_u(axv[2 * q]);
+            const u16x2 b = 2 * q + 1 < n ? as_u(axv[2 * q + 1]) : (u16x2){0x7FFF, 0x7FFF};
+            lo[q] = __builtin_elementwise_min(a, b);
+            hi[q] = __builtin_elementwise_max(a, b);
+        }
+#pragma unroll
+        for (int w = 1; w < NP; w *= 2) {
+#pragma unroll
+            for (int q = 0; q + w < NP; q += 2 * w) {
+                const u16x2 l = __builtin_elementwise_min(lo[q], lo[q + w]);
+                const u16x2 h = __builtin_elementwise_min(__builtin_elementwise_max(lo[q], lo[q + w]),
+                                                          __builtin_elementwise_min(hi[q], hi[q + w]));
+                lo[q] = l;
+                hi[q] = h;
+            }
+        }
+        m1 = lo[0];
+        m2 = hi[0];
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < n; ++i) {
         const int k = K0 + i;
@@ -325,41 +370,92 @@ __device__ __forceinline__ void row_update_w(uint8_t *__restrict__ smem, uint32_
     const u16x2 m1p = m1 + (u16x2){1, 1};
     uint32_t sd[ND];
     uint32_t rprev = 0;
+    if constexpr (!kWide && !GEN) {
+        // Narrow rows: each step over all edges at once (the edges are
+        // independent), so dependent packed operations are not adjacent.
+        s16x2 Rv[W], Lv[W];
 #pragma unroll
-    for (int k = 0; k < W; ++k) {
-        if (k >= wrow) continue;
-        const s16x2 x = as_s(xv[k]);
-        const s16x2 ax = kWide ? __builtin_elementwise_max(x, (s16x2){0, 0} - x) : as_s(axv[k]);
-        // t = 1 on the argmin edge (|x| == m1), else 0.
-        const u16x2 t = __builtin_elementwise_sub_sat(m1p, as_u(bits_of(ax)));
-        const s16x2 b = as_s(bits_of(t * d21 + as_u(bits_of(b1))));
+        for (int k = 0; k < W; ++k) {
+            const u16x2 t = __builtin_elementwise_sub_sat(m1p, as_u(axv[k]));
+            Rv[k] = as_s(bits_of(t * d21 + as_u(bits_of(b1))));
+        }
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            const s16x2 sx = as_s(xv[k]) >> (s16x2){15, 15};
+            Rv[k] = (Rv[k] ^ sx) - sx;
+        }
+#pragma unroll
+        for (int k = 0; k < W; ++k)
+            Lv[k] = __builtin_elementwise_max(__builtin_elementwise_add_sat(as_s(xv[k]), Rv[k]),
+                                              (s16x2){-127 * 256, -127 * 256});
+#pragma unroll
+        for (int k = 0; k < W; ++k) lds_st16(smem, la[k], perm(bits_of(Lv[k]), kPack));
+#pragma unroll
+        for (int j = 0; j < ND; ++j)
+            sd[j] = 2 * j + 1 < W ? __builtin_amdgcn_perm(bits_of(Rv[2 * j + 1]), bits_of(Rv[2 * j]), kPack2)
+                                  : perm(bits_of(Rv[2 * j]), kPack);
+#pragma unroll
+        for (int c = 0; c < ND; c += 4) R.template store<W>(sd, u, Z, c, ND - c < 4 ? ND - c : 4);
+        return;
+    }
+    // Wide rows: the same steps over groups of four edges (a group's values
+    // stay in registers; the whole row's would not).
+#pragma unroll
+    for (int g = 0; g < W; g += 4) {
+        s16x2 Rg[4], Lg[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int k = g + i;
+            if (k >= W || k >= wrow) continue;
+            const s16x2 x = as_s(xv[k]);
+            const s16x2 ax = kWide ? __builtin_elementwise_max(x, (s16x2){0, 0} - x) : as_s(axv[k]);
+            // t = 1 on the argmin edge (|x| == m1), else 0.
+            const u16x2 t = __builtin_elementwise_sub_sat(m1p, as_u(bits_of(ax)));
+            Rg[i] = as_s(bits_of(t * d21 + as_u(bits_of(b1))));
+        }
         // R' = sgn(x) * b; L' = sat(x + R'). The low byte of x is 0 or 0xFF
         // and that of R' is 0, so no carry reaches the high byte.
-        const s16x2 sx = x >> (s16x2){15, 15};
-        const s16x2 Rn = (b ^ sx) - sx;
-        const s16x2 Ln = __builtin_elementwise_max(__builtin_elementwise_add_sat(x, Rn),
-                                                   (s16x2){-127 * 256, -127 * 256});
-        const uint32_t a = kWide ? gather(md[k], lb, u, (uint32_t)Z) : la[k];
-        lds_st16(smem, a, perm(bits_of(Ln), kPack));
-        // messages k-1 and k share a dword (an odd row's last dword pads
-        // with a zero pair word); store each group of 4 dwords once complete
-        const int j = k >> 1;
-        if (k & 1) {
-            sd[j] = __builtin_amdgcn_perm(bits_of(Rn), rprev, kPack2);
-        } else {
-            rprev = bits_of(Rn);
-            if (k == wrow - 1) sd[j] = perm(bits_of(Rn), kPack);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int k = g + i;
+            if (k >= W || k >= wrow) continue;
+            const s16x2 sx = as_s(xv[k]) >> (s16x2){15, 15};
+            Rg[i] = (Rg[i] ^ sx) - sx;
+            Lg[i] = __builtin_elementwise_max(__builtin_elementwise_add_sat(as_s(xv[k]), Rg[i]),
+                                              (s16x2){-127 * 256, -127 * 256});
         }
-        if (GEN && IN_LDS) {
-            if ((k & 1) || k == wrow - 1) R.template store<W>(sd, u, Z, j, 1, wrow);
-        } else if (GEN) {
-            if ((k & 1) || k == wrow - 1) {
-                if ((j & 3) == 3) R.store_rt(sd, u, nd, j & ~3, 4);
-                else if (j == nd - 1) R.store_rt(sd, u, nd, j & ~3, nd - (j & ~3));
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int k = g + i;
+            if (k >= W || k >= wrow) continue;
+            const uint32_t a = kWide ? gather(md[k], lb, u, (uint32_t)Z) : la[k];
+            lds_st16(smem, a, perm(bits_of(Lg[i]), kPack));
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int k = g + i;
+            if (k >= W || k >= wrow) continue;
+            const s16x2 Rn = Rg[i];
+            // messages k-1 and k share a dword (an odd row's last dword pads
+            // with a zero pair word); store each group of 4 dwords once complete
+            const int j = k >> 1;
+            if (k & 1) {
+                sd[j] = __builtin_amdgcn_perm(bits_of(Rn), rprev, kPack2);
+            } else {
+                rprev = bits_of(Rn);
+                if (k == wrow - 1) sd[j] = perm(bits_of(Rn), kPack);
             }
-        } else if ((k & 1) || k == W - 1) {
-            if ((j & 3) == 3) R.template store<W>(sd, u, Z, j & ~3, 4);
-            else if (j == ND - 1) R.template store<W>(sd, u, Z, j & ~3, ND - (j & ~3));
+            if (GEN && IN_LDS) {
+                if ((k & 1) || k == wrow - 1) R.template store<W>(sd, u, Z, j, 1, wrow);
+            } else if (GEN) {
+                if ((k & 1) || k == wrow - 1) {
+                    if ((j & 3) == 3) R.store_rt(sd, u, nd, j & ~3, 4);
+                    else if (j == nd - 1) R.store_rt(sd, u, nd, j & ~3, nd - (j & ~3));
+                }
+            } else if ((k & 1) || k == W - 1) {
+                if ((j & 3) == 3) R.template store<W>(sd, u, Z, j & ~3, 4);
+                else if (j == ND - 1) R.template store<W>(sd, u, Z, j & ~3, ND - (j & ~3));
+            }
         }
     }
 }
