@@ -54,13 +54,18 @@ __device__ inline u16x2 normalise(u16x2 m, u16x2 off16, u16x2 w) {
     return v << (u16x2){8, 8};
 }
 
-// Block metadata md = 2(c*Z + s) | (Z - s) << 16 (column c, shift s). Lane
-// u reads variable (u + s) mod Z of column c: LDS byte address lb + 2(cZ +
-// s), minus 2Z when u + s wraps (u >= Z - s); lb = pair posteriors + 2u.
-// The fields are scalar; the lane work is one compare, one select, one add.
-__device__ inline uint32_t gather(uint32_t md, uint32_t lb, uint32_t u, uint32_t Z) {
-    const uint32_t off = md & 0xFFFFu, thr = md >> 16;
-    const uint32_t wrap = u >= thr ? 2u * Z : 0u;
+// Block metadata md = 2(c*Z + s) | (Z - s) << 16 (column c, shift s) and
+// its low half off = 2(c*Z + s). Lane u reads variable (u + s) mod Z of
+// column c: LDS byte address lb + off, minus 2Z when u + s wraps
+// (u >= Z - s); lb = pair posteriors + 2u. With the lane key
+// U = u << 16 | 0xFFFF, U >= md exactly when u >= Z - s, so the compare
+// takes md as loaded (no scalar shift); the lane work is one compare, one
+// select, one add.
+__device__ inline uint32_t lane_key(uint32_t u) { return u << 16 | 0xFFFFu; }
+
+__device__ inline uint32_t gather(uint32_t md, uint32_t off, uint32_t lb, uint32_t U,
+                                  uint32_t Z) {
+    const uint32_t wrap = U >= md ? 2u * Z : 0u;
     return lb + off - wrap;
 }
 
@@ -232,7 +237,8 @@ constexpr uint32_t kPack2 = 0x07050301u;     // (R_k, R_k+1) -> pair words k, k+
 // issued first, then x = sat(L - R), folded into m1 / m2 / S.
 template <int K0, int K1, bool KEEP_GATHER>
 __device__ __forceinline__ void row_phase1(const uint8_t *__restrict__ smem, uint32_t lb,
-                                           const uint32_t *rd, const uint32_t *md, uint32_t u,
+                                           const uint32_t *rd, const uint32_t *md,
+                                           const uint32_t *mo, uint32_t u,
                                            int Z, int wr, uint32_t *xv, uint32_t *axv,
                                            uint32_t *la, u16x2 &m1, u16x2 &m2, uint32_t &S) {
     constexpr int n = K1 - K0;
@@ -240,7 +246,7 @@ __device__ __forceinline__ void row_phase1(const uint8_t *__restrict__ smem, uin
 #pragma unroll
     for (int i = 0; i < n; ++i) {
         if (K0 + i < wr) {  // wr: the row's weight (below K1 in the generic path)
-            const uint32_t a = gather(md[K0 + i], lb, u, (uint32_t)Z);
+            const uint32_t a = gather(md[K0 + i], mo[K0 + i], lb, lane_key(u), (uint32_t)Z);
             if (KEEP_GATHER) la[K0 + i] = a;
             lraw[i] = lds_ld16(smem, a);
         }
@@ -326,9 +332,12 @@ __device__ __forceinline__ void row_update_w(uint8_t *__restrict__ smem, uint32_
                                              const uint32_t *pre, int wr = W) {
     constexpr bool kWide = W > 10;
     const int wrow = GEN ? wr : W;
-    uint32_t md[W];
+    uint32_t md[W], mo[W];
 #pragma unroll
-    for (int k = 0; k < W; ++k) md[k] = meta[e0 + k];  // the table is padded
+    for (int k = 0; k < W; ++k) {
+        md[k] = meta[e0 + k];  // the table is padded
+        mo[k] = md[k] & 0xFFFFu;
+    }
     // This row's check-to-variable messages (none in the first iteration).
     constexpr int ND = (W + 1) / 2;
     const int nd = GEN ? (wr + 1) / 2 : ND;
@@ -351,13 +360,13 @@ __device__ __forceinline__ void row_update_w(uint8_t *__restrict__ smem, uint32_
     uint32_t S = 0;
     if constexpr (kWide) {
         constexpr int H = (W + 1) / 2;
-        row_phase1<0, H, false>(smem, lb, rd, md, u, Z, wrow, xv, axv, la, m1, m2, S);
+        row_phase1<0, H, false>(smem, lb, rd, md, mo, u, Z, wrow, xv, axv, la, m1, m2, S);
         // keep the halves apart: the scheduler would otherwise issue every
         // read of the row up front and hold both halves' registers at once
         __builtin_amdgcn_sched_barrier(0);
-        row_phase1<H, W, false>(smem, lb, rd, md, u, Z, wrow, xv, axv, la, m1, m2, S);
+        row_phase1<H, W, false>(smem, lb, rd, md, mo, u, Z, wrow, xv, axv, la, m1, m2, S);
     } else {
-        row_phase1<0, W, true>(smem, lb, rd, md, u, Z, wrow, xv, axv, la, m1, m2, S);
+        row_phase1<0, W, true>(smem, lb, rd, md, mo, u, Z, wrow, xv, axv, la, m1, m2, S);
     }
     const u16x2 a1 = normalise(m1, off16, wgt);
     const u16x2 a2 = normalise(m2, off16, wgt);
@@ -428,7 +437,8 @@ __device__ __forceinline__ void row_update_w(uint8_t *__restrict__ smem, uint32_
         for (int i = 0; i < 4; ++i) {
             const int k = g + i;
             if (k >= W || k >= wrow) continue;
-            const uint32_t a = kWide ? gather(md[k], lb, u, (uint32_t)Z) : la[k];
+            const uint32_t a =
+                kWide ? gather(md[k], mo[k], lb, lane_key(u), (uint32_t)Z) : la[k];
             lds_st16(smem, a, perm(bits_of(Lg[i]), kPack));
         }
 #pragma unroll
@@ -466,11 +476,15 @@ __device__ __forceinline__ void row_update_w(uint8_t *__restrict__ smem, uint32_
 template <int W>
 __device__ __forceinline__ uint32_t row_parity_w(const uint8_t *__restrict__ smem, uint32_t lb,
                                                  cmeta_t meta, int e0, uint32_t u, int Z) {
-    uint32_t md[W], raw[W];
+    uint32_t md[W], mo[W], raw[W];
 #pragma unroll
-    for (int k = 0; k < W; ++k) md[k] = meta[e0 + k];
+    for (int k = 0; k < W; ++k) {
+        md[k] = meta[e0 + k];
+        mo[k] = md[k] & 0xFFFFu;
+    }
 #pragma unroll
-    for (int k = 0; k < W; ++k) raw[k] = lds_ld16(smem, gather(md[k], lb, u, (uint32_t)Z));
+    for (int k = 0; k < W; ++k)
+        raw[k] = lds_ld16(smem, gather(md[k], mo[k], lb, lane_key(u), (uint32_t)Z));
     uint32_t acc = 0;
 #pragma unroll
     for (int k = 0; k < W; ++k) acc ^= raw[k];
