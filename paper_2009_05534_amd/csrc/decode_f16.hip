@@ -95,6 +95,41 @@ __device__ __forceinline__ void row_phase1(const uint32_t *__restrict__ Lw,
         }
         lraw[i] = Lw[g.addr];
     }
+    if constexpr (KEEP_GATHER) {
+        // Narrow rows (K0 = 0, every edge): each step over all edges at
+        // once and the two smallest magnitudes by a pairwise tree, so
+        // dependent packed operations are rarely adjacent (gfx950 inserts a
+        // wait state between them). Magnitudes compare as integers.
+#pragma unroll
+        for (int i = 0; i < n; ++i)
+            xv[i] = bits_of(as_h(swap_halves(lraw[i], swl[i])) - as_h(rraw[i]));
+#pragma unroll
+        for (int i = 0; i < n; ++i) S ^= xv[i];
+        constexpr int NP = (n + 1) / 2;
+        u16x2 lo[NP], hi[NP];
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+            const u16x2 a = as_u(xv[2 * q] & 0x7FFF7FFFu);
+            const u16x2 b =
+                2 * q + 1 < n ? as_u(xv[2 * q + 1] & 0x7FFF7FFFu) : (u16x2){0x7C00, 0x7C00};
+            lo[q] = __builtin_elementwise_min(a, b);
+            hi[q] = __builtin_elementwise_max(a, b);
+        }
+#pragma unroll
+        for (int w = 1; w < NP; w *= 2) {
+#pragma unroll
+            for (int q = 0; q + w < NP; q += 2 * w) {
+                const u16x2 l = __builtin_elementwise_min(lo[q], lo[q + w]);
+                const u16x2 h = __builtin_elementwise_min(__builtin_elementwise_max(lo[q], lo[q + w]),
+                                                          __builtin_elementwise_min(hi[q], hi[q + w]));
+                lo[q] = l;
+                hi[q] = h;
+            }
+        }
+        m1 = lo[0];
+        m2 = hi[0];
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < n; ++i) {
         const h16x2 L = as_h(swap_halves(lraw[i], swl[i]));
@@ -137,21 +172,40 @@ __device__ __forceinline__ void row_update_w(uint32_t *__restrict__ Lw, uint32_t
     const uint32_t a1 = normalise(bits_of(m1), off, wgt);
     const uint32_t a2 = normalise(bits_of(m2), off, wgt);
     const u16x2 m1p = m1 + (u16x2){1, 1};
+    // The write-back one step at a time over groups of edges (all of a
+    // narrow row, four of a wide one), for the same reason.
+    constexpr int G = kWide ? 4 : W;
 #pragma unroll
-    for (int k = 0; k < W; ++k) {
-        // mask = 0xFFFF on the argmin edge (|x| == m1), else 0.
-        const u16x2 t = __builtin_elementwise_sub_sat(m1p, as_u(xv[k] & 0x7FFF7FFFu));
-        const uint32_t mask = bits_of((u16x2){0, 0} - t);
-        const uint32_t mag = (a2 & mask) | (a1 & ~mask);
-        const uint32_t Rn = mag | ((S ^ xv[k]) & 0x80008000u);
-        const h16x2 Ln = as_h(xv[k]) + as_h(Rn);
-        if (kWide) {
-            const Gather g = gather(md[k], u, Zh);
-            Lw[g.addr] = swap_halves(bits_of(Ln), g.rot);
-        } else {
-            Lw[la[k]] = swap_halves(bits_of(Ln), sw[k]);
+    for (int g0 = 0; g0 < W; g0 += G) {
+        uint32_t Rg[G], Lg[G];
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+            const int k = g0 + i;
+            if (k >= W) continue;
+            // mask = 0xFFFF on the argmin edge (|x| == m1), else 0.
+            const u16x2 t = __builtin_elementwise_sub_sat(m1p, as_u(xv[k] & 0x7FFF7FFFu));
+            Rg[i] = bits_of((u16x2){0, 0} - t);
         }
-        msg_st(Rb, e0 + k, Zh, ro, Rn);
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+            const int k = g0 + i;
+            if (k >= W) continue;
+            const uint32_t mag = (a2 & Rg[i]) | (a1 & ~Rg[i]);
+            Rg[i] = mag | ((S ^ xv[k]) & 0x80008000u);
+            Lg[i] = bits_of(as_h(xv[k]) + as_h(Rg[i]));
+        }
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+            const int k = g0 + i;
+            if (k >= W) continue;
+            if (kWide) {
+                const Gather g = gather(md[k], u, Zh);
+                Lw[g.addr] = swap_halves(Lg[i], g.rot);
+            } else {
+                Lw[la[k]] = swap_halves(Lg[i], sw[k]);
+            }
+            msg_st(Rb, e0 + k, Zh, ro, Rg[i]);
+        }
     }
 }
 
