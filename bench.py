@@ -42,11 +42,17 @@ KERNEL_SOURCES = ("decode_i8.hip", "ldpc_internal.h")
 
 
 def kernel_source_sha() -> str:
+    """Hash of the int8 kernel's sources with comments and blank space
+    removed (a comment edit does not change the measured kernel)."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2009_05534_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, "paper_2009_05534_amd", "csrc", name)) as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

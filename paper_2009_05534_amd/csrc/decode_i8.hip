@@ -14,7 +14,8 @@
 // plus one fixed byte shuffle, with no per-lane half swapping.
 //
 // The Z independent rows of a layer (§II) run in parallel, layers strictly
-// in order with one workgroup barrier each; after every iteration the
+// in order, with a workgroup barrier wherever the next layer shares a block
+// column with the layers since the last barrier; after every iteration the
 // syndrome of the hard decisions is checked per codeword (a sweep that stops
 // at the first failing check), and a codeword whose checks all hold has its
 // outputs written at once (its half of the pair is still computed, but
