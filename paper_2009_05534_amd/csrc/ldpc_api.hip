@@ -308,7 +308,7 @@ int ldpc_decode_ex(const ldpc_args *a) {
     void *msg = nullptr;
     hipError_t e;
     if (!msg_in_lds) {
-        const size_t msg_bytes = i8 ? (size_t)((a->n_cw + 1) / 2) * p.E_pad * p.Z * 2
+        const size_t msg_bytes = i8 ? (((size_t)a->n_cw + 1) / 2) * p.E_pad * p.Z * 2
                                     : (size_t)a->n_cw * p.E * Zh * 4;
         e = hipMallocAsync(&msg, msg_bytes, stream);
         if (e != hipSuccess) return hip_fail(e, "hipMallocAsync(messages)");
