@@ -148,7 +148,8 @@ typedef struct ldpc_args {
 void ldpc_args_init(ldpc_args *a);
 
 /* ldpc_decode_ex -- decode with the options of ldpc_args. Messages kept in
- * device memory take n_cw*E*Z bytes (int8) or 2*n_cw*E*Z bytes (binary16),
+ * device memory take 2*ceil(n_cw/2)*E_pad*Z bytes (int8; E_pad = E with
+ * every row's weight rounded up to even) or 2*n_cw*E*Z bytes (binary16),
  * allocated per call with hipMallocAsync on `stream` and released the same
  * way.
  * Errors: as ldpc_decode. */
