@@ -71,6 +71,27 @@ def evaluate(pool, bg, Z, rows, wq, points, n_per_point, chunk, max_iter=10):
     return out
 
 
+class _InProcess:
+    """Executor stand-in that runs each job at once in this process
+    (--workers 0: no child processes, e.g. under a profiler)."""
+
+    class _Done:
+        def __init__(self, value):
+            self._value = value
+
+        def result(self):
+            return self._value
+
+    def submit(self, fn, arg):
+        return self._Done(fn(arg))
+
+    def map(self, fn, args):
+        return (fn(a) for a in args)
+
+    def shutdown(self):
+        pass
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--bg", type=int, default=1)
@@ -84,14 +105,16 @@ def main():
     ap.add_argument("--ebn0-hi", type=float, default=2.0)
     ap.add_argument("--eval-n", type=int, default=20_000, help="held-out codewords per point")
     ap.add_argument("--eval-points", default="1.0,1.25,1.5,1.75,2.0")
-    ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
+    ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1),
+                    help="data-generation processes (0: generate in this process)")
     ap.add_argument("--out", default=os.path.join(ROOT, "paper_2009_05534_amd", "weights",
                                                   "nwms_bg1_z384.npz"))
     ap.add_argument("--report-every", type=int, default=20)
     args = ap.parse_args()
 
     # worker processes first, before the GPU is touched
-    pool = cf.ProcessPoolExecutor(max_workers=args.workers, mp_context=mp.get_context("fork"))
+    pool = (cf.ProcessPoolExecutor(max_workers=args.workers, mp_context=mp.get_context("fork"))
+            if args.workers > 0 else _InProcess())
     g = make_graph(args.bg, args.Z)
     assert args.rows == g.M, "training uses the full graph"
 
