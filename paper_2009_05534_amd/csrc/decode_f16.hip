@@ -382,15 +382,14 @@ template <int WMAX>
 hipError_t launch_w(const DecodeLaunch &p, hipStream_t stream) {
     const int Zh = p.Z / 2;
     const int lds = p.cpw * lds_bytes_f16(p.n_cols, p.Z) + p.cpw * (int)sizeof(int);
-    static bool attr_set = false;
-    if (!attr_set) {
+    static std::once_flag attr_once;  // once per process, also under concurrent calls
+    std::call_once(attr_once, [] {
         // Opt in to more than the default 64 KiB of dynamic LDS.
         const hipError_t e = hipFuncSetAttribute(
             reinterpret_cast<const void *>(&decode_f16_kernel<WMAX>),
             hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes());
         if (e != hipSuccess) note_hip_error("hipFuncSetAttribute(decode_f16_kernel)", e);
-        attr_set = true;
-    }
+    });
     const int blocks = (p.n_cw + p.cpw - 1) / p.cpw;
     // hipGetLastError reports the last error of ANY earlier runtime call on
     // this thread; clear it so the check below sees this launch only.

@@ -842,15 +842,14 @@ hipError_t launch_w(const DecodeLaunch &p, hipStream_t stream) {
                                 : lds_bytes_i8_pair_post(p.n_cols, p.Z);
     const int pairs = p.cpw / 2;
     const int lds = pairs * per_pair + lds_flags_bytes_i8(pairs);
-    static bool attr_set = false;
-    if (!attr_set) {
+    static std::once_flag attr_once;  // once per process, also under concurrent calls
+    std::call_once(attr_once, [] {
         // Opt in to more than the default 64 KiB of dynamic LDS.
         const hipError_t e = hipFuncSetAttribute(
             reinterpret_cast<const void *>(&decode_i8_kernel<WMAX, IN_LDS>),
             hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes());
         if (e != hipSuccess) note_hip_error("hipFuncSetAttribute(decode_i8_kernel)", e);
-        attr_set = true;
-    }
+    });
     if (p.cpw < 2 || (p.cpw & 1) || pairs * p.Z > 768) {
         note_hip_error("decode_i8_kernel: bad workgroup shape", hipErrorInvalidValue);
         return hipErrorInvalidValue;
@@ -962,15 +961,14 @@ hipError_t launch_decode_batch(const BatchLaunch &b, hipStream_t stream) {
         note_hip_error("launch reset_counter_kernel", e);
         return e;
     }
-    static bool attr_set[2] = {false, false};
+    static std::once_flag attr_once[2];  // once per process, also under concurrent calls
     const void *fn = b.wmax <= 10 ? reinterpret_cast<const void *>(&decode_batch_kernel<10>)
                                   : reinterpret_cast<const void *>(&decode_batch_kernel<20>);
-    bool &set = attr_set[b.wmax <= 10 ? 0 : 1];
-    if (!set) {
-        e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes());
-        if (e != hipSuccess) note_hip_error("hipFuncSetAttribute(decode_batch_kernel)", e);
-        set = true;
-    }
+    std::call_once(attr_once[b.wmax <= 10 ? 0 : 1], [fn] {
+        const hipError_t ea =
+            hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes());
+        if (ea != hipSuccess) note_hip_error("hipFuncSetAttribute(decode_batch_kernel)", ea);
+    });
     (void)hipGetLastError();
     if (b.wmax <= 10)
         hipLaunchKernelGGL(decode_batch_kernel<10>, dim3(b.grid), dim3(b.lanes), b.lds, stream,

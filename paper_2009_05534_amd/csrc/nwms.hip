@@ -317,8 +317,8 @@ hipError_t launch_nwms(const float *llr, const uint8_t *cbits, const float *w, f
     p.scale = scale;
     const int threads = (Z + 63) / 64 * 64;
     const int lds = n_cols * Z * (int)sizeof(float);
-    static bool attr_set = false;
-    if (!attr_set) {
+    static std::once_flag attr_once;  // once per process, also under concurrent calls
+    std::call_once(attr_once, [] {
         hipError_t e1 = hipFuncSetAttribute(reinterpret_cast<const void *>(&nwms_forward_kernel),
                                             hipFuncAttributeMaxDynamicSharedMemorySize,
                                             max_lds_bytes());
@@ -327,8 +327,7 @@ hipError_t launch_nwms(const float *llr, const uint8_t *cbits, const float *w, f
                                             max_lds_bytes());
         if (e1 != hipSuccess) note_hip_error("hipFuncSetAttribute(nwms_forward_kernel)", e1);
         if (e2 != hipSuccess) note_hip_error("hipFuncSetAttribute(nwms_backward_kernel)", e2);
-        attr_set = true;
-    }
+    });
     (void)hipGetLastError();
     hipLaunchKernelGGL(nwms_forward_kernel, dim3(n_cw), dim3(threads), lds, stream, p, row_ptr,
                        meta_row);
