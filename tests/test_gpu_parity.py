@@ -271,3 +271,37 @@ def test_i8_wide_rows(Z, weights, kb):
             ref = oracle_i8(g, q, early_exit=early)
             got = gpu_decode(1, Z, g.M, q, msg_placement=placement, early_exit=early)
             assert_i8_equal(got, ref)
+
+
+def _random_cases(n_cases, seed):
+    import random
+    rng = random.Random(seed)
+    cases = []
+    for i in range(n_cases):
+        bg = rng.choice([1, 2])
+        Z = 8 * rng.randint(1, 48)           # any supported lift, not only the listed ones
+        rows = rng.randint(4, 46 if bg == 1 else 42)
+        n = rng.randint(1, 40 if Z <= 192 else 12)
+        cases.append((i, bg, Z, rows, n, rng.uniform(0.5, 3.0), rng.random() < 0.7,
+                      rng.choice(["auto", "device", "lds"]), rng.choice([0, 2, 4])))
+    return cases
+
+
+@pytest.mark.parametrize("i,bg,Z,rows,n,ebn0,ee,placement,cpw", _random_cases(40, 20261203))
+def test_random_shapes(i, bg, Z, rows, n, ebn0, ee, placement, cpw):
+    """Seeded random shapes, lifts, batch sizes, message placements and
+    workgroup packings: int8 bit-exact, binary16 close (small batches)."""
+    from paper_2009_05534_amd import ldpc
+    g = _graph(bg, Z, rows)
+    b = make_batch(g, n, ebn0, data_seed=2000 + i)
+    try:
+        got = gpu_decode(bg, Z, rows, b.q, early_exit=ee, msg_placement=placement,
+                         cw_per_block=cpw)
+    except ldpc.LdpcError:
+        # LDS placement of a pair that does not fit a workgroup is refused
+        assert placement == "lds"
+        return
+    assert_i8_equal(got, oracle_i8(g, b.q, early_exit=ee))
+    if n <= 16:
+        gf = gpu_decode(bg, Z, rows, b.q, precision="f16", early_exit=ee)
+        assert_f16_close(gf, oracle_f16(g, b.q, early_exit=ee))
