@@ -96,3 +96,26 @@ def test_batch_with_learned_weights(lib):
         ref = oracle.decode_i8(g, gr.batch.q, wq=w, n_threads=4)
         assert (jb.out_bits.cpu().numpy() == ref[0]).all()
         assert (jb.out_iters.cpu().numpy() == ref[1]).all()
+
+
+def test_small_lift_wave_tasks_random_lifts(lib):
+    """Lifts up to 64 (one wave per task, six tasks of any shapes to a
+    workgroup) mixed with larger ones, over lifts outside the standard set:
+    every job equals decoding it alone, with and without early exit."""
+    import random
+    rng = random.Random(7)
+    lifts = sorted({8 * rng.randint(1, 8) for _ in range(10)} | {8, 40, 56, 120, 200})
+    for bg in (1, 2):
+        for Z in lifts:
+            lib.register(make_graph(bg, Z))
+    groups = make_mixed(240, 1.25, seed=11, lifts=tuple(lifts))
+    assert any(gr.Z <= 64 for gr in groups) and any(gr.Z > 64 for gr in groups)
+    for ee in (True, False):
+        jobs = _jobs(lib, groups)
+        lib.decode_batch(jobs, early_exit=ee)
+        for gr, jb in zip(groups, jobs):
+            got = (jb.out_bits.cpu().numpy(), jb.out_iters.cpu().numpy(),
+                   jb.out_ok.cpu().numpy().astype(bool))
+            alone = _alone(lib, gr, early_exit=ee)
+            for a, b in zip(got, alone):
+                assert (a == b).all(), (ee, gr.bg, gr.Z, gr.rows)
