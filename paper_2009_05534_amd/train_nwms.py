@@ -110,11 +110,41 @@ def main():
     ap.add_argument("--out", default=os.path.join(ROOT, "paper_2009_05534_amd", "weights",
                                                   "nwms_bg1_z384.npz"))
     ap.add_argument("--report-every", type=int, default=20)
+    ap.add_argument("--init", default="",
+                    help="start from this checkpoint's weights (fresh optimiser state)")
+    ap.add_argument("--data-start", type=int, default=0,
+                    help="index of the first training codeword (fresh data when continuing)")
+    ap.add_argument("--eval-only", default="",
+                    help="evaluate this checkpoint (no training); results go to "
+                         "<checkpoint>_eval<n>.json")
     args = ap.parse_args()
 
     # worker processes first, before the GPU is touched
     pool = (cf.ProcessPoolExecutor(max_workers=args.workers, mp_context=mp.get_context("fork"))
             if args.workers > 0 else _InProcess())
+    if args.eval_only:
+        import torch
+
+        from paper_2009_05534_amd import ldpc, nwms
+        g = make_graph(args.bg, args.Z)
+        torch.cuda.set_device(0)
+        ldpc.register(g)
+        wq, meta = nwms.load_weights(args.eval_only)
+        assert meta["graph_digest"] == g.digest(), "checkpoint of another graph"
+        points = [float(x) for x in args.eval_points.split(",")]
+        t1 = time.time()
+        ev = {}
+        for p in points:  # one point at a time, so progress shows
+            ev.update(evaluate(pool, args.bg, args.Z, args.rows, wq, [p], args.eval_n, 8192))
+            print(json.dumps({str(p): ev[str(p)]}), flush=True)
+        summary = {"checkpoint": os.path.basename(args.eval_only), "eval_n": args.eval_n,
+                   "eval_seconds": round(time.time() - t1, 1), "eval": ev}
+        out = os.path.splitext(args.eval_only)[0] + f"_eval{args.eval_n}.json"
+        with open(out, "w") as f:
+            json.dump(summary, f, indent=1)
+        print(f"[eval] wrote {out}", flush=True)
+        pool.shutdown()
+        return
     g = make_graph(args.bg, args.Z)
     assert args.rows == g.M, "training uses the full graph"
 
@@ -124,11 +154,17 @@ def main():
     torch.cuda.set_device(0)
     ldpc.register(g)
     tr = nwms.Trainer(args.bg, args.Z, args.rows, n_iter=args.n_iter, lr=args.lr)
+    if args.init:
+        _, meta0 = nwms.load_weights(args.init)
+        assert meta0["graph_digest"] == g.digest(), "checkpoint of another graph"
+        with np.load(args.init, allow_pickle=False) as f0:
+            tr.w = np.array(f0["w"], dtype=np.float64)
     chunk = args.batch * 8
-    starts = list(range(0, args.n_train, chunk))
+    end = args.data_start + args.n_train
+    starts = list(range(args.data_start, end, chunk))
     t0 = time.time()
     rng_db = (args.ebn0_lo, args.ebn0_hi)
-    futs = [pool.submit(_train_chunk, (args.bg, args.Z, s, min(chunk, args.n_train - s), *rng_db))
+    futs = [pool.submit(_train_chunk, (args.bg, args.Z, s, min(chunk, end - s), *rng_db))
             for s in starts[:2]]
     nxt = 2
     seen = 0
@@ -137,7 +173,7 @@ def main():
         if nxt < len(starts):
             s = starts[nxt]
             futs.append(pool.submit(_train_chunk, (args.bg, args.Z, s,
-                                                   min(chunk, args.n_train - s), *rng_db)))
+                                                   min(chunk, end - s), *rng_db)))
             nxt += 1
         for i in range(0, q.shape[0], args.batch):
             loss = tr.step(q[i:i + args.batch], c[i:i + args.batch])
@@ -147,7 +183,9 @@ def main():
                       f"w[mean] {tr.w.mean():.4f} {time.time() - t0:.0f}s", flush=True)
     train_s = time.time() - t0
     tr.save(args.out, g.digest(), extra={"n_train": seen, "batch": args.batch,
-                                          "train_seconds": train_s, "ebn0_db": list(rng_db)})
+                                          "train_seconds": train_s, "ebn0_db": list(rng_db),
+                                          "init": os.path.basename(args.init) or None,
+                                          "data_start": args.data_start})
     print(f"[train] saved {args.out} after {seen} codewords in {train_s:.0f}s", flush=True)
     points = [float(x) for x in args.eval_points.split(",")]
     t1 = time.time()
