@@ -221,8 +221,11 @@ void ldpc_plan_destroy(ldpc_plan *plan);
  *           natural-log LLR is llr / scale
  *   cbits : uint8 [n_cw][Nc] the transmitted codewords, 0/1 (device)
  *   w     : float [n_iter][rows] multipliers (device)
- *   loss  : float [n_cw] out: mean over iterations t and code bits j of
- *           BCE(sigmoid(-L_tj / scale), c_j), L_t the posteriors after t
+ *   iter_w: float [n_iter] loss weight of each iteration (device), or NULL
+ *           for 1/n_iter each
+ *   loss  : float [n_cw] out: sum over iterations t of iter_w[t] times the
+ *           mean over code bits j of BCE(sigmoid(-L_tj / scale), c_j), L_t
+ *           the posteriors after t
  *   grad  : float [n_iter][rows] out: d(sum of loss)/dw, summed over the
  *           codewords in index order
  *   out_llr : float [n_cw][Nc] final posteriors or NULL
@@ -235,8 +238,8 @@ void ldpc_plan_destroy(ldpc_plan *plan);
  */
 #define LDPC_NWMS_MAX_ROW_WEIGHT 20
 int ldpc_nwms_loss_grad(int bg, int Z, int rows, int n_cw, const float *llr,
-                        const uint8_t *cbits, int n_iter, const float *w, float scale,
-                        float *loss, float *grad, float *out_llr, void *stream);
+                        const uint8_t *cbits, int n_iter, const float *w, const float *iter_w,
+                        float scale, float *loss, float *grad, float *out_llr, void *stream);
 
 /* Error text for a return code; the last HIP error code seen by the
  * library (hipError_t as int, 0 if none). */

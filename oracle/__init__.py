@@ -46,8 +46,8 @@ def _load():
                                           ctypes.c_uint16, P, I, P, P, P, P, I]
         lib.oracle_decode_f64.argtypes = [I, I, I, I, I, P, P, P, I, P, I, I, ctypes.c_double,
                                           ctypes.c_double, P, I, P, P, P, P, I]
-        lib.oracle_nwms_grad_f64.argtypes = [I, I, I, I, P, P, P, I, P, P, I, P, ctypes.c_double,
-                                             P, P]
+        lib.oracle_nwms_grad_f64.argtypes = [I, I, I, I, P, P, P, I, P, P, I, P, P,
+                                             ctypes.c_double, P, P]
         lib.oracle_nwms_grad_f64.restype = ctypes.c_int
         lib.oracle_f64_to_f16.argtypes = [P, P, ctypes.c_long]
         lib.oracle_f16_to_f64.argtypes = [P, P, ctypes.c_long]
@@ -148,11 +148,12 @@ def decode_f64(g, llr, max_iter=10, early_exit=True, beta=0.75, delta=0.0, w=Non
     return bits, iters, ok.astype(bool), out
 
 
-def nwms_loss_grad(g, llr, cbits, w, scale=4.0):
+def nwms_loss_grad(g, llr, cbits, w, scale=4.0, iter_w=None):
     """Learned weighted min-sum in double precision: per-codeword loss
-    (mean over iterations and bits of the BCE of sigmoid(-L/scale) against
-    the codeword) and the exact gradient of the summed loss with respect to
-    the weights w [n_iter, M]. llr [n_cw, T] real, cbits [n_cw, N*Z] 0/1."""
+    (over iterations t weighted by iter_w[t], default 1/n_iter each, the
+    mean over bits of the BCE of sigmoid(-L/scale) against the codeword)
+    and the exact gradient of the summed loss with respect to the weights
+    w [n_iter, M]. llr [n_cw, T] real, cbits [n_cw, N*Z] 0/1."""
     llr = np.ascontiguousarray(llr, dtype=np.float64)
     cb = np.ascontiguousarray(cbits, dtype=np.uint8)
     w = np.ascontiguousarray(w, dtype=np.float64)
@@ -162,8 +163,13 @@ def nwms_loss_grad(g, llr, cbits, w, scale=4.0):
     dims, (rp, col, sh) = _graph_args(g)
     loss = np.zeros(n_cw)
     grad = np.zeros_like(w)
+    lam = None
+    if iter_w is not None:
+        lam = np.ascontiguousarray(iter_w, dtype=np.float64)
+        assert lam.shape == (w.shape[0],)
     rc = _load().oracle_nwms_grad_f64(g.M, g.N, g.Z, g.n_punct, _ptr(rp), _ptr(col), _ptr(sh),
                                       n_cw, _ptr(llr), _ptr(cb), w.shape[0], _ptr(w),
+                                      _ptr(lam) if lam is not None else None,
                                       float(scale), _ptr(loss), _ptr(grad))
     if rc != 0:
         raise ValueError(f"oracle_nwms_grad_f64 failed ({rc})")

@@ -560,7 +560,8 @@ int oracle_decode_f64(int M, int N, int Z, int n_punct, int K,
  * iterations. Posterior after iteration t: L_t. With y = L_t / scale (scale
  * converts the LLR units to natural-log units) and p = sigmoid(-y) =
  * P(bit = 1), the loss of a codeword c is
- *     loss = (1/n_iter) * sum_t (1/(N*Z)) * sum_j BCE(p_tj, c_j),
+ *     loss = sum_t lambda_t * (1/(N*Z)) * sum_j BCE(p_tj, c_j),
+ * with per-iteration loss weights lambda_t (iter_w; NULL: 1/n_iter each),
  * BCE(p, c) = -(c log p + (1 - c) log(1 - p)); dBCE/dL = (c - p) / scale.
  *
  * Backward (reverse of the layered schedule). Each check-row update
@@ -583,7 +584,8 @@ static double softplus(double v) { return v > 0 ? v + log1p(exp(-v)) : log1p(exp
 int oracle_nwms_grad_f64(int M, int N, int Z, int n_punct,
                          const int32_t *row_ptr, const int16_t *col, const int16_t *shift,
                          int n_cw, const double *llr, const uint8_t *cbits, int n_iter,
-                         const double *w, double scale, double *loss, double *grad_w) {
+                         const double *w, const double *iter_w, double scale, double *loss,
+                         double *grad_w) {
     graph_t g = {M, N, Z, n_punct, row_ptr, col, shift};
     if (!graph_check(&g) || n_cw < 1 || n_iter < 1 || !llr || !cbits || !w || !loss ||
         !grad_w || !(scale > 0))
@@ -639,17 +641,21 @@ int oracle_nwms_grad_f64(int M, int N, int Z, int n_punct,
         }
         /* loss */
         double lsum = 0.0;
-        for (int t = 0; t < n_iter; ++t)
+        for (int t = 0; t < n_iter; ++t) {
+            const double lam = iter_w ? iter_w[t] : 1.0 / n_iter;
+            double st = 0.0;
             for (int j = 0; j < NZ; ++j) {
                 const double y = Lt[(size_t)t * NZ + j] / scale;
-                lsum += c[j] ? softplus(y) : softplus(-y);
+                st += c[j] ? softplus(y) : softplus(-y);
             }
-        loss[cw] = lsum / ((double)n_iter * NZ);
+            lsum += lam * st;
+        }
+        loss[cw] = lsum / NZ;
         /* backward */
         for (int j = 0; j < NZ; ++j) gL[j] = 0.0;
         for (size_t i = 0; i < (size_t)E * Z; ++i) gR[i] = 0.0;
-        const double coef = 1.0 / ((double)n_iter * NZ * scale);
         for (int t = n_iter - 1; t >= 0; --t) {
+            const double coef = (iter_w ? iter_w[t] : 1.0 / n_iter) / ((double)NZ * scale);
             for (int j = 0; j < NZ; ++j) {
                 const double y = Lt[(size_t)t * NZ + j] / scale;
                 const double p = 1.0 / (1.0 + exp(y)); /* sigmoid(-y) */

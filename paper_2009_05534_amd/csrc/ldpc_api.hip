@@ -338,8 +338,8 @@ int ldpc_decode(int bg, int Z, int rows, int n_cw, const int8_t *llr_in, int max
 }
 
 int ldpc_nwms_loss_grad(int bg, int Z, int rows, int n_cw, const float *llr,
-                        const uint8_t *cbits, int n_iter, const float *w, float scale,
-                        float *loss, float *grad, float *out_llr, void *stream) {
+                        const uint8_t *cbits, int n_iter, const float *w, const float *iter_w,
+                        float scale, float *loss, float *grad, float *out_llr, void *stream) {
     if (n_cw < 1 || n_iter < 1 || n_iter > LDPC_MAX_ITER || !llr || !cbits || !w || !loss ||
         !grad || !(scale > 0.0f))
         return LDPC_EINVAL;
@@ -369,7 +369,8 @@ int ldpc_nwms_loss_grad(int bg, int Z, int rows, int n_cw, const float *llr,
     const size_t bytes = sizeof(float) * nwms_workspace_floats(n_cw, rows, n_cols, Z, E, n_iter);
     hipError_t e = hipMallocAsync(&ws, bytes, stream_h);
     if (e != hipSuccess) return hip_fail(e, "hipMallocAsync(nwms workspace)");
-    e = launch_nwms(llr, cbits, w, loss, grad, out_llr, static_cast<float *>(ws), n_cw, rows,
+    e = launch_nwms(llr, cbits, w, iter_w, loss, grad, out_llr, static_cast<float *>(ws), n_cw,
+                    rows,
                     n_cols, Z, E, n_iter, scale, row_ptr, meta_row, wmax, stream_h);
     const hipError_t ef = hipFreeAsync(ws, stream_h);
     if (e != hipSuccess) return e == hipErrorOutOfMemory ? LDPC_ENOMEM : LDPC_EHIP;

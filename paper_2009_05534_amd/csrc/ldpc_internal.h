@@ -205,7 +205,8 @@ hipError_t launch_decode_f16(const DecodeLaunch &p, hipStream_t stream);
 
 // Learned weighted min-sum: forward, backward and gradient reduction.
 size_t nwms_workspace_floats(int n_cw, int rows, int n_cols, int Z, int E, int n_iter);
-hipError_t launch_nwms(const float *llr, const uint8_t *cbits, const float *w, float *loss,
+hipError_t launch_nwms(const float *llr, const uint8_t *cbits, const float *w,
+                       const float *iter_w, float *loss,
                        float *grad, float *out_llr, float *ws, int n_cw, int rows, int n_cols,
                        int Z, int E, int n_iter, float scale, const int32_t *row_ptr,
                        const uint32_t *meta_row, int wmax, hipStream_t stream);

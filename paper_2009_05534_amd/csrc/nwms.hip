@@ -7,8 +7,9 @@
 // layered schedule with L_v in LDS, check-to-variable messages R in device
 // memory; every variable-to-check message x is recorded on a device tape,
 // and after each iteration t the loss gradient of the posteriors,
-//     dLoss/dL_tj = (c_j - sigmoid(-L_tj/scale)) / (n_iter * N*Z * scale),
-// is stored (loss = mean over t and j of BCE(sigmoid(-L_tj/scale), c_j)).
+//     dLoss/dL_tj = lambda_t * (c_j - sigmoid(-L_tj/scale)) / (N*Z * scale),
+// is stored (loss = sum over t of lambda_t times the mean over j of
+// BCE(sigmoid(-L_tj/scale), c_j); lambda_t = iter_w[t], or 1/n_iter).
 // Backward: the same schedule in reverse with dLoss/dL in LDS and dLoss/dR
 // in device memory; per check row, with signs and argmins fixed,
 //     g_k  = (gL'_k + gR'_k) * s_k,  dw += sum_k g_k * (k == k1 ? m2 : m1),
@@ -168,6 +169,7 @@ struct NwmsLaunch {
     const float *llr;        // [n_cw][T]
     const uint8_t *cbits;    // [n_cw][Nc]
     const float *w;          // [n_iter][rows]
+    const float *iter_w;     // [n_iter] loss weight per iteration, or null (1/n_iter)
     float *loss;             // [n_cw]
     float *out_llr;          // [n_cw][Nc] final posteriors or null
     float *ws;               // per-codeword workspace
@@ -198,9 +200,10 @@ __global__ __launch_bounds__(512) void nwms_forward_kernel(NwmsLaunch p,
         for (int col = 2; col < N; ++col) L[col * Z + z] = p.llr[(size_t)cw * T + (col - 2) * Z + z];
     }
     __syncthreads();
-    const float coef = 1.0f / ((float)p.n_iter * (float)Nc * p.scale);
     float lsum = 0.0f;
     for (int t = 0; t < p.n_iter; ++t) {
+        const float lam = p.iter_w ? p.iter_w[t] : 1.0f / (float)p.n_iter;
+        const float coef = lam / ((float)Nc * p.scale);
         float *tp = tape + (size_t)t * E * Z;
         for (int r = 0; r < p.rows; ++r) {
             const int e0 = row_ptr[r], w = row_ptr[r + 1] - e0;
@@ -215,20 +218,20 @@ __global__ __launch_bounds__(512) void nwms_forward_kernel(NwmsLaunch p,
                 const float y = L[j] / p.scale;
                 const float pr = 1.0f / (1.0f + expf(y));  // sigmoid(-y)
                 dl[j] = ((float)c[j] - pr) * coef;
-                lsum += c[j] ? softplusf(y) : softplusf(-y);
+                lsum += lam * (c[j] ? softplusf(y) : softplusf(-y));
             }
         }
     }
     if (p.out_llr && lane)
         for (int col = 0; col < N; ++col) p.out_llr[(size_t)cw * Nc + col * Z + z] = L[col * Z + z];
-    // loss of the codeword: mean over iterations and bits
+    // loss of the codeword: weighted over iterations, mean over bits
     const float ws_sum = wave_sum(lane ? lsum : 0.0f);
     if ((threadIdx.x & 63) == 0) wpart[threadIdx.x >> 6] = ws_sum;
     __syncthreads();
     if (threadIdx.x == 0) {
         float s = 0.0f;
         for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += wpart[i];
-        p.loss[cw] = s / ((float)p.n_iter * (float)Nc);
+        p.loss[cw] = s / (float)Nc;
     }
 }
 
@@ -294,8 +297,8 @@ size_t nwms_workspace_floats(int n_cw, int rows, int n_cols, int Z, int E, int n
     return per * n_cw + (size_t)n_cw * n_iter * rows;
 }
 
-hipError_t launch_nwms(const float *llr, const uint8_t *cbits, const float *w, float *loss,
-                       float *grad, float *out_llr, float *ws, int n_cw, int rows, int n_cols,
+hipError_t launch_nwms(const float *llr, const uint8_t *cbits, const float *w,
+                       const float *iter_w, float *loss, float *grad, float *out_llr, float *ws, int n_cw, int rows, int n_cols,
                        int Z, int E, int n_iter, float scale, const int32_t *row_ptr,
                        const uint32_t *meta_row, int wmax, hipStream_t stream) {
     if (wmax > kNwmsWmax) return hipErrorInvalidValue;
@@ -303,6 +306,7 @@ hipError_t launch_nwms(const float *llr, const uint8_t *cbits, const float *w, f
     p.llr = llr;
     p.cbits = cbits;
     p.w = w;
+    p.iter_w = iter_w;
     p.loss = loss;
     p.out_llr = out_llr;
     p.ws = ws;

@@ -89,7 +89,7 @@ def lib():
         L.ldpc_plan_info.argtypes = [P, P, P, P]
         L.ldpc_plan_destroy.argtypes = [P]
         L.ldpc_plan_destroy.restype = None
-        L.ldpc_nwms_loss_grad.argtypes = [I, I, I, I, P, P, I, P, ctypes.c_float, P, P, P, P]
+        L.ldpc_nwms_loss_grad.argtypes = [I, I, I, I, P, P, I, P, P, ctypes.c_float, P, P, P, P]
         L.ldpc_strerror.argtypes = [I]
         L.ldpc_strerror.restype = ctypes.c_char_p
         L.ldpc_last_hip_error.argtypes = []
@@ -233,13 +233,15 @@ def decode(llr, bg: int, Z: int, rows: int, *, max_iter: int = 10, precision: st
 
 
 def nwms_loss_grad(llr, cbits, w, bg: int, Z: int, rows: int, *, scale: float = 4.0,
-                   want_llr: bool = False, stream=None):
+                   iter_w=None, want_llr: bool = False, stream=None):
     """Learned weighted min-sum on the GPU: fp32 unrolled forward pass over
     w.shape[0] iterations, loss per codeword and the gradient of the summed
     loss with respect to w [n_iter, rows] (hand-written backward kernel).
 
-    llr float32 [n, T] and cbits uint8 [n, Nc] are device tensors; returns
-    (loss [n], grad [n_iter, rows], final posteriors [n, Nc] or None)."""
+    llr float32 [n, T] and cbits uint8 [n, Nc] are device tensors; iter_w a
+    float32 device tensor [n_iter] of per-iteration loss weights or None
+    (1/n_iter each); returns (loss [n], grad [n_iter, rows], final
+    posteriors [n, Nc] or None)."""
     import torch
     K, T, Nc, E = query(bg, Z, rows)
     n = int(llr.shape[0])
@@ -248,12 +250,16 @@ def nwms_loss_grad(llr, cbits, w, bg: int, Z: int, rows: int, *, scale: float = 
     if w.dim() != 2 or w.shape[1] != rows:
         raise ValueError("w must be [n_iter, rows]")
     _require(w, tuple(w.shape), 4, "w")
+    if iter_w is not None:
+        _require(iter_w, (int(w.shape[0]),), 4, "iter_w")
     dev = llr.device
     loss = torch.empty(n, dtype=torch.float32, device=dev)
     grad = torch.empty(tuple(w.shape), dtype=torch.float32, device=dev)
     out = torch.empty((n, Nc), dtype=torch.float32, device=dev) if want_llr else None
     _check(lib().ldpc_nwms_loss_grad(bg, Z, rows, n, llr.data_ptr(), cbits.data_ptr(),
-                                     int(w.shape[0]), w.data_ptr(), float(scale), loss.data_ptr(),
+                                     int(w.shape[0]), w.data_ptr(),
+                                     iter_w.data_ptr() if iter_w is not None else None,
+                                     float(scale), loss.data_ptr(),
                                      grad.data_ptr(), out.data_ptr() if out is not None else None,
                                      _stream_ptr(stream)), "ldpc_nwms_loss_grad")
     return loss, grad, out

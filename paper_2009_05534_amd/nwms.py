@@ -52,8 +52,10 @@ class Trainer:
     (used as fp32 in LLR units of 1/scale) and transmitted codewords."""
 
     def __init__(self, bg: int, Z: int, rows: int, n_iter: int = 10, lr: float = 1e-2,
-                 beta0: float = 0.75, scale: float = 4.0, device="cuda:0"):
+                 beta0: float = 0.75, scale: float = 4.0, device="cuda:0", iter_w=None):
         self.bg, self.Z, self.rows, self.n_iter, self.scale = bg, Z, rows, n_iter, scale
+        # per-iteration loss weights (None: the mean over iterations)
+        self.iter_w = None if iter_w is None else np.asarray(iter_w, dtype=np.float32)
         self.w = np.full((n_iter, rows), beta0, dtype=np.float64)
         self.opt = Adam(lr=lr)
         self.device = device
@@ -68,8 +70,9 @@ class Trainer:
         llr = torch.from_numpy(np.ascontiguousarray(q, dtype=np.float32)).to(dev)
         cb = torch.from_numpy(np.ascontiguousarray(c, dtype=np.uint8)).to(dev)
         w = torch.from_numpy(self.w.astype(np.float32)).to(dev)
+        lam = None if self.iter_w is None else torch.from_numpy(self.iter_w).to(dev)
         loss, grad, _ = ldpc.nwms_loss_grad(llr, cb, w, self.bg, self.Z, self.rows,
-                                            scale=self.scale)
+                                            scale=self.scale, iter_w=lam)
         n = q.shape[0]
         g = grad.cpu().numpy().astype(np.float64) / n
         self.w = np.clip(self.opt.step(self.w, g), 0.0, W_MAX)

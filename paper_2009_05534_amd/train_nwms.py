@@ -110,6 +110,9 @@ def main():
     ap.add_argument("--out", default=os.path.join(ROOT, "paper_2009_05534_amd", "weights",
                                                   "nwms_bg1_z384.npz"))
     ap.add_argument("--report-every", type=int, default=20)
+    ap.add_argument("--loss-iters", default="mean",
+                    help="loss weight per iteration: 'mean' (1/n_iter each), 'ramp' "
+                         "(proportional to the iteration number t) or 'pow:P' (to t**P)")
     ap.add_argument("--init", default="",
                     help="start from this checkpoint's weights (fresh optimiser state)")
     ap.add_argument("--data-start", type=int, default=0,
@@ -153,7 +156,17 @@ def main():
     from paper_2009_05534_amd import ldpc, nwms
     torch.cuda.set_device(0)
     ldpc.register(g)
-    tr = nwms.Trainer(args.bg, args.Z, args.rows, n_iter=args.n_iter, lr=args.lr)
+    iter_w = None
+    if args.loss_iters != "mean":
+        if args.loss_iters == "ramp":
+            power = 1.0
+        elif args.loss_iters.startswith("pow:"):
+            power = float(args.loss_iters[4:])
+        else:
+            raise SystemExit(f"unknown --loss-iters {args.loss_iters}")
+        iter_w = np.arange(1, args.n_iter + 1, dtype=np.float64) ** power
+        iter_w /= iter_w.sum()
+    tr = nwms.Trainer(args.bg, args.Z, args.rows, n_iter=args.n_iter, lr=args.lr, iter_w=iter_w)
     if args.init:
         _, meta0 = nwms.load_weights(args.init)
         assert meta0["graph_digest"] == g.digest(), "checkpoint of another graph"
@@ -185,6 +198,7 @@ def main():
     tr.save(args.out, g.digest(), extra={"n_train": seen, "batch": args.batch,
                                           "train_seconds": train_s, "ebn0_db": list(rng_db),
                                           "init": os.path.basename(args.init) or None,
+                                          "loss_iters": args.loss_iters,
                                           "data_start": args.data_start})
     print(f"[train] saved {args.out} after {seen} codewords in {train_s:.0f}s", flush=True)
     points = [float(x) for x in args.eval_points.split(",")]

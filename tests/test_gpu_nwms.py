@@ -16,12 +16,14 @@ def _gpu():
         pytest.skip("no GPU")
 
 
-@pytest.mark.parametrize("bg,Z,rows,T,n,ebn0", [
-    (2, 16, 12, 3, 4, 1.0),
-    (1, 32, 20, 4, 3, 1.5),
-    (1, 384, 46, 2, 2, 1.5),
+@pytest.mark.parametrize("bg,Z,rows,T,n,ebn0,weighted", [
+    (2, 16, 12, 3, 4, 1.0, False),
+    (1, 32, 20, 4, 3, 1.5, False),
+    (1, 384, 46, 2, 2, 1.5, False),
+    (2, 16, 12, 3, 4, 1.0, True),
+    (1, 32, 20, 4, 3, 1.5, True),
 ])
-def test_loss_grad_match_oracle(bg, Z, rows, T, n, ebn0):
+def test_loss_grad_match_oracle(bg, Z, rows, T, n, ebn0, weighted):
     from paper_2009_05534_amd import ldpc
     full = make_graph(bg, Z)
     ldpc.register(full)
@@ -32,10 +34,14 @@ def test_loss_grad_match_oracle(bg, Z, rows, T, n, ebn0):
     dl = torch.from_numpy(llr).cuda()
     dc = torch.from_numpy(b.c).cuda()
     dw = torch.from_numpy(w).cuda()
-    loss, grad, post = ldpc.nwms_loss_grad(dl, dc, dw, bg, Z, rows, want_llr=True)
+    # per-iteration loss weights (rising towards the last iteration), or the default
+    lam = np.linspace(0.5, 1.5, T).astype(np.float32) / T if weighted else None
+    dlam = torch.from_numpy(lam).cuda() if weighted else None
+    loss, grad, post = ldpc.nwms_loss_grad(dl, dc, dw, bg, Z, rows, iter_w=dlam, want_llr=True)
     torch.cuda.synchronize()
-    ref_loss, ref_grad = oracle.nwms_loss_grad(g, llr.astype(np.float64), b.c,
-                                               w.astype(np.float64))
+    ref_loss, ref_grad = oracle.nwms_loss_grad(
+        g, llr.astype(np.float64), b.c, w.astype(np.float64),
+        iter_w=lam.astype(np.float64) if weighted else None)
     assert np.allclose(loss.cpu().numpy(), ref_loss, rtol=1e-5, atol=0)
     gg = grad.cpu().numpy().astype(np.float64)
     assert np.linalg.norm(gg - ref_grad) <= 1e-4 * np.linalg.norm(ref_grad)
