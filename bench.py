@@ -230,6 +230,25 @@ def main():
         "mean_iters": mean_it,
     }
 
+    # The learned weighted min-sum (default checkpoint, trained for this
+    # shape) against plain min-sum on the same batches, outside the timing.
+    wpath = os.path.join(ROOT, "paper_2009_05534_amd", "weights", "nwms_bg1_z384.npz")
+    if os.path.exists(wpath):
+        from paper_2009_05534_amd import nwms
+        wq, _ = nwms.load_weights(wpath)
+        wdev = torch.from_numpy(np.ascontiguousarray(wq)).to(dev)
+        lb, li = {}, {}
+        for i, b in enumerate(batches):
+            ldpc.decode_into(llr[i], BG, Z, ROWS, bits[i], iters[i], max_iter=args.max_iter,
+                             weights=wdev, out_ok=oks[i])
+            torch.cuda.synchronize()
+            got = np.unpackbits(bits[i].cpu().numpy(), axis=1, bitorder="little")[:, :K]
+            lb[str(EBN0_POINTS[i])] = float(np.mean((got != b.u).any(axis=1)))
+            li[str(EBN0_POINTS[i])] = float(iters[i].float().mean().item())
+        result["learned"] = {"checkpoint": os.path.basename(wpath), "bler": lb, "mean_iters": li,
+                             "note": "int8 decoder with the trained per-(iteration, row) weights; "
+                                     "bler/mean_iters above are plain beta = 3/4"}
+
     if not args.no_extras:
         log("timing int8, fixed 10 iterations")
         w10, l10, eu10 = timed("i8", False, 2, 1)
