@@ -57,6 +57,13 @@ extern "C" {
 #define LDPC_MAX_ITER 64
 
 /*
+ * Graph tables are data. The library holds no base-graph generator and so
+ * exports no seeded initialiser: the caller registers each lifted base graph
+ * with ldpc_set_graph (the same call would load the standard's tables), can
+ * read back what is registered with ldpc_get_graph, and can check it by its
+ * digest (ldpc_graph_digest). A checker that must decode the same graph as
+ * the library takes the table from ldpc_get_graph.
+ *
  * ldpc_set_graph -- register the full base graph `bg` (an identifier >= 1)
  * lifted by Z (§II). The graph has m_rows block rows and n_cols = kb + m_rows
  * block columns, the first 2 columns punctured. Block e of row r
@@ -78,6 +85,28 @@ int ldpc_set_graph(int bg, int Z, int m_rows, int kb, const int32_t *row_ptr,
  * K information bits, T transmitted LLRs per codeword ((kb+rows-2)*Z),
  * Nc = (kb+rows)*Z code bits, E nonzero blocks. Any output may be NULL. */
 int ldpc_query(int bg, int Z, int rows, int *K, int *T, int *Nc, int *E);
+
+/*
+ * ldpc_get_graph -- the registered base graph (bg, Z) as a list of nonzero
+ * blocks, row-major with columns ascending within a row (§II: block (r, c)
+ * with shift s is a Z x Z cyclic permutation). Host pointers owned by the
+ * caller. *nnz is in/out: on entry the capacity of row/col/shift, on return
+ * the number of blocks E. With row, col and shift all NULL only the sizes
+ * are returned (m_rows, kb, nnz may each be NULL).
+ * Errors: LDPC_ENOGRAPH; LDPC_EINVAL (some but not all of row/col/shift
+ * NULL, nnz NULL, or capacity below E; nothing is written).
+ */
+int ldpc_get_graph(int bg, int Z, int *m_rows, int *kb, int *nnz, int16_t *row, int16_t *col,
+                   int16_t *shift);
+
+/*
+ * ldpc_graph_digest -- 64-bit FNV-1a digest of the registered graph
+ * (bg, Z): the bytes hashed are little-endian int32 words bg, Z, m_rows,
+ * kb, row_ptr[0..m_rows], col[0..E), shift[0..E) (col and shift
+ * sign-extended). Host-side only; no device call.
+ * Errors: LDPC_EINVAL (out NULL), LDPC_ENOGRAPH.
+ */
+int ldpc_graph_digest(int bg, int Z, uint64_t *out);
 
 /*
  * ldpc_decode -- layered normalised min-sum (beta = 3/4), int8 path, early
@@ -191,6 +220,13 @@ int ldpc_decode_batch(const ldpc_job *jobs, int n_jobs, int max_iter, int early_
  * the device memory the launch holds until it completes. */
 int ldpc_decode_batch_async(const ldpc_job *jobs, int n_jobs, int max_iter, int early_exit,
                             void *stream, size_t *bytes_in_flight);
+
+/* Device bytes that ldpc_decode_batch_async would hold in flight for these
+ * jobs (tables, task queue and per-workgroup message regions), computed on
+ * the host without allocating or launching: what a caller admitting work
+ * against a memory budget must reserve. Same argument checks as the batch
+ * calls. Errors: LDPC_EINVAL, LDPC_ENOGRAPH. */
+int ldpc_decode_batch_bytes(const ldpc_job *jobs, int n_jobs, size_t *bytes);
 
 /* A reusable plan bound to the jobs' buffers (refill the inputs and launch
  * again). Flags: LDPC_PLAN_GRAPH captures the launch (a counter-reset

@@ -23,22 +23,41 @@ _LIB = os.path.join(_HERE, "libldpc_oracle.so")
 _lib = None
 
 
+def _compile(out: str, extra: list[str]) -> None:
+    tmp = out + ".tmp"
+    subprocess.check_call(["gcc", "-O3", *extra, "-std=c11", "-Wall", "-Wextra", "-fPIC",
+                           "-shared", "-o", tmp, _SRC, "-lm", "-lpthread"])
+    os.replace(tmp, out)
+
+
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain C, no vectorising intrinsics)."""
+    """Compile the oracle with gcc -O3 (plain C, no intrinsics; generic x86-64
+    code, so the built library runs on any host it is copied to)."""
     if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared",
-                               "-o", tmp, _SRC, "-lm", "-lpthread"])
-        os.replace(tmp, _LIB)
+        _compile(_LIB, [])
     return _LIB
 
 
-def _load():
+def use_native_build(directory: str) -> str:
+    """Compile the oracle with -O3 -march=native for the host it runs on into
+    ``directory`` and make this module use that build (the CPU baseline's
+    timing; the arithmetic is the same C source). Returns the library path."""
+    global _lib
+    path = os.path.join(directory, "libldpc_oracle_native.so")
+    _compile(path, ["-march=native"])
+    _lib = None
+    _load(path)
+    return path
+
+
+def _load(path: str | None = None):
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build(force=True)
-        lib = ctypes.CDLL(_LIB)
+        if path is None:
+            path = _LIB
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build(force=True)
+        lib = ctypes.CDLL(path)
         P = ctypes.c_void_p
         I = ctypes.c_int
         lib.oracle_decode_i8.argtypes = [I, I, I, I, I, P, P, P, I, P, I, I, I, P, I, P, P, P, P, I]

@@ -32,12 +32,30 @@ def _compile(src: str, obj: str, verbose: bool) -> None:
     subprocess.check_call(cmd)
 
 
-def build(verbose: bool = False) -> str:
+def _stale(src: str, obj: str) -> bool:
+    """An object is stale when it is missing or older than its source or
+    any header of the source directory (or the public header)."""
+    if not os.path.exists(obj):
+        return True
+    deps = [src, os.path.join(HERE, "..", "include", "ldpc.h")]
+    deps += [os.path.join(CSRC, h) for h in os.listdir(CSRC) if h.endswith(".h")]
+    t = os.path.getmtime(obj)
+    return any(os.path.getmtime(d) > t for d in deps)
+
+
+def build(verbose: bool = False, incremental: bool = False) -> str:
+    """Compile every source (or, with incremental=True, only those whose
+    object in _build/ is stale) and link libldpc.so."""
     with tempfile.TemporaryDirectory(prefix="ldpc_build_") as tmpdir:
-        objs = [os.path.join(tmpdir, s.replace(".hip", ".o")) for s in SOURCES]
-        with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-            futs = [ex.submit(_compile, os.path.join(CSRC, s), o, verbose)
-                    for s, o in zip(SOURCES, objs)]
+        objdir = tmpdir
+        if incremental:
+            objdir = os.path.join(HERE, "..", "_build")
+            os.makedirs(objdir, exist_ok=True)
+        objs = [os.path.join(objdir, s.replace(".hip", ".o")) for s in SOURCES]
+        todo = [(s, o) for s, o in zip(SOURCES, objs)
+                if not incremental or _stale(os.path.join(CSRC, s), o)]
+        with cf.ThreadPoolExecutor(max_workers=max(1, len(todo))) as ex:
+            futs = [ex.submit(_compile, os.path.join(CSRC, s), o, verbose) for s, o in todo]
             for f in futs:
                 f.result()
         tmp = LIB + ".tmp"
@@ -50,5 +68,5 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose="-v" in sys.argv)
+    build(verbose="-v" in sys.argv, incremental="-i" in sys.argv)
     print(LIB)

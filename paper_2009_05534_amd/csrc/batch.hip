@@ -47,7 +47,7 @@ hipError_t size_messages(Plan *p, int grid) {
         if (p->d_msg) (void)hipFree(p->d_msg);
         p->d_msg = nullptr;
         p->msg_capacity = 0;
-        hipError_t e = hipMalloc(&p->d_msg, need * sizeof(uint16_t));
+        hipError_t e = hipMalloc(&p->d_msg, need * sizeof(uint16_t) + kMsgTail);
         if (e != hipSuccess) return e;
         p->msg_capacity = need;
     }
@@ -237,6 +237,41 @@ int plan_launch(Plan *p, hipStream_t stream) {
 
 void plan_destroy(Plan *p) { free_plan(p); }
 
+namespace {
+// Device memory layout of a one-shot asynchronous batch launch:
+// tasks | jobs | wave tasks | counter | messages (256-aligned).
+struct AsyncLayout {
+    int grid = 1;
+    size_t tb = 0, jbytes = 0, wbytes = 0, o_waves = 0, o_counter = 0, o_msg = 0, total = 0;
+};
+
+AsyncLayout async_layout(const TaskSet &ts, size_t n_jobs, int lds_cap) {
+    AsyncLayout L;
+    int dev = 0, cus = 1;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int per_cu = std::max(1, std::min(8, lds_cap / std::max(ts.lds, 1)));
+    L.grid = std::max(1, std::min((int)ts.tasks.size(), std::max(cus, 1) * per_cu));
+    L.tb = sizeof(BatchTask) * ts.tasks.size();
+    L.jbytes = sizeof(BatchJob) * n_jobs;
+    L.wbytes = sizeof(WaveTask) * ts.waves.size();
+    L.o_waves = L.tb + L.jbytes;
+    L.o_counter = (L.o_waves + L.wbytes + 255) & ~(size_t)255;
+    L.o_msg = L.o_counter + 256;
+    L.total = L.o_msg + (size_t)L.grid * ts.msg_per_block * sizeof(uint16_t) + kMsgTail;
+    return L;
+}
+}  // namespace
+
+int batch_async_bytes(const std::vector<BatchJob> &jobs, const std::vector<int> &job_cw,
+                      int lds_cap, size_t *bytes) {
+    TaskSet ts;
+    const int rc = build_tasks(jobs, job_cw, lds_cap, ts);
+    if (rc != LDPC_OK) return rc;
+    *bytes = async_layout(ts, jobs.size(), lds_cap).total;
+    return LDPC_OK;
+}
+
 // One launch over `jobs` with every buffer stream-ordered on `stream`: the
 // tables and message regions are allocated with hipMallocAsync, filled,
 // used by the persistent kernel and released, all without blocking the
@@ -249,18 +284,11 @@ int batch_async(const std::vector<BatchJob> &jobs, const std::vector<int> &job_c
     if (rc != LDPC_OK) return rc;
     const std::vector<BatchTask> &tasks = ts.tasks;
     const int lds = ts.lds, msg_per_block = ts.msg_per_block;
-    int dev = 0, cus = 1;
-    (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    const int per_cu = std::max(1, std::min(8, lds_cap / std::max(lds, 1)));
-    const int grid = std::max(1, std::min((int)tasks.size(), std::max(cus, 1) * per_cu));
-    const size_t tb = sizeof(BatchTask) * tasks.size(), jbytes = sizeof(BatchJob) * jobs.size();
-    const size_t wbytes = sizeof(WaveTask) * ts.waves.size();
-    // layout: tasks | jobs | wave tasks | counter | messages (256-aligned)
-    const size_t o_waves = tb + jbytes, o_counter = (o_waves + wbytes + 255) & ~(size_t)255;
-    const size_t o_msg = o_counter + 256;
-    const size_t mbytes = (size_t)grid * msg_per_block * sizeof(uint16_t);
-    const size_t total = o_msg + mbytes;
+    const AsyncLayout lay = async_layout(ts, jobs.size(), lds_cap);
+    const int grid = lay.grid;
+    const size_t tb = lay.tb, jbytes = lay.jbytes;
+    const size_t o_waves = lay.o_waves, o_counter = lay.o_counter, o_msg = lay.o_msg;
+    const size_t total = lay.total;
     uint8_t *buf = nullptr;
     hipError_t e = hipMallocAsync(reinterpret_cast<void **>(&buf), total, stream);
     if (e != hipSuccess) {

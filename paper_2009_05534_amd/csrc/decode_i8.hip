@@ -738,8 +738,8 @@ __device__ __forceinline__ void decode_block(const BlockWork &bw, uint8_t *smem,
     int *flags = reinterpret_cast<int *>(smem + bw.slots * pair_bytes);
     // The workgroup's message region as a raw buffer (dword 3 = 0x00020000:
     // untyped 32-bit data format for gfx9 raw buffer access).
-    const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
-        bw.msg, 0, IN_LDS ? 0 : 2 * bw.slots * bw.E_pad * Z, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rsrc =
+        __builtin_amdgcn_make_buffer_rsrc(bw.msg, 0, IN_LDS ? 0 : bw.msg_records, 0x00020000);
 
     // Initialisation: punctured columns 0 and 1 carry no channel LLR.
     if (validA) {
@@ -818,6 +818,14 @@ __global__ __launch_bounds__(768) __attribute__((amdgpu_waves_per_eu(5))) void d
                            : nullptr;
     bw.msg = IN_LDS ? nullptr
                     : reinterpret_cast<uint16_t *>(p.msg) + (size_t)(first / 2) * p.E_pad * p.Z;
+    if (!IN_LDS) {
+        // this workgroup's pairs up to the end of the allocation (the last
+        // workgroup may hold fewer than cpw / 2 pairs)
+        const size_t base = (size_t)(first / 2) * p.E_pad * p.Z * 2;
+        const size_t full = (size_t)(p.cpw / 2) * p.E_pad * p.Z * 2;
+        const size_t left = p.msg_bytes - base;
+        bw.msg_records = (uint32_t)(left < full ? left : full);
+    }
     bw.row_pad = p.row_pad;
     bw.E_pad = p.E_pad;
     bw.groups = p.groups;
@@ -916,6 +924,9 @@ __global__ __launch_bounds__(kBatchLanes) __attribute__((amdgpu_waves_per_eu(5))
             bw.out_llr = nullptr;
             bw.msg = msg_ws + (size_t)blockIdx.x * msg_per_block +
                      (wave_task ? (size_t)wv * wave_msg : 0);
+            // the task's pairs lie inside the workgroup's region; the region
+            // of the last workgroup is followed by the allocation's tail
+            bw.msg_records = 2u * (uint32_t)(bw.slots * jb.E_pad * jb.Z) + (uint32_t)kMsgTail;
             bw.row_pad = jb.row_pad;
             bw.E_pad = jb.E_pad;
             bw.groups = jb.groups;

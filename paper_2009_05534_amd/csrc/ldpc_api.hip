@@ -191,6 +191,56 @@ int ldpc_set_graph(int bg, int Z, int m_rows, int kb, const int32_t *row_ptr, co
     return LDPC_OK;
 }
 
+// FNV-1a (64-bit) over the registered table serialised as little-endian
+// int32 words: bg, Z, m_rows, kb, row_ptr[0..m_rows], col[0..E), shift[0..E).
+int ldpc_graph_digest(int bg, int Z, uint64_t *out) {
+    if (!out) return LDPC_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_graphs.find({bg, Z});
+    if (it == g_graphs.end()) return LDPC_ENOGRAPH;
+    const HostGraph &g = it->second;
+    uint64_t h = 0xcbf29ce484222325ull;
+    auto word = [&h](int32_t v) {
+        const uint32_t u = (uint32_t)v;
+        for (int b = 0; b < 4; ++b) {
+            h ^= (u >> (8 * b)) & 0xFFu;
+            h *= 0x100000001b3ull;
+        }
+    };
+    word(g.bg);
+    word(g.Z);
+    word(g.m_rows);
+    word(g.kb);
+    for (int32_t v : g.row_ptr) word(v);
+    for (int16_t v : g.col) word(v);
+    for (int16_t v : g.shift) word(v);
+    *out = h;
+    return LDPC_OK;
+}
+
+int ldpc_get_graph(int bg, int Z, int *m_rows, int *kb, int *nnz, int16_t *row, int16_t *col,
+                   int16_t *shift) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_graphs.find({bg, Z});
+    if (it == g_graphs.end()) return LDPC_ENOGRAPH;
+    const HostGraph &g = it->second;
+    const int E = g.row_ptr.back();
+    if ((row || col || shift) && (!row || !col || !shift || !nnz || *nnz < E))
+        return LDPC_EINVAL;
+    if (m_rows) *m_rows = g.m_rows;
+    if (kb) *kb = g.kb;
+    if (row) {
+        for (int r = 0; r < g.m_rows; ++r)
+            for (int e = g.row_ptr[r]; e < g.row_ptr[r + 1]; ++e) {
+                row[e] = (int16_t)r;
+                col[e] = g.col[e];
+                shift[e] = g.shift[e];
+            }
+    }
+    if (nnz) *nnz = E;
+    return LDPC_OK;
+}
+
 int ldpc_query(int bg, int Z, int rows, int *K, int *T, int *Nc, int *E) {
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = g_graphs.find({bg, Z});
@@ -308,8 +358,9 @@ int ldpc_decode_ex(const ldpc_args *a) {
     void *msg = nullptr;
     hipError_t e;
     if (!msg_in_lds) {
-        const size_t msg_bytes = i8 ? (((size_t)a->n_cw + 1) / 2) * p.E_pad * p.Z * 2
+        const size_t msg_bytes = i8 ? (((size_t)a->n_cw + 1) / 2) * p.E_pad * p.Z * 2 + kMsgTail
                                     : (size_t)a->n_cw * p.E * Zh * 4;
+        p.msg_bytes = msg_bytes;
         e = hipMallocAsync(&msg, msg_bytes, stream);
         if (e != hipSuccess) return hip_fail(e, "hipMallocAsync(messages)");
     }
@@ -481,6 +532,16 @@ int ldpc_decode_batch_async(const ldpc_job *jobs, int n_jobs, int max_iter, int 
     if (rc != LDPC_OK) return rc;
     return batch_async(bj, job_cw, kBatchLanes, max_iter, early_exit ? 1 : 0, wmax, lds_cap,
                        static_cast<hipStream_t>(stream), bytes_in_flight);
+}
+
+int ldpc_decode_batch_bytes(const ldpc_job *jobs, int n_jobs, size_t *bytes) {
+    if (!jobs || n_jobs < 1 || !bytes) return LDPC_EINVAL;
+    std::vector<BatchJob> bj;
+    std::vector<int> job_cw;
+    int wmax = 0, lds_cap = 0;
+    const int rc = batch_jobs(jobs, n_jobs, bj, job_cw, wmax, lds_cap);
+    if (rc != LDPC_OK) return rc;
+    return batch_async_bytes(bj, job_cw, lds_cap, bytes);
 }
 
 int ldpc_decode_batch(const ldpc_job *jobs, int n_jobs, int max_iter, int early_exit,

@@ -57,6 +57,8 @@ struct DecodeLaunch {
     int n_cw, rows, n_cols, kb, Z, E, E_pad;
     int max_iter, early_exit;
     int beta, offset;         // int8: Q1.7 beta and offset; f16: bit patterns
+    size_t msg_bytes;         // bytes allocated at msg (int8 device placement;
+                              // kMsgTail bytes past the last pair's region)
     int cpw;                  // codewords per workgroup (int8: even, two per pair)
     int wmax;                 // max row weight over the kept rows
     uint64_t groups;          // int8: bit r set = row r starts a new layer
@@ -77,6 +79,10 @@ struct BlockWork {
                               // [row_pad[r]*Z, row_pad[r+1]*Z), lane u's Wp
                               // (the row weight rounded up to even) messages
                               // contiguous at u*Wp
+    uint32_t msg_records;     // device placement: bytes of the message region
+                              // this workgroup may touch (its allocated pairs
+                              // plus the allocation's tail), the raw buffer's
+                              // range: a read beyond it returns zero
     const int32_t *row_pad;   // even-padded row starts
     uint64_t groups;          // bit r: row r needs a barrier before it
     const uint8_t *wq;        // per-(iteration, row) weights or null
@@ -150,9 +156,16 @@ int plan_launch(Plan *p, hipStream_t stream);
 void plan_destroy(Plan *p);
 Plan *plan_new();
 void plan_info(const Plan *p, int *grid, int *n_tasks, float *tuned_ms);
+int batch_async_bytes(const std::vector<BatchJob> &jobs, const std::vector<int> &job_cw,
+                      int lds_cap, size_t *bytes);
 int batch_async(const std::vector<BatchJob> &jobs, const std::vector<int> &job_cw, int lanes,
                 int max_iter, int early_exit, int wmax, int lds_cap, hipStream_t stream,
                 size_t *bytes_in_flight);
+
+// Bytes allocated past the last int8 message region: a lane's message loads
+// move whole dwordx4 chunks, which for the last lane of the last pair can
+// reach up to 12 bytes past its row (the dwords beyond the row are unused).
+constexpr size_t kMsgTail = 16;
 
 // Bytes of LDS one int8 codeword pair needs (posteriors and messages, or
 // posteriors only) and one binary16 codeword.

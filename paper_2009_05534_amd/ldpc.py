@@ -54,8 +54,8 @@ class Job(ctypes.Structure):
 PLAN_GRAPH = 1
 PLAN_AUTOTUNE = 2
 
-EXPORTS = ("ldpc_set_graph", "ldpc_query", "ldpc_decode", "ldpc_args_init", "ldpc_decode_ex",
-           "ldpc_decode_batch", "ldpc_decode_batch_async", "ldpc_plan_create", "ldpc_plan_launch", "ldpc_plan_info",
+EXPORTS = ("ldpc_set_graph", "ldpc_query", "ldpc_get_graph", "ldpc_graph_digest", "ldpc_decode", "ldpc_args_init", "ldpc_decode_ex",
+           "ldpc_decode_batch", "ldpc_decode_batch_async", "ldpc_decode_batch_bytes", "ldpc_plan_create", "ldpc_plan_launch", "ldpc_plan_info",
            "ldpc_plan_destroy", "ldpc_nwms_loss_grad", "ldpc_strerror", "ldpc_last_hip_error",
            "ldpc_last_error_message", "ldpc_shutdown")
 
@@ -77,11 +77,15 @@ def lib():
         L.ldpc_set_graph.argtypes = [I, I, I, I, P, P, P]
         L.ldpc_query.argtypes = [I, I, I, P, P, P, P]
         L.ldpc_decode.argtypes = [I, I, I, I, P, I, P, P, P]
+        L.ldpc_get_graph.argtypes = [I, I, P, P, P, P, P, P]
+        L.ldpc_graph_digest.argtypes = [I, I, P]
         L.ldpc_args_init.argtypes = [ctypes.POINTER(Args)]
         L.ldpc_args_init.restype = None
         L.ldpc_decode_ex.argtypes = [ctypes.POINTER(Args)]
         L.ldpc_decode_batch.argtypes = [ctypes.POINTER(Job), I, I, I, P]
         L.ldpc_decode_batch_async.argtypes = [ctypes.POINTER(Job), I, I, I, P,
+                                              ctypes.POINTER(ctypes.c_size_t)]
+        L.ldpc_decode_batch_bytes.argtypes = [ctypes.POINTER(Job), I,
                                               ctypes.POINTER(ctypes.c_size_t)]
         L.ldpc_plan_create.argtypes = [ctypes.POINTER(Job), I, I, I, I, P,
                                        ctypes.POINTER(ctypes.c_void_p)]
@@ -126,6 +130,27 @@ def query(bg: int, Z: int, rows: int) -> tuple[int, int, int, int]:
     out = [ctypes.c_int() for _ in range(4)]
     _check(lib().ldpc_query(bg, Z, rows, *[ctypes.addressof(o) for o in out]), "ldpc_query")
     return tuple(o.value for o in out)
+
+
+def get_graph(bg: int, Z: int):
+    """The registered graph (bg, Z) as (m_rows, kb, row, col, shift): one
+    entry per nonzero block, row-major, columns ascending (numpy int16)."""
+    L = lib()
+    m, kb, nnz = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(L.ldpc_get_graph(bg, Z, ctypes.byref(m), ctypes.byref(kb), ctypes.byref(nnz),
+                            None, None, None), "ldpc_get_graph")
+    row, col, shift = (np.empty(nnz.value, np.int16) for _ in range(3))
+    _check(L.ldpc_get_graph(bg, Z, ctypes.byref(m), ctypes.byref(kb), ctypes.byref(nnz),
+                            row.ctypes.data, col.ctypes.data, shift.ctypes.data),
+           "ldpc_get_graph")
+    return m.value, kb.value, row, col, shift
+
+
+def graph_digest(bg: int, Z: int) -> int:
+    """64-bit FNV-1a digest of the registered graph (see include/ldpc.h)."""
+    out = ctypes.c_uint64()
+    _check(lib().ldpc_graph_digest(bg, Z, ctypes.byref(out)), "ldpc_graph_digest")
+    return out.value
 
 
 def _require(t, shape, itemsize, name):
@@ -324,6 +349,16 @@ def decode_batch_async(jobs, *, max_iter: int = 10, early_exit: bool = True,
     _check(lib().ldpc_decode_batch_async(arr, len(jobs), max_iter, int(early_exit),
                                          _stream_ptr(stream), ctypes.byref(nb)),
            "ldpc_decode_batch_async")
+    return int(nb.value)
+
+
+def decode_batch_bytes(jobs) -> int:
+    """Device bytes decode_batch_async would hold in flight for these jobs
+    (computed without allocating or launching)."""
+    arr = _job_array(jobs)
+    nb = ctypes.c_size_t()
+    _check(lib().ldpc_decode_batch_bytes(arr, len(jobs), ctypes.byref(nb)),
+           "ldpc_decode_batch_bytes")
     return int(nb.value)
 
 

@@ -5,14 +5,18 @@ arrive as a Poisson process. Their int8 LLRs sit in device memory from
 arrival on (the device-resident input queue). The server keeps up to
 `n_slots` decode launches in flight, each on its own stream: whenever a slot
 is free and blocks are waiting, it admits waiting blocks in earliest-deadline
-order for as long as the device-memory budget for check-to-variable
-messages allows, and launches them as ONE persistent mixed-shape decode
-(ldpc.decode_batch_async). Blocks that arrive while other launches run are
-admitted as soon as a slot and memory free up, so their work overlaps on the
-device. Blocks of the shape the learned per-(iteration, row) weights were
-trained for are decoded with them; their codewords whose checks fail are
-decoded again with plain normalised min-sum (beta = 3/4) as the fallback. A block's latency runs from
-its arrival to the host seeing its last launch complete.
+order for as long as the device-memory budget allows -- charged with the
+exact bytes the library reports a launch of those blocks holds in flight
+(tables, task queue and per-workgroup message regions,
+ldpc.decode_batch_bytes) -- and launches them as ONE persistent mixed-shape
+decode (ldpc.decode_batch_async). Blocks that arrive while other launches
+run are admitted as soon as a slot and memory free up, so their work
+overlaps on the device. Blocks of the shape the learned per-(iteration, row)
+weights were trained for are decoded with them; the codewords of such a
+block whose checks fail are decoded again with plain normalised min-sum
+(beta = 3/4) as the fallback, and only those codewords take the plain
+result. A block's latency runs from its arrival to the host seeing its last
+launch complete.
 """
 from __future__ import annotations
 
@@ -73,11 +77,6 @@ def rescale(blocks: list[Block], rate_hz: float) -> list[Block]:
                                 iters=None, ok=None, fallback=False) for b in blocks]
 
 
-def message_bytes(bg: int, Z: int, rows: int, n_cw: int) -> int:
-    """Device bytes of int8 messages a block needs while it is decoded."""
-    from . import ldpc
-    _, _, _, E = ldpc.query(bg, Z, rows)
-    return n_cw * E * Z
 
 
 class Server:
@@ -112,7 +111,7 @@ class Server:
         return self._w_dev[rows]
 
     def _prepare(self, blocks):
-        torch, ldpc = self.torch, self.ldpc
+        torch = self.torch
         for b in blocks:
             b._llr = torch.from_numpy(b.q).to(self.dev)
             K = b.u.shape[1]
@@ -120,20 +119,35 @@ class Server:
             b._iters = torch.empty(b.n_cw, dtype=torch.int32, device=self.dev)
             b._ok = torch.empty(b.n_cw, dtype=torch.uint8, device=self.dev)
             b._ok_host = torch.empty(b.n_cw, dtype=torch.uint8, pin_memory=True)
-            b._mem = message_bytes(b.bg, b.Z, b.rows, b.n_cw)
-            if b._mem > self.mem_budget:
-                raise ValueError(f"block {b.id} needs more message memory than the budget")
+            b._plain = None
+            if self._weights(b.bg, b.rows, b.Z) is not None:
+                # the fallback pass writes here; merged per codeword afterwards
+                b._plain = (torch.empty_like(b._bits), torch.empty_like(b._iters),
+                            torch.empty_like(b._ok))
+            if self.ldpc.decode_batch_bytes(self._jobs([b], False)) > self.mem_budget:
+                raise ValueError(f"block {b.id} needs more device memory than the budget")
         torch.cuda.synchronize(self.dev)
-        del ldpc
 
     def _jobs(self, batch, plain: bool):
         ldpc = self.ldpc
         jobs = []
         for b in batch:
             w = None if plain else self._weights(b.bg, b.rows, b.Z)
-            jobs.append(ldpc.BatchJob(b._llr, b.bg, b.Z, b.rows, weights=w, out_bits=b._bits,
-                                      out_iters=b._iters, out_ok=b._ok))
+            bits, iters, ok = b._plain if plain else (b._bits, b._iters, b._ok)
+            jobs.append(ldpc.BatchJob(b._llr, b.bg, b.Z, b.rows, weights=w, out_bits=bits,
+                                      out_iters=iters, out_ok=ok))
         return jobs
+
+    def _merge_fallback(self, batch):
+        """Codewords whose learned pass failed take the plain pass's result;
+        the others keep theirs (enqueued on the current stream)."""
+        torch = self.torch
+        for b in batch:
+            pb, pi, po = b._plain
+            keep = b._ok.bool()
+            b._bits.copy_(torch.where(keep[:, None], b._bits, pb))
+            b._iters.copy_(torch.where(keep, b._iters, pi))
+            b._ok.copy_(torch.where(keep, b._ok, po))
 
     def run(self, blocks: list[Block]) -> dict:
         """Serve the trace in real time; returns latency/throughput stats."""
@@ -181,18 +195,22 @@ class Server:
                 while free_slots and queue:
                     queue.sort(key=lambda b: b.arrival)  # earliest deadline first
                     batch, mem = [], 0
-                    while (queue and len(batch) < self.max_blocks
-                           and mem_used + mem + queue[0]._mem <= self.mem_budget):
-                        b = queue.pop(0)
-                        batch.append(b)
-                        mem += b._mem
+                    while queue and len(batch) < self.max_blocks:
+                        need = self.ldpc.decode_batch_bytes(self._jobs(batch + [queue[0]], plain))
+                        if mem_used + need > self.mem_budget:
+                            break
+                        batch.append(queue.pop(0))
+                        mem = need
                     if not batch:
                         break
                     slot = free_slots.pop()
                     st = self.streams[slot]
-                    self.ldpc.decode_batch_async(self._jobs(batch, plain), max_iter=self.max_iter,
-                                                 stream=st)
+                    held = self.ldpc.decode_batch_async(self._jobs(batch, plain),
+                                                        max_iter=self.max_iter, stream=st)
+                    assert held == mem, (held, mem)
                     with torch.cuda.stream(st):
+                        if plain:
+                            self._merge_fallback(batch)
                         for b in batch:
                             b._ok_host.copy_(b._ok, non_blocking=True)
                     ev = torch.cuda.Event()
@@ -215,7 +233,7 @@ class Server:
             "blocks": len(order),
             "codewords": int(sum(b.n_cw for b in order)),
             "launches": launches,
-            "peak_message_bytes": peak_mem,
+            "peak_bytes_in_flight": peak_mem,
             "offered_blocks_per_s": len(order) / max(order[-1].arrival, 1e-9),
             "gbps": bits / t_end / 1e9,
             "latency_ms_p50": float(np.percentile(lat, 50) * 1e3),
@@ -235,8 +253,11 @@ class Server:
         bits, iters, ok, _ = ldpc.decode(llr, b.bg, b.Z, b.rows, max_iter=self.max_iter,
                                          weights=w, msg_placement="device")
         if w is not None and not bool(ok.all()):
-            bits, iters, ok, _ = ldpc.decode(llr, b.bg, b.Z, b.rows, max_iter=self.max_iter,
-                                             msg_placement="device")
+            pb, pi, po, _ = ldpc.decode(llr, b.bg, b.Z, b.rows, max_iter=self.max_iter,
+                                        msg_placement="device")
+            bits = torch.where(ok[:, None], bits, pb)
+            iters = torch.where(ok, iters, pi)
+            ok = torch.where(ok, ok, po)
         torch.cuda.synchronize(self.dev)
         return bits.cpu().numpy(), iters.cpu().numpy(), ok.cpu().numpy().astype(bool)
 

@@ -82,3 +82,74 @@ def test_decode_rejects_bad_arguments_before_launch(lib):
     a.bg = 7
     assert lib_.ldpc_decode_ex(ctypes.byref(a)) == -4
     assert lib_.ldpc_strerror(-4) == b"no graph registered for (bg, Z)"
+
+
+# 64-bit FNV-1a digests of the seeded BG-shaped graphs as registered (the
+# serialisation ldpc_graph_digest documents). A change of the generator, of
+# its seed or of the registration shows up here without a GPU.
+GRAPH_DIGESTS = {
+    (1, 16): 0xfa3e352ac64691f6, (1, 32): 0x04781dd60869e805, (1, 64): 0x12bb92c0e39589f7,
+    (1, 96): 0x41c5b9a7810d7709, (1, 128): 0x67d9d517a853400b, (1, 192): 0xf3e01120b1f0731d,
+    (1, 256): 0xa42ed78e52ae34a4, (1, 384): 0xd9b4ecb517ac63f7,
+    (2, 16): 0xb456a0fae817d9b4, (2, 32): 0x62eabcbdbc688626, (2, 64): 0x4410fcd8fa721a9e,
+    (2, 96): 0x5e010df5469887f5, (2, 128): 0x7be67e2e0d1d5dd2, (2, 192): 0xcd7a794444470530,
+    (2, 256): 0x058183d5c1e6d741, (2, 384): 0xce829705b36186da,
+}
+
+
+def _fnv1a64_words(words):
+    """FNV-1a 64 over little-endian 32-bit words (the published constants)."""
+    h = 0xcbf29ce484222325
+    for w in words:
+        for byte in int(w & 0xFFFFFFFF).to_bytes(4, "little"):
+            h = ((h ^ byte) * 0x100000001b3) & 0xFFFFFFFFFFFFFFFF
+    return h
+
+
+def test_graph_digest_and_readback(lib):
+    from paper_2009_05534_amd import ldpc
+    from synth import LIFTS, make_graph
+    for bg in (1, 2):
+        for Z in LIFTS:
+            g = make_graph(bg, Z)
+            ldpc.register(g)
+            # called through the raw C ABI
+            out = ctypes.c_uint64()
+            assert lib.ldpc_graph_digest(bg, Z, ctypes.byref(out)) == 0
+            assert out.value == GRAPH_DIGESTS[(bg, Z)], (bg, Z, hex(out.value))
+            words = [bg, Z, g.M, g.kb, *g.row_ptr.tolist(), *g.col.tolist(), *g.shift.tolist()]
+            assert out.value == _fnv1a64_words(words)
+            m, kb, nnz = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(0)
+            assert lib.ldpc_get_graph(bg, Z, ctypes.byref(m), ctypes.byref(kb),
+                                      ctypes.byref(nnz), None, None, None) == 0
+            assert (m.value, kb.value, nnz.value) == (g.M, g.kb, g.E)
+            row, col, sh = (np.full(g.E, -1, np.int16) for _ in range(3))
+            assert lib.ldpc_get_graph(bg, Z, None, None, ctypes.byref(nnz),
+                                      row.ctypes.data_as(ctypes.c_void_p),
+                                      col.ctypes.data_as(ctypes.c_void_p),
+                                      sh.ctypes.data_as(ctypes.c_void_p)) == 0
+            assert (col == g.col).all() and (sh == g.shift).all()
+            assert (np.bincount(row, minlength=g.M) == np.diff(g.row_ptr)).all()
+            assert (np.diff(row) >= 0).all()
+    # too small a buffer, a partial set of arrays, an unregistered graph
+    small = ctypes.c_int(10)
+    buf = np.zeros(10, np.int16)
+    p = buf.ctypes.data_as(ctypes.c_void_p)
+    assert lib.ldpc_get_graph(1, 384, None, None, ctypes.byref(small), p, p, p) == -1
+    assert (buf == 0).all()
+    assert lib.ldpc_get_graph(1, 384, None, None, ctypes.byref(small), p, None, None) == -1
+    assert lib.ldpc_get_graph(2, 24, None, None, ctypes.byref(small), None, None, None) == -4
+    assert lib.ldpc_graph_digest(1, 384, None) == -1
+
+
+def test_library_graph_feeds_the_oracle(lib):
+    # the helper the GPU comparisons use hands the oracle exactly the
+    # registered table, sub-codes included
+    from libgraph import library_graph
+    from synth import make_graph
+    for bg, Z, rows in ((1, 384, 46), (2, 16, 42), (1, 32, 7)):
+        ref = make_graph(bg, Z, rows)
+        got = library_graph(bg, Z, rows)
+        assert (got.M, got.N, got.kb, got.n_punct) == (ref.M, ref.N, ref.kb, ref.n_punct)
+        assert (got.row_ptr == ref.row_ptr).all()
+        assert (got.col == ref.col).all() and (got.shift == ref.shift).all()

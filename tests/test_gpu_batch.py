@@ -4,6 +4,7 @@ import numpy as np
 import pytest
 
 import oracle
+from libgraph import library_graph
 from synth import make_graph
 from synth.mixed import make_mixed
 
@@ -44,7 +45,7 @@ def test_mixed_batch_equals_alone_and_oracle(lib):
         alone = _alone(lib, gr)
         for a, b in zip(got, alone):
             assert (a == b).all(), (gr.bg, gr.Z, gr.rows)
-        g = make_graph(gr.bg, gr.Z, gr.rows)
+        g = library_graph(gr.bg, gr.Z, gr.rows)
         ref = oracle.decode_i8(g, gr.batch.q, n_threads=4)
         for a, b in zip(got, ref[:3]):
             assert (a == b).all(), (gr.bg, gr.Z, gr.rows)
@@ -92,7 +93,7 @@ def test_batch_with_learned_weights(lib):
                                  weights=torch.from_numpy(w).cuda()))
     lib.decode_batch(jobs)
     for gr, jb, w in zip(groups, jobs, ws):
-        g = make_graph(gr.bg, gr.Z, gr.rows)
+        g = library_graph(gr.bg, gr.Z, gr.rows)
         ref = oracle.decode_i8(g, gr.batch.q, wq=w, n_threads=4)
         assert (jb.out_bits.cpu().numpy() == ref[0]).all()
         assert (jb.out_iters.cpu().numpy() == ref[1]).all()

@@ -69,6 +69,59 @@ def test_hand_example_fp16():
     assert oracle.f16_to_f64(llr[0]).tolist() == [12.25, -8.25, 9.25, -22.25]
 
 
+def test_hand_example_fp16_rounding():
+    # A row where every binary16 operation of the update rounds: the
+    # normalisation's offset subtraction and product, the extrinsic
+    # subtraction L - R and the posterior sum x + R' (rounding to nearest,
+    # ties to even). One check on three bits, L = [42, -13, -87],
+    # w = rn16(2.9) = 2.900390625 (0x41CD), offset rn16(0.3) =
+    # 0.300048828125 (0x34CD), two iterations, no early exit.
+    #
+    # Iteration 1 (R = 0, x = L): |x| = [42, 13, 87], m1 = 13 (edge 1),
+    # m2 = 42, sign product + (two negatives).
+    #   m1 - off = 12.699951171875 -> 12.703125 (quantum 2^-7);
+    #   w * 12.703125 = 36.844024658203125 -> a1 = 36.84375 (2^-5)
+    #   m2 - off = 41.699951171875 -> 41.6875 (2^-5);
+    #   w * 41.6875 = 120.9100341796875 -> a2 = 120.9375 (2^-4)
+    #   R' = [+a1, -a2, -a1] (edge k gets the sign of x_k times the product)
+    #   L' = [42 + 36.84375 = 78.84375 -> 78.875 (2^-4),
+    #         -13 - 120.9375 = -133.9375 -> -134.0 (2^-3, a tie: to even),
+    #         -87 - 36.84375 = -123.84375 -> -123.875 (2^-4)]
+    # Iteration 2: x = L' - R' = [78.875 - 36.84375 = 42.03125 (exact),
+    #   -134 + 120.9375 = -13.0625 (exact), -123.875 + 36.84375 = -87.03125
+    #   -> -87.0 (2^-4, a tie: to even)]; m1 = 13.0625, m2 = 42.03125
+    #   m1 - off = 12.762451171875 -> 12.765625; w * 12.765625 =
+    #   37.025299072265625 -> a1 = 37.03125
+    #   m2 - off = 41.731201171875 -> 41.71875; w * 41.71875 =
+    #   121.00067138671875 -> a2 = 121.0
+    #   L' = [42.03125 + 37.03125 = 79.0625 (exact),
+    #         -13.0625 - 121 = -134.0625 -> -134.0 (2^-3, a tie: to even),
+    #         -87.0 - 37.03125 = -124.03125 -> -124.0 (2^-3)]
+    # Keeping any one of the four operations unrounded changes the result
+    # (e.g. an unrounded L - R gives -124.0625 for the last bit).
+    g = one_row(w=3)
+    q = np.array([[42, -13, -87]], np.int8)
+    for iters, want in ((1, [78.875, -134.0, -123.875]), (2, [79.0625, -134.0, -124.0])):
+        _, _, _, llr = oracle.decode_f16(g, q, max_iter=iters, early_exit=False, beta=2.9,
+                                         delta=0.3, want_llr=True)
+        assert oracle.f16_to_f64(llr[0]).tolist() == want
+    # the same steps in numpy's IEEE binary16 arithmetic, one operation at a time
+    h = np.float16
+    w, off = h(2.9), h(0.3)
+    a1, a2 = w * (h(13) - off), w * (h(42) - off)
+    L1 = [h(42) + a1, h(-13) - a2, h(-87) - a1]
+    x = [L1[0] - a1, L1[1] + a2, L1[2] + a1]
+    b1, b2 = w * (abs(x[1]) - off), w * (abs(x[0]) - off)
+    L2 = [x[0] + b1, x[1] - b2, x[2] - b1]
+    assert [float(v) for v in L1] == [78.875, -134.0, -123.875]
+    assert [float(v) for v in L2] == [79.0625, -134.0, -124.0]
+    # per-(iteration, row) weights take the same path as a scalar beta
+    wh = np.full((2, 1), 0x41CD, np.uint16)
+    _, _, _, llr = oracle.decode_f16(g, q, max_iter=2, early_exit=False, wh=wh, delta=0.3,
+                                     want_llr=True)
+    assert oracle.f16_to_f64(llr[0]).tolist() == [79.0625, -134.0, -124.0]
+
+
 # --------------------------------------------------------------------------
 # binary16 rounding against numpy's IEEE conversion
 # --------------------------------------------------------------------------
