@@ -65,6 +65,9 @@ def _load(path: str | None = None):
                                           ctypes.c_uint16, P, I, P, P, P, P, I]
         lib.oracle_decode_f64.argtypes = [I, I, I, I, I, P, P, P, I, P, I, I, ctypes.c_double,
                                           ctypes.c_double, P, I, P, P, P, P, I]
+        lib.oracle_decode_bp_f64.argtypes = [I, I, I, I, I, P, P, P, I, P, I, I, I, I,
+                                             ctypes.c_double, P, P, P, P, I]
+        lib.oracle_decode_bp_f64.restype = ctypes.c_int
         lib.oracle_nwms_grad_f64.argtypes = [I, I, I, I, P, P, P, I, P, P, I, P, P,
                                              ctypes.c_double, P, P]
         lib.oracle_nwms_grad_f64.restype = ctypes.c_int
@@ -164,6 +167,27 @@ def decode_f64(g, llr, max_iter=10, early_exit=True, beta=0.75, delta=0.0, w=Non
                                    _ptr(ok), _ptr(out), n_threads)
     if rc != 0:
         raise ValueError(f"oracle_decode_f64 failed ({rc})")
+    return bits, iters, ok.astype(bool), out
+
+
+def decode_bp(g, llr, rule="spa", schedule="layered", max_iter=10, early_exit=True,
+              beta=0.75, want_llr=False, n_threads=1):
+    """Double-precision belief propagation on real-valued LLRs [n_cw, T] with
+    the sum-product ("spa") or normalised min-sum ("minsum", beta) check rule
+    on the layered or flooding schedule (context for the decoder's choices)."""
+    llr = np.ascontiguousarray(llr, dtype=np.float64)
+    n_cw = llr.shape[0]
+    assert llr.shape == (n_cw, g.T)
+    rules = {"minsum": 0, "spa": 1}
+    schedules = {"layered": 0, "flooding": 1}
+    dims, (rp, col, sh) = _graph_args(g)
+    bits, iters, ok, out = _outputs(g, n_cw, want_llr, np.float64)
+    rc = _load().oracle_decode_bp_f64(*dims, _ptr(rp), _ptr(col), _ptr(sh), n_cw, _ptr(llr),
+                                      max_iter, int(early_exit), rules[rule],
+                                      schedules[schedule], float(beta), _ptr(bits), _ptr(iters),
+                                      _ptr(ok), _ptr(out), n_threads)
+    if rc != 0:
+        raise ValueError(f"oracle_decode_bp_f64 failed ({rc})")
     return bits, iters, ok.astype(bool), out
 
 

@@ -1,10 +1,11 @@
 """Exhaustive-search references for tiny codes -- TEST INFRASTRUCTURE ONLY.
 
 For a code small enough to list every codeword, these give the maximum-
-likelihood codeword and the max-log-MAP bit LLRs by definition (no message
-passing), so they check the min-sum oracle from outside: on a cycle-free
-Tanner graph min-sum with beta = 1 is exact max-log-MAP (paper §III's min-sum
-approximation becomes exact when the graph is a tree).
+likelihood codeword, the max-log-MAP and the exact MAP bit LLRs by
+definition (no message passing), so they check the oracle from outside: on a
+cycle-free Tanner graph min-sum with beta = 1 is exact max-log-MAP (paper
+§III's min-sum approximation becomes exact when the graph is a tree) and
+sum-product belief propagation is exact MAP.
 """
 from __future__ import annotations
 
@@ -76,4 +77,17 @@ def maxlog_map(words: np.ndarray, llr: np.ndarray) -> np.ndarray:
     out = np.empty(words.shape[1])
     for j in range(words.shape[1]):
         out[j] = corr[words[:, j] == 0].max() - corr[words[:, j] == 1].max()
+    return out
+
+
+def exact_map(words: np.ndarray, llr: np.ndarray) -> np.ndarray:
+    """Exact bitwise MAP LLR of each bit, log P(c_j = 0 | y) / P(c_j = 1 | y)
+    = logsumexp_{c: c_j = 0} corr(c) - logsumexp_{c: c_j = 1} corr(c) (what
+    sum-product belief propagation computes exactly on a cycle-free graph)."""
+    corr = correlation(words, llr)
+    out = np.empty(words.shape[1])
+    for j in range(words.shape[1]):
+        a, b = corr[words[:, j] == 0], corr[words[:, j] == 1]
+        out[j] = (a.max() + np.log(np.exp(a - a.max()).sum())) - \
+                 (b.max() + np.log(np.exp(b - b.max()).sum()))
     return out

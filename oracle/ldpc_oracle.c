@@ -29,7 +29,8 @@
  *           emulated by exact double arithmetic followed by one rounding.
  *   f64  -- double precision, no clamp (beta per (iteration, block row)).
  * The f64 mode also provides the exact gradient of the learned weighted
- * min-sum loss (oracle_nwms_grad_f64).
+ * min-sum loss (oracle_nwms_grad_f64), and, for context only, the
+ * sum-product check rule and the flooding schedule (oracle_decode_bp_f64).
  */
 #include <math.h>
 #include <pthread.h>
@@ -544,6 +545,173 @@ int oracle_decode_f64(int M, int N, int Z, int n_punct, int K,
         jb->status = ORACLE_OK;
     }
     run_threads(jobs, sizeof(f64_job_t), n_threads, f64_worker);
+    int status = ORACLE_OK;
+    for (int i = 0; i < n_threads; ++i)
+        if (jobs[i].status != ORACLE_OK) status = jobs[i].status;
+    free(jobs);
+    return status;
+}
+
+/* ------------------------------------------------------------------ */
+/* Check rules and schedules for context (double precision)            */
+/* ------------------------------------------------------------------ */
+/*
+ * The decoder's method is the normalised min-sum approximation of belief
+ * propagation on the layered schedule (§III). For context on what those two
+ * choices cost, this routine also runs
+ *   rule BP_SPA   -- the sum-product check rule of §III: the message to edge
+ *                    k is 2 atanh(prod_{j != k} tanh(x_j / 2)), the product
+ *                    taken directly (|product| kept at most the largest
+ *                    double below 1, so a message is at most about 36.7;
+ *                    the true value is then within 1e-15 of a hard decision);
+ *   rule BP_MINSUM -- the normalised min-sum of the double mode (beta);
+ *   schedule BP_LAYERED  -- block rows in order, each row reading the
+ *                    posteriors the previous rows left (§III layered);
+ *   schedule BP_FLOODING -- every check row of an iteration reads the
+ *                    posteriors of the previous iteration; afterwards each
+ *                    posterior is its channel LLR plus all its incoming
+ *                    check-to-variable messages (§III flooding).
+ * Same stopping rule, outputs and no clamping as the double mode.
+ */
+#define BP_MINSUM 0
+#define BP_SPA 1
+#define BP_LAYERED 0
+#define BP_FLOODING 1
+
+typedef struct {
+    const graph_t *g;
+    int kb_bits;
+    const double *llr;
+    int n_cw, max_iter, early_exit, rule, schedule;
+    double beta;
+    uint8_t *out_bits;
+    int32_t *out_iters;
+    uint8_t *out_ok;
+    double *out_llr;
+    int cw_begin, cw_end, status;
+} bp_job_t;
+
+/* New check-to-variable messages rn[0..w) of one check row from its
+ * variable-to-check messages x[0..w). */
+static void check_rule(int rule, double beta, const double *x, int w, double *rn) {
+    if (rule == BP_SPA) {
+        const double pmax = nextafter(1.0, 0.0);
+        for (int k = 0; k < w; ++k) {
+            double p = 1.0;
+            for (int j = 0; j < w; ++j)
+                if (j != k) p *= tanh(x[j] / 2.0);
+            if (p > pmax) p = pmax;
+            if (p < -pmax) p = -pmax;
+            rn[k] = 2.0 * atanh(p);
+        }
+        return;
+    }
+    double m1 = INFINITY, m2 = INFINITY;
+    int k1 = -1, S = 0;
+    for (int k = 0; k < w; ++k) {
+        const double a = fabs(x[k]);
+        if (a < m1) { m2 = m1; m1 = a; k1 = k; }
+        else if (a < m2) { m2 = a; }
+        S ^= signbit(x[k]) ? 1 : 0;
+    }
+    for (int k = 0; k < w; ++k) {
+        const double mag = beta * ((k == k1) ? m2 : m1);
+        rn[k] = (S ^ (signbit(x[k]) ? 1 : 0)) ? -mag : mag;
+    }
+}
+
+static void decode_one_bp(const bp_job_t *jb, int cw, double *L, double *Lch, double *R,
+                          double *x, double *rn, uint8_t *hd) {
+    const graph_t *g = jb->g;
+    const int Z = g->Z, NZ = g->N * g->Z, E = g->row_ptr[g->M];
+    const int T = (g->N - g->n_punct) * Z;
+    const double *b = jb->llr + (size_t)cw * T;
+    for (int j = 0; j < g->n_punct * Z; ++j) Lch[j] = 0.0;
+    for (int i = 0; i < T; ++i) Lch[g->n_punct * Z + i] = b[i];
+    memcpy(L, Lch, sizeof(double) * (size_t)NZ);
+    for (size_t i = 0; i < (size_t)E * Z; ++i) R[i] = 0.0;
+
+    int iters = jb->max_iter, ok = 0;
+    for (int t = 1; t <= jb->max_iter; ++t) {
+        for (int r = 0; r < g->M; ++r) {
+            const int e0 = g->row_ptr[r], w_r = g->row_ptr[r + 1] - e0;
+            for (int z = 0; z < Z; ++z) {
+                for (int k = 0; k < w_r; ++k)
+                    x[k] = L[var_of(g, e0 + k, z)] - R[(size_t)(e0 + k) * Z + z];
+                check_rule(jb->rule, jb->beta, x, w_r, rn);
+                for (int k = 0; k < w_r; ++k) {
+                    R[(size_t)(e0 + k) * Z + z] = rn[k];
+                    /* layered: the posterior takes the new message at once */
+                    if (jb->schedule == BP_LAYERED) L[var_of(g, e0 + k, z)] = x[k] + rn[k];
+                }
+            }
+        }
+        if (jb->schedule == BP_FLOODING) {
+            /* every row read the previous iteration's posteriors; now each
+             * posterior is its channel LLR plus all its new messages */
+            memcpy(L, Lch, sizeof(double) * (size_t)NZ);
+            for (int r = 0; r < g->M; ++r)
+                for (int e = g->row_ptr[r]; e < g->row_ptr[r + 1]; ++e)
+                    for (int z = 0; z < Z; ++z) L[var_of(g, e, z)] += R[(size_t)e * Z + z];
+        }
+        if (jb->early_exit || t == jb->max_iter) {
+            for (int j = 0; j < NZ; ++j) hd[j] = L[j] < 0.0;
+            const int holds = all_checks_hold(g, hd);
+            if (jb->early_exit && holds) { iters = t; ok = 1; break; }
+            if (t == jb->max_iter) ok = holds;
+        }
+    }
+    for (int j = 0; j < NZ; ++j) hd[j] = L[j] < 0.0;
+    pack_bits(hd, jb->kb_bits, jb->out_bits + (size_t)cw * ((jb->kb_bits + 7) / 8));
+    jb->out_iters[cw] = iters;
+    if (jb->out_ok) jb->out_ok[cw] = (uint8_t)ok;
+    if (jb->out_llr) memcpy(jb->out_llr + (size_t)cw * NZ, L, sizeof(double) * (size_t)NZ);
+}
+
+static void *bp_worker(void *arg) {
+    bp_job_t *jb = (bp_job_t *)arg;
+    const graph_t *g = jb->g;
+    const size_t NZ = (size_t)g->N * g->Z, EZ = (size_t)g->row_ptr[g->M] * g->Z;
+    const size_t W = (size_t)max_row_weight(g);
+    double *L = malloc(sizeof(double) * NZ), *Lch = malloc(sizeof(double) * NZ);
+    double *R = malloc(sizeof(double) * EZ);
+    double *x = malloc(sizeof(double) * W), *rn = malloc(sizeof(double) * W);
+    uint8_t *hd = malloc(NZ);
+    if (!L || !Lch || !R || !x || !rn || !hd) { jb->status = ORACLE_ENOMEM; goto out; }
+    for (int cw = jb->cw_begin; cw < jb->cw_end; ++cw) decode_one_bp(jb, cw, L, Lch, R, x, rn, hd);
+    jb->status = ORACLE_OK;
+out:
+    free(L); free(Lch); free(R); free(x); free(rn); free(hd);
+    return NULL;
+}
+
+int oracle_decode_bp_f64(int M, int N, int Z, int n_punct, int K,
+                         const int32_t *row_ptr, const int16_t *col, const int16_t *shift,
+                         int n_cw, const double *llr, int max_iter, int early_exit, int rule,
+                         int schedule, double beta, uint8_t *out_bits, int32_t *out_iters,
+                         uint8_t *out_ok, double *out_llr, int n_threads) {
+    graph_t g = {M, N, Z, n_punct, row_ptr, col, shift};
+    if (!graph_check(&g) || n_cw < 0 || max_iter < 1 || K < 0 || K > N * Z ||
+        (rule != BP_MINSUM && rule != BP_SPA) ||
+        (schedule != BP_LAYERED && schedule != BP_FLOODING) ||
+        (n_cw > 0 && (!llr || !out_bits || !out_iters)))
+        return ORACLE_EINVAL;
+    if (n_cw == 0) return ORACLE_OK;
+    if (n_threads < 1) n_threads = 1;
+    if (n_threads > n_cw) n_threads = n_cw;
+    bp_job_t *jobs = calloc((size_t)n_threads, sizeof(bp_job_t));
+    if (!jobs) return ORACLE_ENOMEM;
+    for (int i = 0; i < n_threads; ++i) {
+        bp_job_t *jb = &jobs[i];
+        jb->g = &g; jb->kb_bits = K; jb->llr = llr; jb->n_cw = n_cw; jb->max_iter = max_iter;
+        jb->early_exit = early_exit; jb->rule = rule; jb->schedule = schedule; jb->beta = beta;
+        jb->out_bits = out_bits; jb->out_iters = out_iters; jb->out_ok = out_ok;
+        jb->out_llr = out_llr;
+        jb->cw_begin = (int)((long long)n_cw * i / n_threads);
+        jb->cw_end = (int)((long long)n_cw * (i + 1) / n_threads);
+        jb->status = ORACLE_OK;
+    }
+    run_threads(jobs, sizeof(bp_job_t), n_threads, bp_worker);
     int status = ORACLE_OK;
     for (int i = 0; i < n_threads; ++i)
         if (jobs[i].status != ORACLE_OK) status = jobs[i].status;

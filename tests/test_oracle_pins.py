@@ -319,3 +319,84 @@ def test_toy_code_matches_ml_at_high_snr():
     assert agree >= 0.99
     # whenever the decoder reports success its output is a codeword
     assert not ((H.astype(int) @ hd[ok].T.astype(int)) % 2).any()
+
+
+# --------------------------------------------------------------------------
+# Sum-product rule and flooding schedule (context variants): exact MAP on
+# trees, max-log-MAP for min-sum, and the schedules' order properties
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("w", [2, 3, 5, 8])
+@pytest.mark.parametrize("schedule", ["layered", "flooding"])
+def test_spa_single_check_is_exact_map(w, schedule):
+    # one check is a tree: one sum-product update gives every bit's exact
+    # a-posteriori LLR, whichever schedule
+    rng = np.random.default_rng(30 + w)
+    g = one_row(w=w)
+    words = bf.all_codewords(g.dense_H())
+    for _ in range(20):
+        lf = rng.standard_normal((1, w)) * 3
+        _, _, _, post = oracle.decode_bp(g, lf, rule="spa", schedule=schedule, max_iter=1,
+                                         early_exit=False, want_llr=True)
+        assert np.allclose(post[0], bf.exact_map(words, lf[0]), rtol=1e-11, atol=1e-11)
+
+
+@pytest.mark.parametrize("Z", [1, 3])
+@pytest.mark.parametrize("schedule", ["layered", "flooding"])
+def test_bp_tree_is_exact(Z, schedule):
+    # on a forest, belief propagation run long enough is exact: sum-product
+    # gives the MAP LLRs, min-sum with beta = 1 the max-log-MAP LLRs, on
+    # either schedule
+    rng = np.random.default_rng(40 + Z)
+    base = np.where(TREE >= 0, rng.integers(0, Z, TREE.shape), -1)
+    g = make_toy_graph(base, Z=Z, kb=5)
+    words = bf.all_codewords(g.dense_H())
+    for _ in range(10):
+        lf = rng.standard_normal((1, g.N * Z)) * 2
+        _, _, _, spa = oracle.decode_bp(g, lf, rule="spa", schedule=schedule, max_iter=12,
+                                        early_exit=False, want_llr=True)
+        assert np.allclose(spa[0], bf.exact_map(words, lf[0]), rtol=1e-10, atol=1e-10)
+        _, _, _, ms = oracle.decode_bp(g, lf, rule="minsum", schedule=schedule, beta=1.0,
+                                       max_iter=12, early_exit=False, want_llr=True)
+        assert np.allclose(ms[0], bf.maxlog_map(words, lf[0]), rtol=0, atol=1e-9)
+
+
+def test_bp_layered_minsum_equals_double_mode():
+    # the min-sum rule on the layered schedule is the decoder's double mode
+    g = make_graph(2, 16).sub(12)
+    b = make_batch(g, 20, 1.0, data_seed=12)
+    lf = b.q.astype(np.float64)
+    ref = oracle.decode_f64(g, lf, max_iter=6, beta=0.75, want_llr=True)
+    got = oracle.decode_bp(g, lf, rule="minsum", schedule="layered", beta=0.75, max_iter=6,
+                           want_llr=True)
+    for a, r in zip(got, ref):
+        assert np.array_equal(a, r)
+
+
+def _permute_rows(g, perm):
+    rows = [(g.col[g.row_ptr[r]:g.row_ptr[r + 1]], g.shift[g.row_ptr[r]:g.row_ptr[r + 1]])
+            for r in perm]
+    rp = np.concatenate([[0], np.cumsum([len(c) for c, _ in rows])]).astype(np.int32)
+    return type(g)(bg=g.bg, Z=g.Z, M=g.M, N=g.N, kb=g.kb, row_ptr=rp,
+                   col=np.concatenate([c for c, _ in rows]).astype(np.int16),
+                   shift=np.concatenate([s for _, s in rows]).astype(np.int16))
+
+
+@pytest.mark.parametrize("rule", ["spa", "minsum"])
+def test_flooding_ignores_row_order_layered_does_not(rule):
+    # flooding reads only the previous iteration's posteriors, so the order
+    # of the check rows cannot matter (up to the order of the final sums);
+    # the layered schedule depends on it
+    g = make_graph(2, 16).sub(10)
+    perm = np.random.default_rng(3).permutation(g.M)
+    gp = _permute_rows(g, perm)
+    b = make_batch(g, 8, 1.0, data_seed=13)
+    lf = b.q.astype(np.float64) / 4
+    kw = dict(rule=rule, max_iter=5, early_exit=False, want_llr=True)
+    _, _, _, f0 = oracle.decode_bp(g, lf, schedule="flooding", **kw)
+    _, _, _, f1 = oracle.decode_bp(gp, lf, schedule="flooding", **kw)
+    assert np.allclose(f0, f1, rtol=1e-12, atol=1e-9)
+    _, _, _, l0 = oracle.decode_bp(g, lf, schedule="layered", **kw)
+    _, _, _, l1 = oracle.decode_bp(gp, lf, schedule="layered", **kw)
+    assert np.abs(l0 - l1).max() > 1e-3
+    assert np.abs(l0 - f0).max() > 1e-3
