@@ -326,9 +326,10 @@ class BatchJob:
 
 
 def _job_array(jobs):
+    """ctypes array of Job structs from BatchJob objects or Job structs."""
     arr = (Job * len(jobs))()
     for i, j in enumerate(jobs):
-        arr[i] = j.c_struct()
+        arr[i] = j if isinstance(j, Job) else j.c_struct()
     return arr
 
 
@@ -354,7 +355,8 @@ def decode_batch_async(jobs, *, max_iter: int = 10, early_exit: bool = True,
 
 def decode_batch_bytes(jobs) -> int:
     """Device bytes decode_batch_async would hold in flight for these jobs
-    (computed without allocating or launching)."""
+    (computed without allocating or launching). ``jobs``: BatchJob objects
+    or their Job structs (whose buffers the caller keeps alive)."""
     arr = _job_array(jobs)
     nb = ctypes.c_size_t()
     _check(lib().ldpc_decode_batch_bytes(arr, len(jobs), ctypes.byref(nb)),

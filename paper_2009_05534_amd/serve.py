@@ -124,19 +124,38 @@ class Server:
                 # the fallback pass writes here; merged per codeword afterwards
                 b._plain = (torch.empty_like(b._bits), torch.empty_like(b._iters),
                             torch.empty_like(b._ok))
-            if self.ldpc.decode_batch_bytes(self._jobs([b], False)) > self.mem_budget:
+            # the library's job records of both passes, built once per block
+            b._job = {plain: self._make_job(b, plain) for plain in (False, True)
+                      if not plain or b._plain is not None}
+            b._cjob = {k: j.c_struct() for k, j in b._job.items()}
+            if self.ldpc.decode_batch_bytes([b._cjob[False]]) > self.mem_budget:
                 raise ValueError(f"block {b.id} needs more device memory than the budget")
         torch.cuda.synchronize(self.dev)
 
+    def _make_job(self, b, plain: bool):
+        w = None if plain else self._weights(b.bg, b.rows, b.Z)
+        bits, iters, ok = b._plain if plain else (b._bits, b._iters, b._ok)
+        return self.ldpc.BatchJob(b._llr, b.bg, b.Z, b.rows, weights=w, out_bits=bits,
+                                  out_iters=iters, out_ok=ok)
+
     def _jobs(self, batch, plain: bool):
-        ldpc = self.ldpc
-        jobs = []
-        for b in batch:
-            w = None if plain else self._weights(b.bg, b.rows, b.Z)
-            bits, iters, ok = b._plain if plain else (b._bits, b._iters, b._ok)
-            jobs.append(ldpc.BatchJob(b._llr, b.bg, b.Z, b.rows, weights=w, out_bits=bits,
-                                      out_iters=iters, out_ok=ok))
-        return jobs
+        """The job records (ctypes structs) of the blocks' learned or plain pass."""
+        return [b._cjob[plain] for b in batch]
+
+    def _admit(self, queue, plain: bool, room: int):
+        """The longest earliest-deadline prefix of `queue` (at most
+        max_blocks) whose launch footprint fits `room` bytes, and that
+        footprint. The footprint only grows with the prefix, so a binary
+        search over its length needs a handful of library queries."""
+        lo, hi, need_lo = 0, min(len(queue), self.max_blocks), 0
+        while lo < hi:
+            mid = (lo + hi + 1) // 2
+            need = self.ldpc.decode_batch_bytes(self._jobs(queue[:mid], plain))
+            if need <= room:
+                lo, need_lo = mid, need
+            else:
+                hi = mid - 1
+        return lo, need_lo
 
     def _merge_fallback(self, batch):
         """Codewords whose learned pass failed take the plain pass's result;
@@ -194,15 +213,11 @@ class Server:
             for queue, plain in ((fallback, True), (pending, False)):
                 while free_slots and queue:
                     queue.sort(key=lambda b: b.arrival)  # earliest deadline first
-                    batch, mem = [], 0
-                    while queue and len(batch) < self.max_blocks:
-                        need = self.ldpc.decode_batch_bytes(self._jobs(batch + [queue[0]], plain))
-                        if mem_used + need > self.mem_budget:
-                            break
-                        batch.append(queue.pop(0))
-                        mem = need
-                    if not batch:
+                    k, mem = self._admit(queue, plain, self.mem_budget - mem_used)
+                    if k == 0:
                         break
+                    batch = queue[:k]
+                    del queue[:k]
                     slot = free_slots.pop()
                     st = self.streams[slot]
                     held = self.ldpc.decode_batch_async(self._jobs(batch, plain),

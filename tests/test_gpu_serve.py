@@ -72,7 +72,9 @@ def test_fallback_keeps_learned_successes(server_mod):
     serve = server_mod
     from paper_2009_05534_amd import ldpc
     blocks = [b for b in serve.make_trace(400, seed=9) if b.bg == 1 and b.n_cw >= 4][:30]
-    wq = np.full((10, 46), 40, np.uint8)  # weak weights: more failures
+    # weights of 1/2: by the oracle, 8 of these 30 blocks then have codewords
+    # that the learned pass decodes next to codewords it does not
+    wq = np.full((10, 46), 64, np.uint8)
     srv = serve.Server(weights_bg1=wq, n_slots=2, mem_budget=64 << 20)
     trace = serve.rescale(blocks, 1e4)
     srv.run(trace)
