@@ -185,6 +185,32 @@ void ldpc_args_init(ldpc_args *a);
 int ldpc_decode_ex(const ldpc_args *a);
 
 /*
+ * ldpc_decode_noalloc -- ldpc_decode_ex for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same arguments, checks, kernels and results, but the
+ * check-to-variable messages live in a static per-device scratch array of
+ * LDPC_NOALLOC_SCRATCH_BYTES (64 MiB, part of the library's code object,
+ * held on every device the library runs on until the process ends) instead
+ * of a per-call allocation. No device or host memory is allocated or freed.
+ *   - Limit: the message bytes of ldpc_decode_ex (int8:
+ *     2*ceil(n_cw/2)*E_pad*Z + 16 unless the messages are placed in LDS;
+ *     binary16: 2*n_cw*E*Z) must not exceed the scratch, else LDPC_EINVAL
+ *     and ldpc_last_error_message() names both sizes. At BG1 Z = 384 with
+ *     46 rows that is up to 514 int8 or 276 binary16 codewords per call.
+ *   - The graph's device tables must already be resident on the current
+ *     device (any ldpc_decode / ldpc_decode_ex call of (bg, Z) there uploads
+ *     them), else LDPC_ENOGRAPH with a message saying so.
+ *   - Every call on one device shares that device's scratch: calls that
+ *     overlap on one device (different streams, or other threads) race and
+ *     give wrong results. Serialise them, e.g. on one stream. The decoders
+ *     write every message before reading it, so nothing needs clearing
+ *     between calls.
+ * Errors: as ldpc_decode_ex (LDPC_ENOMEM never occurs).
+ */
+#define LDPC_NOALLOC_SCRATCH_BYTES (64u << 20)
+int ldpc_decode_noalloc(const ldpc_args *a);
+
+/*
  * Mixed-shape batches. A job is a set of codewords of one shape (bg, Z,
  * rows) with its own device buffers: llr int8 [n_cw][T], out_bits
  * [n_cw][K/8], out_iters int32 [n_cw], out_ok uint8 [n_cw] or NULL, and

@@ -68,8 +68,10 @@ std::vector<int32_t> padded_row_ptr(const HostGraph &g) {
     return rp;
 }
 
-// Device tables of graph (bg, Z) on the current device; caller holds g_mu.
-int tables_for(const HostGraph &g, DevTables **out) {
+// Device tables of graph (bg, Z) on the current device, uploaded on first
+// use unless `upload` is false (then LDPC_ENOGRAPH when they are not yet
+// resident); caller holds g_mu.
+int tables_for(const HostGraph &g, DevTables **out, bool upload = true) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e);
@@ -79,6 +81,7 @@ int tables_for(const HostGraph &g, DevTables **out) {
         *out = &it->second;
         return LDPC_OK;
     }
+    if (!upload) return LDPC_ENOGRAPH;
     const int Zh = g.Z / 2;
     const int E = g.row_ptr.back();
     std::vector<uint32_t> meta(E + kMetaPad, 0u), meta_row(E + kMetaPad, 0u),
@@ -119,6 +122,144 @@ int sub_sizes(const HostGraph &g, int rows, int *K, int *T, int *Nc, int *E) {
     if (T) *T = (n - 2) * g.Z;
     if (Nc) *Nc = n * g.Z;
     if (E) *E = g.row_ptr[rows];
+    return LDPC_OK;
+}
+
+// Argument checks, graph look-up and launch shape of one decode call, shared
+// by ldpc_decode_ex and ldpc_decode_noalloc (upload = false: the graph's
+// device tables must already be resident; nothing is allocated on the device
+// or the host heap). msg_bytes: the device message buffer the launch needs
+// unless msg_in_lds.
+int prepare_decode(const ldpc_args *a, bool upload, DecodeLaunch &p, bool &msg_in_lds,
+                   size_t &msg_bytes) {
+    if (!a || a->n_cw < 1 || a->max_iter < 1 || a->max_iter > LDPC_MAX_ITER || !a->llr_in ||
+        !a->out_bits || !a->out_iters || (a->precision != LDPC_I8 && a->precision != LDPC_F16) ||
+        a->beta_q < 0 || a->beta_q > 255 || a->offset_q < 0 || a->offset_q > 127 ||
+        (a->wq && a->wq_iters < 1) || (a->wh && a->wh_iters < 1) || a->cw_per_block < 0 ||
+        a->msg_placement < LDPC_MSG_AUTO || a->msg_placement > LDPC_MSG_DEVICE)
+        return LDPC_EINVAL;
+    g_msg[0] = '\0';
+    int lds_cap = 0;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_graphs.find({a->bg, a->Z});
+        if (it == g_graphs.end()) return LDPC_ENOGRAPH;
+        const HostGraph &g = it->second;
+        int E = 0;
+        if (sub_sizes(g, a->rows, nullptr, nullptr, nullptr, &E) != LDPC_OK) return LDPC_EINVAL;
+        DevTables *t = nullptr;
+        const int rc = tables_for(g, &t, upload);
+        if (rc == LDPC_ENOGRAPH)
+            snprintf(g_msg, sizeof(g_msg),
+                     "graph (%d, %d) has no device tables on this device yet: decode it once "
+                     "with ldpc_decode or ldpc_decode_ex first", a->bg, a->Z);
+        if (rc != LDPC_OK) return rc;
+        int wmax = 0, e_pad = 0;
+        for (int r = 0; r < a->rows; ++r) {
+            const int w = g.row_ptr[r + 1] - g.row_ptr[r];
+            if (w > wmax) wmax = w;
+            e_pad += w + (w & 1);
+        }
+        p.row_ptr = t->row_ptr;
+        p.row_pad = t->row_pad;
+        p.E_pad = e_pad;
+        p.meta = a->precision == LDPC_I8 ? t->meta_i8 : t->meta;
+        p.rows = a->rows;
+        p.n_cols = g.kb + a->rows;
+        p.kb = g.kb;
+        p.Z = g.Z;
+        p.E = E;
+        p.wmax = wmax;
+        p.groups = layer_groups(g.row_ptr.data(), g.col.data(), a->rows);
+        lds_cap = max_lds_bytes();
+    }
+    p.llr = a->llr_in;
+    p.out_bits = a->out_bits;
+    p.out_iters = a->out_iters;
+    p.out_ok = a->out_ok;
+    p.out_llr = a->out_llr;
+    p.n_cw = a->n_cw;
+    p.max_iter = a->max_iter;
+    p.early_exit = a->early_exit ? 1 : 0;
+    const int Zh = p.Z / 2;
+    const bool i8 = a->precision == LDPC_I8;
+    int cpw = 0;
+    msg_in_lds = false;
+    if (i8) {
+        // Codewords go in pairs of Z lanes. Message placement: LDS when two
+        // pairs' full state fits a CU, else device memory so that several
+        // pairs share a CU.
+        const int full = lds_bytes_i8_pair(p.n_cols, p.E, p.Z) + 8;
+        if (a->msg_placement == LDPC_MSG_LDS)
+            msg_in_lds = true;
+        else if (a->msg_placement == LDPC_MSG_DEVICE)
+            msg_in_lds = false;
+        else
+            msg_in_lds = 2 * full + 8 <= lds_cap;
+        const int per_pair = msg_in_lds ? full : lds_bytes_i8_pair_post(p.n_cols, p.Z) + 8;
+        int pairs = (a->cw_per_block + 1) / 2;
+        // Default: about 256 lanes per workgroup with the whole state in LDS,
+        // else about 768 (two pairs per workgroup at the largest lift, one
+        // workgroup per CU: measured as fast as three pairs per CU in steady
+        // state, and with a finer tail for batches of a few thousand).
+        if (pairs == 0) pairs = std::max(1, (msg_in_lds ? 256 : 768) / p.Z);
+        pairs = std::min(pairs, (lds_cap - 8) / per_pair);
+        pairs = std::min(pairs, 768 / p.Z);
+        pairs = std::min(pairs, (a->n_cw + 1) / 2);
+        if (pairs < 1) return LDPC_EINVAL;  // a single pair does not fit
+        cpw = 2 * pairs;
+    } else {
+        const int per_cw = lds_bytes_f16(p.n_cols, p.Z) + 4;
+        cpw = a->cw_per_block;
+        // Default: about 128 lanes (Z/2 per codeword) per workgroup.
+        if (cpw == 0) cpw = std::max(1, 128 / Zh);
+        cpw = std::min(cpw, lds_cap / per_cw);
+        cpw = std::min(cpw, 512 / Zh);
+        cpw = std::min(cpw, a->n_cw);
+        if (cpw < 1) return LDPC_EINVAL;  // a single codeword does not fit
+    }
+    p.cpw = cpw;
+    if (i8) {
+        p.wq = a->wq;
+        p.w_iters = a->wq_iters;
+        p.beta = a->beta_q;
+        p.offset = a->offset_q;
+    } else {
+        p.wh = a->wh;
+        p.w_iters = a->wh_iters;
+        p.beta = a->beta_h;
+        p.offset = a->offset_h;
+    }
+    msg_bytes = msg_in_lds ? 0
+                : i8 ? (((size_t)a->n_cw + 1) / 2) * p.E_pad * p.Z * 2 + kMsgTail
+                     : (size_t)a->n_cw * p.E * Zh * 4;
+    return LDPC_OK;
+}
+
+// Static message scratch of ldpc_decode_noalloc: one copy per device,
+// held until the process ends. In host code `scratch` names a host-side
+// stand-in, not device memory: its device address is resolved per device
+// with hipGetSymbolAddress and only that address is handed to kernels.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+__device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+void *g_scratch_dev[64] = {};  // device ordinal -> address of its `scratch`
+
+// Address of the current device's scratch (resolved once per device).
+int scratch_ptr(void **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= 64) return LDPC_EINVAL;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        g_scratch_dev[dev] = ptr;
+    }
+    *out = g_scratch_dev[dev];
     return LDPC_OK;
 }
 
@@ -261,105 +402,16 @@ void ldpc_args_init(ldpc_args *a) {
 }
 
 int ldpc_decode_ex(const ldpc_args *a) {
-    if (!a || a->n_cw < 1 || a->max_iter < 1 || a->max_iter > LDPC_MAX_ITER || !a->llr_in ||
-        !a->out_bits || !a->out_iters || (a->precision != LDPC_I8 && a->precision != LDPC_F16) ||
-        a->beta_q < 0 || a->beta_q > 255 || a->offset_q < 0 || a->offset_q > 127 ||
-        (a->wq && a->wq_iters < 1) || (a->wh && a->wh_iters < 1) || a->cw_per_block < 0 ||
-        a->msg_placement < LDPC_MSG_AUTO || a->msg_placement > LDPC_MSG_DEVICE)
-        return LDPC_EINVAL;
     DecodeLaunch p{};
-    int lds_cap = 0;
-    {
-        std::lock_guard<std::mutex> lk(g_mu);
-        auto it = g_graphs.find({a->bg, a->Z});
-        if (it == g_graphs.end()) return LDPC_ENOGRAPH;
-        const HostGraph &g = it->second;
-        int E = 0;
-        if (sub_sizes(g, a->rows, nullptr, nullptr, nullptr, &E) != LDPC_OK) return LDPC_EINVAL;
-        DevTables *t = nullptr;
-        const int rc = tables_for(g, &t);
-        if (rc != LDPC_OK) return rc;
-        int wmax = 0;
-        for (int r = 0; r < a->rows; ++r) {
-            const int w = g.row_ptr[r + 1] - g.row_ptr[r];
-            if (w > wmax) wmax = w;
-        }
-        p.row_ptr = t->row_ptr;
-        p.row_pad = t->row_pad;
-        p.E_pad = padded_row_ptr(g)[a->rows];
-        p.meta = a->precision == LDPC_I8 ? t->meta_i8 : t->meta;
-        p.rows = a->rows;
-        p.n_cols = g.kb + a->rows;
-        p.kb = g.kb;
-        p.Z = g.Z;
-        p.E = E;
-        p.wmax = wmax;
-        p.groups = layer_groups(g.row_ptr.data(), g.col.data(), a->rows);
-        lds_cap = max_lds_bytes();
-    }
-    p.llr = a->llr_in;
-    p.out_bits = a->out_bits;
-    p.out_iters = a->out_iters;
-    p.out_ok = a->out_ok;
-    p.out_llr = a->out_llr;
-    p.n_cw = a->n_cw;
-    p.max_iter = a->max_iter;
-    p.early_exit = a->early_exit ? 1 : 0;
-    const int Zh = p.Z / 2;
-    const bool i8 = a->precision == LDPC_I8;
-    int cpw = 0;
     bool msg_in_lds = false;
-    if (i8) {
-        // Codewords go in pairs of Z lanes. Message placement: LDS when two
-        // pairs' full state fits a CU, else device memory so that several
-        // pairs share a CU.
-        const int full = lds_bytes_i8_pair(p.n_cols, p.E, p.Z) + 8;
-        if (a->msg_placement == LDPC_MSG_LDS)
-            msg_in_lds = true;
-        else if (a->msg_placement == LDPC_MSG_DEVICE)
-            msg_in_lds = false;
-        else
-            msg_in_lds = 2 * full + 8 <= lds_cap;
-        const int per_pair = msg_in_lds ? full : lds_bytes_i8_pair_post(p.n_cols, p.Z) + 8;
-        int pairs = (a->cw_per_block + 1) / 2;
-        // Default: about 256 lanes per workgroup with the whole state in LDS,
-        // else about 768 (two pairs per workgroup at the largest lift, one
-        // workgroup per CU: measured as fast as three pairs per CU in steady
-        // state, and with a finer tail for batches of a few thousand).
-        if (pairs == 0) pairs = std::max(1, (msg_in_lds ? 256 : 768) / p.Z);
-        pairs = std::min(pairs, (lds_cap - 8) / per_pair);
-        pairs = std::min(pairs, 768 / p.Z);
-        pairs = std::min(pairs, (a->n_cw + 1) / 2);
-        if (pairs < 1) return LDPC_EINVAL;  // a single pair does not fit
-        cpw = 2 * pairs;
-    } else {
-        const int per_cw = lds_bytes_f16(p.n_cols, p.Z) + 4;
-        cpw = a->cw_per_block;
-        // Default: about 128 lanes (Z/2 per codeword) per workgroup.
-        if (cpw == 0) cpw = std::max(1, 128 / Zh);
-        cpw = std::min(cpw, lds_cap / per_cw);
-        cpw = std::min(cpw, 512 / Zh);
-        cpw = std::min(cpw, a->n_cw);
-        if (cpw < 1) return LDPC_EINVAL;  // a single codeword does not fit
-    }
-    p.cpw = cpw;
+    size_t msg_bytes = 0;
+    int rc = prepare_decode(a, true, p, msg_in_lds, msg_bytes);
+    if (rc != LDPC_OK) return rc;
     hipStream_t stream = static_cast<hipStream_t>(a->stream);
-    if (i8) {
-        p.wq = a->wq;
-        p.w_iters = a->wq_iters;
-        p.beta = a->beta_q;
-        p.offset = a->offset_q;
-    } else {
-        p.wh = a->wh;
-        p.w_iters = a->wh_iters;
-        p.beta = a->beta_h;
-        p.offset = a->offset_h;
-    }
+    const bool i8 = a->precision == LDPC_I8;
     void *msg = nullptr;
     hipError_t e;
     if (!msg_in_lds) {
-        const size_t msg_bytes = i8 ? (((size_t)a->n_cw + 1) / 2) * p.E_pad * p.Z * 2 + kMsgTail
-                                    : (size_t)a->n_cw * p.E * Zh * 4;
         p.msg_bytes = msg_bytes;
         e = hipMallocAsync(&msg, msg_bytes, stream);
         if (e != hipSuccess) return hip_fail(e, "hipMallocAsync(messages)");
@@ -369,6 +421,32 @@ int ldpc_decode_ex(const ldpc_args *a) {
     const hipError_t ef = msg ? hipFreeAsync(msg, stream) : hipSuccess;
     if (e != hipSuccess) return e == hipErrorOutOfMemory ? LDPC_ENOMEM : LDPC_EHIP;
     if (ef != hipSuccess) return hip_fail(ef, "hipFreeAsync(messages)");
+    return LDPC_OK;
+}
+
+int ldpc_decode_noalloc(const ldpc_args *a) {
+    DecodeLaunch p{};
+    bool msg_in_lds = false;
+    size_t msg_bytes = 0;
+    int rc = prepare_decode(a, false, p, msg_in_lds, msg_bytes);
+    if (rc != LDPC_OK) return rc;
+    void *msg = nullptr;
+    if (!msg_in_lds) {
+        if (msg_bytes > kScratchBytes) {
+            snprintf(g_msg, sizeof(g_msg),
+                     "ldpc_decode_noalloc: messages need %zu bytes, the static scratch holds %zu",
+                     msg_bytes, kScratchBytes);
+            return LDPC_EINVAL;
+        }
+        rc = scratch_ptr(&msg);
+        if (rc != LDPC_OK) return rc;
+        p.msg_bytes = msg_bytes;
+    }
+    p.msg = static_cast<uint32_t *>(msg);
+    hipStream_t stream = static_cast<hipStream_t>(a->stream);
+    const hipError_t e = a->precision == LDPC_I8 ? launch_decode_i8(p, stream)
+                                                 : launch_decode_f16(p, stream);
+    if (e != hipSuccess) return LDPC_EHIP;
     return LDPC_OK;
 }
 

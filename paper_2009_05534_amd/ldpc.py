@@ -55,6 +55,7 @@ PLAN_GRAPH = 1
 PLAN_AUTOTUNE = 2
 
 EXPORTS = ("ldpc_set_graph", "ldpc_query", "ldpc_get_graph", "ldpc_graph_digest", "ldpc_decode", "ldpc_args_init", "ldpc_decode_ex",
+           "ldpc_decode_noalloc",
            "ldpc_decode_batch", "ldpc_decode_batch_async", "ldpc_decode_batch_bytes", "ldpc_plan_create", "ldpc_plan_launch", "ldpc_plan_info",
            "ldpc_plan_destroy", "ldpc_nwms_loss_grad", "ldpc_strerror", "ldpc_last_hip_error",
            "ldpc_last_error_message", "ldpc_shutdown")
@@ -82,6 +83,7 @@ def lib():
         L.ldpc_args_init.argtypes = [ctypes.POINTER(Args)]
         L.ldpc_args_init.restype = None
         L.ldpc_decode_ex.argtypes = [ctypes.POINTER(Args)]
+        L.ldpc_decode_noalloc.argtypes = [ctypes.POINTER(Args)]
         L.ldpc_decode_batch.argtypes = [ctypes.POINTER(Job), I, I, I, P]
         L.ldpc_decode_batch_async.argtypes = [ctypes.POINTER(Job), I, I, I, P,
                                               ctypes.POINTER(ctypes.c_size_t)]
@@ -107,7 +109,7 @@ def lib():
 
 def _check(rc: int, what: str):
     if rc != 0:
-        detail = lib().ldpc_last_error_message().decode() if rc == -3 or rc == -2 else ""
+        detail = lib().ldpc_last_error_message().decode()
         raise LdpcError(rc, what + (f" [{detail}]" if detail else ""))
 
 
@@ -175,8 +177,12 @@ def _stream_ptr(stream):
 def decode_into(llr, bg: int, Z: int, rows: int, out_bits, out_iters, *, max_iter: int = 10,
                 precision: str = "i8", early_exit: bool = True, beta: float | None = None,
                 offset: float = 0, weights=None, out_ok=None, out_llr=None,
-                cw_per_block: int = 0, msg_placement: str = "auto", stream=None) -> None:
+                cw_per_block: int = 0, msg_placement: str = "auto", stream=None,
+                noalloc: bool = False) -> None:
     """Decode int8 LLRs [n_cw, T] (device tensor) into preallocated outputs.
+
+    ``noalloc``: call ldpc_decode_noalloc (messages in the library's static
+    per-device scratch; nothing is allocated) instead of ldpc_decode_ex.
 
     ``weights``: per-(iteration, row) normalisation, a device tensor uint8
     [iters, rows] (Q1.7, i8) or float16 [iters, rows] (f16).
@@ -226,14 +232,19 @@ def decode_into(llr, bg: int, Z: int, rows: int, out_bits, out_iters, *, max_ite
     a.cw_per_block = cw_per_block
     a.msg_placement = MSG_PLACEMENT[msg_placement]
     a.stream = _stream_ptr(stream)
-    _check(lib().ldpc_decode_ex(ctypes.byref(a)), "ldpc_decode_ex")
+    if noalloc:
+        _check(lib().ldpc_decode_noalloc(ctypes.byref(a)), "ldpc_decode_noalloc")
+    else:
+        _check(lib().ldpc_decode_ex(ctypes.byref(a)), "ldpc_decode_ex")
 
 
 def decode(llr, bg: int, Z: int, rows: int, *, max_iter: int = 10, precision: str = "i8",
            early_exit: bool = True, beta: float | None = None, offset: float = 0, weights=None,
            want_ok: bool = True, want_llr: bool = False, cw_per_block: int = 0,
-           msg_placement: str = "auto", stream=None):
-    """Allocate outputs with torch on llr's device and decode.
+           msg_placement: str = "auto", stream=None, noalloc: bool = False):
+    """Allocate outputs with torch on llr's device and decode (through
+    ldpc_decode_noalloc when ``noalloc``; the outputs are still allocated
+    here, by torch).
 
     Returns (bits uint8 [n, K/8], iters int32 [n], ok bool [n] or None,
     llr int8/float16 [n, Nc] or None)."""
@@ -253,7 +264,7 @@ def decode(llr, bg: int, Z: int, rows: int, *, max_iter: int = 10, precision: st
     decode_into(llr, bg, Z, rows, bits, iters, max_iter=max_iter, precision=precision,
                 early_exit=early_exit, beta=beta, offset=offset, weights=weights, out_ok=ok,
                 out_llr=out, cw_per_block=cw_per_block, msg_placement=msg_placement,
-                stream=stream)
+                stream=stream, noalloc=noalloc)
     return bits, iters, (ok.bool() if ok is not None else None), out
 
 
