@@ -123,7 +123,7 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    from synth import make_graph
+    from synth import make_batch, make_graph
     g = make_graph(BG, Z)
     t0 = time.time()
     batches = load_or_make_batches(g, args.n_cw, args.data_cache)
@@ -264,23 +264,40 @@ def main():
         w16, l16, _ = timed("f16", True, 2, 1)
         result["f16"] = {"gbps": round(2 * len(batches) * n * K / w16 / 1e9, 3),
                          "avg_launch_ms": round(float(np.mean(l16)), 4)}
-        # single-codeword latency per iteration (fixed 10 iterations)
+        # single-codeword latency per iteration (fixed 10 iterations), with
+        # one lane per check row and with the low-latency mapping (alpha
+        # lanes per check row), at Z = 384 and Z = 128
+        def one_cw_us_per_iter(bg, Zx, rows, q1, alpha):
+            b1 = torch.empty((1, bg_k(bg) * Zx // 8), dtype=torch.uint8, device=dev)
+            i1 = torch.empty(1, dtype=torch.int32, device=dev)
+            for _ in range(3):
+                ldpc.decode_into(q1, bg, Zx, rows, b1, i1, max_iter=10, early_exit=False,
+                                 lanes_per_row=alpha)
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(50):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                ldpc.decode_into(q1, bg, Zx, rows, b1, i1, max_iter=10, early_exit=False,
+                                 lanes_per_row=alpha)
+                e1.record(stream)
+                e1.synchronize()
+                ts.append(e0.elapsed_time(e1))
+            return round(float(np.percentile(ts, 50)) * 1e3 / 10, 2)
+
+        def bg_k(bg):
+            return 22 if bg == 1 else 10
+
         one = llr[4][:1].contiguous()
-        b1 = torch.empty((1, K // 8), dtype=torch.uint8, device=dev)
-        i1 = torch.empty(1, dtype=torch.int32, device=dev)
-        for _ in range(3):
-            ldpc.decode_into(one, BG, Z, ROWS, b1, i1, max_iter=10, early_exit=False)
-        torch.cuda.synchronize()
-        ts = []
-        for _ in range(50):
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            ldpc.decode_into(one, BG, Z, ROWS, b1, i1, max_iter=10, early_exit=False)
-            e1.record(stream)
-            e1.synchronize()
-            ts.append(e0.elapsed_time(e1))
-        result["latency_ms"]["single_codeword_us_per_iter_p50"] = round(
-            float(np.percentile(ts, 50)) * 1e3 / 10, 2)
+        lat1 = {str(al): one_cw_us_per_iter(BG, Z, ROWS, one, al) for al in (1, 2)}
+        g128 = make_graph(BG, 128)
+        ldpc.register(g128)
+        q128 = torch.from_numpy(make_batch(g128, 1, EBN0_POINTS[4], data_seed=9).q).to(dev)
+        lat128 = {str(al): one_cw_us_per_iter(BG, 128, ROWS, q128, al) for al in (1, 2, 4)}
+        result["latency_ms"]["single_codeword_us_per_iter_p50"] = min(lat1.values())
+        result["latency_ms"]["single_codeword_us_per_iter"] = {
+            "note": "one codeword, 10 iterations, p50 over 50 calls, by lanes per check row",
+            f"Z{Z}": lat1, "Z128": lat128}
 
     if not args.no_extras:
         # Mixed-shape batch: 2048 codewords, (bg, Z, rows) drawn per codeword,

@@ -165,6 +165,19 @@ typedef struct ldpc_args {
                                by the library per call, stream-ordered; more
                                codewords then share a CU). binary16 always
                                uses device memory. */
+    int lanes_per_row;      /* int8: lanes cooperating on one check row
+                               (the paper's alpha): 0 or 1 = one lane per row
+                               (the throughput mapping); 2 or 4 = the
+                               low-latency mapping (§IV): each block row is
+                               cut into alpha chunks of consecutive blocks,
+                               one per lane, and the chunks' minima, second
+                               minima and sign parities are merged through
+                               LDS. Needs device-placed messages, row weights
+                               up to min(20, 10*alpha), alpha*P*Z <= 1024 and
+                               P*Z a multiple of 64 for P = cw_per_block/2
+                               pairs per workgroup (default: the fewest pairs
+                               that give whole waves); else LDPC_EINVAL.
+                               Results are identical for every alpha. */
     void *stream;
 } ldpc_args;
 

@@ -954,10 +954,355 @@ __global__ __launch_bounds__(kBatchLanes) __attribute__((amdgpu_waves_per_eu(5))
 
 __global__ void reset_counter_kernel(unsigned *counter) { *counter = 0u; }
 
+// ---------------------------------------------------------------------
+// Low-latency mapping: ALPHA cooperating lanes per check row (§IV).
+// ---------------------------------------------------------------------
+// Block row r of weight w is cut into ALPHA chunks of c = ceil(w / ALPHA)
+// consecutive blocks (the last ones shorter, possibly empty). Chunk a of
+// every check row of the workgroup's pairs is handled by the a-th group of
+// L = slots * Z lanes (whole waves, so the chunk's block metadata stays
+// wave-uniform and lives in scalar registers). Each lane reduces its chunk
+// to (min, second min, sign parity), the ALPHA partials of a check row meet
+// in LDS, every lane merges all of them with the same min / second-min rule
+// (associative, so all lanes of a row agree) and writes back its chunk. One
+// exchange barrier per row buys a dependent chain of c instead of w edges
+// per lane. Messages stream through device memory: row r's region holds the
+// ALPHA chunk regions one after the other, chunk a as [Z][(wc_a + 1) / 2]
+// dwords of two pair words (wc_a the chunk's width).
+
+// Message dwords per check row of a row of weight w cut into ALPHA chunks.
+template <int ALPHA>
+__host__ __device__ inline int ll_row_dwords(int w) {
+    const int c = (w + ALPHA - 1) / ALPHA;
+    const int nfull = w / c, rem = w - nfull * c;
+    return nfull * ((c + 1) / 2) + (rem + 1) / 2;
+}
+
+// Chunk a of a row of weight w: first block k0, width wc (0 if empty),
+// dword offset of the chunk's region per check row (times Z * 4 bytes).
+template <int ALPHA>
+__device__ inline void ll_chunk(int w, int a, int &k0, int &wc, int &dw_off) {
+    const int c = (w + ALPHA - 1) / ALPHA;
+    k0 = a * c;
+    const int left = w - k0;
+    wc = left < 0 ? 0 : (left < c ? left : c);
+    dw_off = a * ((c + 1) / 2);
+}
+
+// One row of the low-latency mapping for a lane whose chunk has exactly W
+// blocks (W = 0: an empty chunk, which only takes part in the exchange).
+// xb: this row's exchange buffer [ALPHA][3][L] dwords (min, second min,
+// sign word of each chunk); a, l: the lane's chunk and lane within the
+// chunk group.
+template <int W, bool FIRST, int ALPHA>
+__device__ __forceinline__ void ll_row_w(uint8_t *__restrict__ smem, uint32_t lb,
+                                         const MsgRow<false> &R, cmeta_t meta, int e0,
+                                         uint32_t u, int Z, u16x2 wgt, u16x2 off16,
+                                         const uint32_t *pre, bool busy, uint32_t *xb, int a,
+                                         int L, int l) {
+    constexpr int NW = W > 0 ? W : 1;
+    constexpr int ND = (NW + 1) / 2;
+    uint32_t md[NW], mo[NW], rd[ND], xv[NW], axv[NW], la[NW];
+    u16x2 m1 = {0x7FFF, 0x7FFF}, m2 = {0x7FFF, 0x7FFF};
+    uint32_t S = 0;
+    if constexpr (W > 0) {
+        if (busy) {
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                md[k] = meta[e0 + k];
+                mo[k] = md[k] & 0xFFFFu;
+            }
+            if (FIRST) {
+#pragma unroll
+                for (int j = 0; j < ND; ++j) rd[j] = 0;
+            } else {
+#pragma unroll
+                for (int j = 0; j < ND && j < kPreDwords; ++j) rd[j] = pre[j];
+                if (ND > kPreDwords) R.template load<W, kPreDwords>(rd, u, Z);
+            }
+            row_phase1<0, W, true>(smem, lb, rd, md, mo, u, Z, W, xv, axv, la, m1, m2, S);
+        }
+    }
+    // exchange of the chunk partials
+    xb[(a * 3 + 0) * L + l] = bits_of(m1);
+    xb[(a * 3 + 1) * L + l] = bits_of(m2);
+    xb[(a * 3 + 2) * L + l] = S;
+    __syncthreads();
+    if constexpr (W > 0) {
+        if (!busy) return;
+        u16x2 M1 = {0x7FFF, 0x7FFF}, M2 = {0x7FFF, 0x7FFF};
+        uint32_t SS = 0;
+#pragma unroll
+        for (int b = 0; b < ALPHA; ++b) {
+            const u16x2 p1 = as_u(xb[(b * 3 + 0) * L + l]);
+            const u16x2 p2 = as_u(xb[(b * 3 + 1) * L + l]);
+            M2 = __builtin_elementwise_min(__builtin_elementwise_max(M1, p1),
+                                           __builtin_elementwise_min(M2, p2));
+            M1 = __builtin_elementwise_min(M1, p1);
+            SS ^= xb[(b * 3 + 2) * L + l];
+        }
+        const u16x2 a1 = normalise(M1, off16, wgt);
+        const u16x2 a2 = normalise(M2, off16, wgt);
+        const s16x2 Sm = as_s(SS) >> (s16x2){15, 15};
+        const s16x2 b1 = (as_s(bits_of(a1)) ^ Sm) - Sm;
+        const s16x2 b2 = (as_s(bits_of(a2)) ^ Sm) - Sm;
+        const u16x2 d21 = as_u(bits_of(b2 - b1));
+        const u16x2 m1p = M1 + (u16x2){1, 1};
+        s16x2 Rv[W], Lv[W];
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            // t = 1 where |x| equals the row's minimum (argmin, or a tie,
+            // where both magnitudes are equal anyway)
+            const u16x2 t = __builtin_elementwise_sub_sat(m1p, as_u(axv[k]));
+            Rv[k] = as_s(bits_of(t * d21 + as_u(bits_of(b1))));
+        }
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            const s16x2 sx = as_s(xv[k]) >> (s16x2){15, 15};
+            Rv[k] = (Rv[k] ^ sx) - sx;
+        }
+#pragma unroll
+        for (int k = 0; k < W; ++k)
+            Lv[k] = __builtin_elementwise_max(__builtin_elementwise_add_sat(as_s(xv[k]), Rv[k]),
+                                              (s16x2){-127 * 256, -127 * 256});
+#pragma unroll
+        for (int k = 0; k < W; ++k) lds_st16(smem, la[k], perm(bits_of(Lv[k]), kPack));
+        uint32_t sd[ND];
+#pragma unroll
+        for (int j = 0; j < ND; ++j)
+            sd[j] = 2 * j + 1 < W ? __builtin_amdgcn_perm(bits_of(Rv[2 * j + 1]), bits_of(Rv[2 * j]),
+                                                          kPack2)
+                                  : perm(bits_of(Rv[2 * j]), kPack);
+#pragma unroll
+        for (int c = 0; c < ND; c += 4) R.template store<W>(sd, u, Z, c, ND - c < 4 ? ND - c : 4);
+    }
+}
+
+template <int W, bool FIRST, int ALPHA>
+__device__ __forceinline__ void ll_row(int wc, uint8_t *smem, uint32_t lb, const MsgRow<false> &R,
+                                       cmeta_t meta, int e0, uint32_t u, int Z, u16x2 wgt,
+                                       u16x2 off16, const uint32_t *pre, bool busy, uint32_t *xb,
+                                       int a, int L, int l) {
+    if constexpr (W <= kLLChunkMax) {
+        if (wc == W) {
+            ll_row_w<W, FIRST, ALPHA>(smem, lb, R, meta, e0, u, Z, wgt, off16, pre, busy, xb, a,
+                                      L, l);
+            return;
+        }
+        ll_row<W + 1, FIRST, ALPHA>(wc, smem, lb, R, meta, e0, u, Z, wgt, off16, pre, busy, xb,
+                                    a, L, l);
+    }
+}
+
+// One iteration of the low-latency mapping: rows in order, the exchange
+// barrier inside every row, the layer-group barrier after rows that share
+// a column with the next. Exchange buffers alternate between rows.
+template <bool FIRST, int ALPHA>
+__device__ __forceinline__ void ll_layer_pass(const BlockWork &bw, uint8_t *smem, uint32_t lb,
+                                              uint32_t ro, __amdgpu_buffer_rsrc_t rsrc,
+                                              crow_t row_ptr, cmeta_t meta, const uint8_t *wrow,
+                                              uint32_t u, bool busy, u16x2 off16, uint32_t *pre,
+                                              bool keep, uint32_t *xbuf, int a, int L, int l) {
+    const int Z = bw.Z;
+    const uint64_t bar = (bw.groups >> 1) | (1ull << (bw.rows - 1));
+    int e0 = row_ptr[0], e1 = row_ptr[1];
+    int roff = 0;  // dword offset (per check row) of the row's message region
+    for (int r = 0; r < bw.rows; ++r) {
+        const bool last = r + 1 == bw.rows;
+        const int e2 = last ? row_ptr[1] : row_ptr[r + 2];
+        const int en = last ? row_ptr[0] : e1;
+        const int w = e1 - e0;
+        int k0, wc, doff;
+        ll_chunk<ALPHA>(w, a, k0, wc, doff);
+        const int wt = wrow ? row_weight(wrow, r) : bw.beta;
+        const u16x2 wgt = {(unsigned short)wt, (unsigned short)wt};
+        MsgRow<false> R{rsrc, nullptr, ro, 4u * (uint32_t)((roff + doff) * Z), keep};
+        ll_row<0, FIRST, ALPHA>(wc, smem, lb, R, meta, e0 + k0, u, Z, wgt, off16, pre, busy,
+                                xbuf + (r & 1) * (ALPHA * 3 * L), a, L, l);
+        const int rnext = last ? 0 : roff + ll_row_dwords<ALPHA>(w);
+        // prefetch of the next row's (first) message dwords of this chunk
+        if (busy && (last ? keep : !FIRST)) {
+            int k0n, wcn, doffn;
+            ll_chunk<ALPHA>(e2 - en, a, k0n, wcn, doffn);
+            if (wcn > 0) {
+                const MsgRow<false> Rn{rsrc, nullptr, ro, 4u * (uint32_t)((rnext + doffn) * Z),
+                                       true};
+                Rn.load4(pre, u, (wcn + 1) / 2);
+            }
+        }
+        if ((bar >> r) & 1) __syncthreads();
+        e0 = en;
+        e1 = e2;
+        roff = rnext;
+    }
+}
+
+// Decodes bw.n codewords as bw.slots pairs with ALPHA lanes per check row:
+// lane tid belongs to chunk group a = tid / L (L = slots * Z) and serves
+// check row u of pair p within it. Initialisation, the syndrome check and
+// the outputs are done by chunk group 0 alone (whole rows, as in the
+// one-lane-per-row mapping). Every thread must call it.
+template <int WMAX, int ALPHA>
+__device__ __forceinline__ void decode_block_ll(const BlockWork &bw, uint8_t *smem,
+                                                crow_t row_ptr, cmeta_t meta) {
+    static_assert(WMAX <= kMetaPad, "row metadata window exceeds the table padding");
+    const int Z = bw.Z, L = bw.slots * Z;
+    const int N = bw.n_cols, T = (N - 2) * Z;
+    const int pair_bytes = lds_bytes_i8_pair_post(N, Z);
+    const int tid = (int)threadIdx.x;
+    const int a = __builtin_amdgcn_readfirstlane(tid / L);  // whole waves (L % 64 == 0)
+    const int l = tid - a * L;
+    const int p = l / Z;
+    const uint32_t u = l - p * Z;
+    const bool validA = 2 * p < bw.n, validB = 2 * p + 1 < bw.n;
+    const int ps = validA ? p : 0;
+    uint8_t *Lp = smem + ps * pair_bytes;
+    uint16_t *Lw = reinterpret_cast<uint16_t *>(Lp);
+    const uint32_t lb = (uint32_t)(ps * pair_bytes) + 2u * u;
+    const uint32_t ro = 2u * (uint32_t)(ps * bw.E_pad * Z);
+    int *flags = reinterpret_cast<int *>(smem + bw.slots * pair_bytes);
+    uint32_t *xbuf = reinterpret_cast<uint32_t *>(smem + bw.slots * pair_bytes +
+                                                  lds_flags_bytes_i8(bw.slots));
+    const __amdgpu_buffer_rsrc_t rsrc =
+        __builtin_amdgcn_make_buffer_rsrc(bw.msg, 0, bw.msg_records, 0x00020000);
+
+    if (a == 0 && validA) {
+        Lw[u] = 0;
+        Lw[Z + u] = 0;
+        const int8_t *qa = bw.llr + (size_t)(2 * p) * T;
+        const int8_t *qb = bw.llr + (size_t)(2 * p + 1) * T;
+#pragma unroll 1
+        for (int c = 2; c < N; ++c) {
+            int va = qa[(c - 2) * Z + u];
+            int vb = validB ? qb[(c - 2) * Z + u] : 0;
+            va = va < -127 ? -127 : va;
+            vb = vb < -127 ? -127 : vb;
+            Lw[c * Z + u] = (uint16_t)((va & 0xFF) | ((vb & 0xFF) << 8));
+        }
+    }
+    __syncthreads();
+
+    const u16x2 off16 = {(unsigned short)(bw.offset << 8), (unsigned short)(bw.offset << 8)};
+    bool doneA = !validA, doneB = !validB;
+    uint32_t pre[kPreDwords] = {0u, 0u, 0u, 0u};
+    for (int t = 1; t <= bw.max_iter; ++t) {
+        const uint8_t *wrow = nullptr;
+        if (bw.wq) wrow = bw.wq + (size_t)((t < bw.w_iters ? t : bw.w_iters) - 1) * bw.w_stride;
+        const bool busy = !(doneA && doneB);
+        if (t == 1)
+            ll_layer_pass<true, ALPHA>(bw, smem, lb, ro, rsrc, row_ptr, meta, wrow, u, busy, off16,
+                                       pre, t < bw.max_iter, xbuf, a, L, l);
+        else
+            ll_layer_pass<false, ALPHA>(bw, smem, lb, ro, rsrc, row_ptr, meta, wrow, u, busy,
+                                        off16, pre, t < bw.max_iter, xbuf, a, L, l);
+        if (bw.early_exit || t == bw.max_iter) {
+            if (tid <= 2 * bw.slots) flags[tid] = tid == 2 * bw.slots;
+            __syncthreads();
+            if (a == 0 && busy)
+                syndrome_mark<WMAX>(smem, lb, row_ptr, meta, bw.rows, u, Z, flags + 2 * p, !doneA,
+                                    !doneB);
+            __syncthreads();
+            const bool holdsA = flags[2 * ps] == 0, holdsB = flags[2 * ps + 1] == 0;
+            bool finA = false, finB = false;
+            if (t == bw.max_iter) {
+                finA = !doneA;
+                finB = !doneB;
+            } else {
+                finA = !doneA && holdsA;
+                finB = !doneB && holdsB;
+            }
+            if (a == 0 && (finA || finB))
+                write_outputs(bw, Lp, p, u, (finA ? 1 : 0) | (finB ? 2 : 0), t, holdsA, holdsB);
+            doneA = doneA || finA;
+            doneB = doneB || finB;
+            if (!(doneA && doneB)) flags[2 * bw.slots] = 0;
+            __syncthreads();
+            if (flags[2 * bw.slots]) break;
+        }
+    }
+}
+
+template <int WMAX, int ALPHA>
+__global__ __launch_bounds__(1024) void decode_i8_ll_kernel(DecodeLaunch p,
+                                                            const int32_t *__restrict__ row_ptr,
+                                                            const uint32_t *__restrict__ meta) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    const int T = (p.n_cols - 2) * p.Z, first = blockIdx.x * p.cpw;
+    BlockWork bw;
+    bw.n = p.n_cw - first < p.cpw ? p.n_cw - first : p.cpw;
+    bw.slots = p.cpw / 2;
+    bw.llr = p.llr + (size_t)first * T;
+    bw.out_bits = p.out_bits + (size_t)first * (p.kb * p.Z / 8);
+    bw.out_iters = p.out_iters + first;
+    bw.out_ok = p.out_ok ? p.out_ok + first : nullptr;
+    bw.out_llr = p.out_llr ? static_cast<int8_t *>(p.out_llr) + (size_t)first * p.n_cols * p.Z
+                           : nullptr;
+    bw.msg = reinterpret_cast<uint16_t *>(p.msg) + (size_t)(first / 2) * p.E_pad * p.Z;
+    {
+        const size_t base = (size_t)(first / 2) * p.E_pad * p.Z * 2;
+        const size_t full = (size_t)(p.cpw / 2) * p.E_pad * p.Z * 2;
+        const size_t left = p.msg_bytes - base;
+        bw.msg_records = (uint32_t)(left < full ? left : full);
+    }
+    bw.row_pad = p.row_pad;
+    bw.E_pad = p.E_pad;
+    bw.groups = p.groups;
+    bw.wq = p.wq;
+    bw.w_iters = p.w_iters;
+    bw.w_stride = p.rows;
+    bw.rows = p.rows;
+    bw.n_cols = p.n_cols;
+    bw.kb = p.kb;
+    bw.Z = p.Z;
+    bw.E = p.E;
+    bw.max_iter = p.max_iter;
+    bw.early_exit = p.early_exit;
+    bw.beta = p.beta;
+    bw.offset = p.offset;
+    decode_block_ll<WMAX, ALPHA>(bw, smem, (crow_t)row_ptr, (cmeta_t)meta);
+}
+
+template <int WMAX, int ALPHA>
+hipError_t launch_ll(const DecodeLaunch &p, hipStream_t stream) {
+    const int pairs = p.cpw / 2, L = pairs * p.Z;
+    const int lds = ll_lds_bytes(p.n_cols, p.Z, pairs, ALPHA);
+    static std::once_flag attr_once;
+    std::call_once(attr_once, [] {
+        const hipError_t e = hipFuncSetAttribute(
+            reinterpret_cast<const void *>(&decode_i8_ll_kernel<WMAX, ALPHA>),
+            hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes());
+        if (e != hipSuccess) note_hip_error("hipFuncSetAttribute(decode_i8_ll_kernel)", e);
+    });
+    if (p.cpw < 2 || (p.cpw & 1) || L % 64 != 0 || ALPHA * L > 1024 || !p.msg ||
+        p.wmax > WMAX || p.wmax > kLLChunkMax * ALPHA || lds > max_lds_bytes()) {
+        note_hip_error("decode_i8_ll_kernel: bad workgroup shape", hipErrorInvalidValue);
+        return hipErrorInvalidValue;
+    }
+    const int blocks = (p.n_cw + p.cpw - 1) / p.cpw;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL((decode_i8_ll_kernel<WMAX, ALPHA>), dim3(blocks), dim3(ALPHA * L), lds,
+                       stream, p, p.row_ptr, p.meta);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) note_hip_error("launch decode_i8_ll_kernel", e);
+    return e;
+}
+
+
 }  // namespace
 
 hipError_t launch_decode_i8(const DecodeLaunch &p, hipStream_t stream) {
+    if (p.alpha == 2) return p.wmax <= 10 ? launch_ll<10, 2>(p, stream) : launch_ll<20, 2>(p, stream);
+    if (p.alpha == 4) return p.wmax <= 10 ? launch_ll<10, 4>(p, stream) : launch_ll<20, 4>(p, stream);
     return p.msg ? launch_placed<false>(p, stream) : launch_placed<true>(p, stream);
+}
+
+int ll_message_pair_words(const int32_t *row_ptr, int rows, int alpha) {
+    int e = 0;
+    for (int r = 0; r < rows; ++r) {
+        const int w = row_ptr[r + 1] - row_ptr[r];
+        e += 2 * (alpha == 2 ? ll_row_dwords<2>(w) : alpha == 4 ? ll_row_dwords<4>(w) : (w + 1) / 2);
+    }
+    return e;
 }
 
 hipError_t launch_decode_batch(const BatchLaunch &b, hipStream_t stream) {

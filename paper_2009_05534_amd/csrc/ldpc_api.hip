@@ -136,7 +136,9 @@ int prepare_decode(const ldpc_args *a, bool upload, DecodeLaunch &p, bool &msg_i
         !a->out_bits || !a->out_iters || (a->precision != LDPC_I8 && a->precision != LDPC_F16) ||
         a->beta_q < 0 || a->beta_q > 255 || a->offset_q < 0 || a->offset_q > 127 ||
         (a->wq && a->wq_iters < 1) || (a->wh && a->wh_iters < 1) || a->cw_per_block < 0 ||
-        a->msg_placement < LDPC_MSG_AUTO || a->msg_placement > LDPC_MSG_DEVICE)
+        a->msg_placement < LDPC_MSG_AUTO || a->msg_placement > LDPC_MSG_DEVICE ||
+        (a->lanes_per_row != 0 && a->lanes_per_row != 1 && a->lanes_per_row != 2 &&
+         a->lanes_per_row != 4))
         return LDPC_EINVAL;
     g_msg[0] = '\0';
     int lds_cap = 0;
@@ -171,6 +173,8 @@ int prepare_decode(const ldpc_args *a, bool upload, DecodeLaunch &p, bool &msg_i
         p.E = E;
         p.wmax = wmax;
         p.groups = layer_groups(g.row_ptr.data(), g.col.data(), a->rows);
+        p.alpha = a->lanes_per_row > 1 ? a->lanes_per_row : 1;
+        if (p.alpha > 1) p.E_pad = ll_message_pair_words(g.row_ptr.data(), a->rows, p.alpha);
         lds_cap = max_lds_bytes();
     }
     p.llr = a->llr_in;
@@ -185,7 +189,22 @@ int prepare_decode(const ldpc_args *a, bool upload, DecodeLaunch &p, bool &msg_i
     const bool i8 = a->precision == LDPC_I8;
     int cpw = 0;
     msg_in_lds = false;
-    if (i8) {
+    if (p.alpha > 1) {
+        // Low-latency mapping: alpha lanes per check row, device-placed
+        // messages, whole waves per chunk group (pairs * Z a multiple of 64).
+        if (!i8 || a->msg_placement == LDPC_MSG_LDS || p.wmax > 20 ||
+            p.wmax > kLLChunkMax * p.alpha)
+            return LDPC_EINVAL;
+        int pairs = (a->cw_per_block + 1) / 2;
+        if (pairs == 0) {
+            pairs = 1;
+            while ((pairs * p.Z) % 64 != 0) ++pairs;
+        }
+        if ((pairs * p.Z) % 64 != 0 || p.alpha * pairs * p.Z > 1024 ||
+            ll_lds_bytes(p.n_cols, p.Z, pairs, p.alpha) > lds_cap)
+            return LDPC_EINVAL;
+        cpw = 2 * pairs;
+    } else if (i8) {
         // Codewords go in pairs of Z lanes. Message placement: LDS when two
         // pairs' full state fits a CU, else device memory so that several
         // pairs share a CU.

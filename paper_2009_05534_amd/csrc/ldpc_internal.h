@@ -60,6 +60,9 @@ struct DecodeLaunch {
     size_t msg_bytes;         // bytes allocated at msg (int8 device placement;
                               // kMsgTail bytes past the last pair's region)
     int cpw;                  // codewords per workgroup (int8: even, two per pair)
+    int alpha;                // int8: lanes per check row (1, 2 or 4; 2 and 4:
+                              // the low-latency mapping, E_pad = its message
+                              // pair words per check row, device placement)
     int wmax;                 // max row weight over the kept rows
     uint64_t groups;          // int8: bit r set = row r starts a new layer
                               // group (see layer_groups)
@@ -211,6 +214,17 @@ __host__ __device__ inline uint32_t pack_meta_i8(int c, int s, int Z) {
 __host__ __device__ inline uint32_t pack_meta_row(int c, int s, int Z) {
     return (uint32_t)(c * Z) | ((uint32_t)s << 16);
 }
+
+// Low-latency int8 mapping (alpha lanes per check row): chunks of at most
+// kLLChunkMax blocks per lane; LDS of `pairs` pairs' posteriors, their flags
+// and the two alternating exchange buffers [alpha][3][pairs * Z] dwords;
+// message pair words per check row of the first `rows` rows.
+constexpr int kLLChunkMax = 10;
+__host__ __device__ inline int ll_lds_bytes(int n_cols, int Z, int pairs, int alpha) {
+    return pairs * lds_bytes_i8_pair_post(n_cols, Z) + lds_flags_bytes_i8(pairs) +
+           2 * alpha * 3 * pairs * Z * 4;
+}
+int ll_message_pair_words(const int32_t *row_ptr, int rows, int alpha);
 
 // Host launchers; return hipSuccess or the launch error.
 hipError_t launch_decode_i8(const DecodeLaunch &p, hipStream_t stream);

@@ -39,7 +39,7 @@ class Args(ctypes.Structure):
         ("out_bits", ctypes.c_void_p), ("out_iters", ctypes.c_void_p),
         ("out_ok", ctypes.c_void_p), ("out_llr", ctypes.c_void_p),
         ("cw_per_block", ctypes.c_int), ("msg_placement", ctypes.c_int),
-        ("stream", ctypes.c_void_p),
+        ("lanes_per_row", ctypes.c_int), ("stream", ctypes.c_void_p),
     ]
 
 
@@ -178,7 +178,7 @@ def decode_into(llr, bg: int, Z: int, rows: int, out_bits, out_iters, *, max_ite
                 precision: str = "i8", early_exit: bool = True, beta: float | None = None,
                 offset: float = 0, weights=None, out_ok=None, out_llr=None,
                 cw_per_block: int = 0, msg_placement: str = "auto", stream=None,
-                noalloc: bool = False) -> None:
+                noalloc: bool = False, lanes_per_row: int = 0) -> None:
     """Decode int8 LLRs [n_cw, T] (device tensor) into preallocated outputs.
 
     ``noalloc``: call ldpc_decode_noalloc (messages in the library's static
@@ -231,6 +231,7 @@ def decode_into(llr, bg: int, Z: int, rows: int, out_bits, out_iters, *, max_ite
     a.out_llr = out_llr.data_ptr() if out_llr is not None else None
     a.cw_per_block = cw_per_block
     a.msg_placement = MSG_PLACEMENT[msg_placement]
+    a.lanes_per_row = lanes_per_row
     a.stream = _stream_ptr(stream)
     if noalloc:
         _check(lib().ldpc_decode_noalloc(ctypes.byref(a)), "ldpc_decode_noalloc")
@@ -241,7 +242,8 @@ def decode_into(llr, bg: int, Z: int, rows: int, out_bits, out_iters, *, max_ite
 def decode(llr, bg: int, Z: int, rows: int, *, max_iter: int = 10, precision: str = "i8",
            early_exit: bool = True, beta: float | None = None, offset: float = 0, weights=None,
            want_ok: bool = True, want_llr: bool = False, cw_per_block: int = 0,
-           msg_placement: str = "auto", stream=None, noalloc: bool = False):
+           msg_placement: str = "auto", stream=None, noalloc: bool = False,
+           lanes_per_row: int = 0):
     """Allocate outputs with torch on llr's device and decode (through
     ldpc_decode_noalloc when ``noalloc``; the outputs are still allocated
     here, by torch).
@@ -264,7 +266,7 @@ def decode(llr, bg: int, Z: int, rows: int, *, max_iter: int = 10, precision: st
     decode_into(llr, bg, Z, rows, bits, iters, max_iter=max_iter, precision=precision,
                 early_exit=early_exit, beta=beta, offset=offset, weights=weights, out_ok=ok,
                 out_llr=out, cw_per_block=cw_per_block, msg_placement=msg_placement,
-                stream=stream, noalloc=noalloc)
+                stream=stream, noalloc=noalloc, lanes_per_row=lanes_per_row)
     return bits, iters, (ok.bool() if ok is not None else None), out
 
 
