@@ -41,16 +41,19 @@ def log(msg):
 
 
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "decode_i8_bg1_z384_counters.md")
+KERNEL_SOURCES_F16 = ("decode_f16.hip", "ldpc_internal.h")
+COUNTERS_FILE_F16 = os.path.join(ROOT, "profiles", "decode_f16_bg1_z384_counters.md")
 KERNEL_SOURCES = ("decode_i8.hip", "ldpc_internal.h")
 
 
-def kernel_source_sha() -> str:
-    """Hash of the int8 kernel's sources with comments and blank space
-    removed (a comment edit does not change the measured kernel)."""
+def kernel_source_sha(sources=KERNEL_SOURCES) -> str:
+    """Hash of a kernel's sources (the int8 one by default) with comments
+    and blank space removed (a comment edit does not change the measured
+    kernel)."""
     import hashlib
     import re
     h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
+    for name in sources:
         with open(os.path.join(ROOT, "paper_2009_05534_amd", "csrc", name)) as f:
             text = f.read()
         text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
@@ -59,17 +62,17 @@ def kernel_source_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch of the int8 kernel from the committed counter
-    summary (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads
-    for a plain copy of known size), or None when the summary is missing or
-    was taken on other kernel sources."""
+def measured_traffic(counters_file=None, sources=None):
+    """HBM bytes per launch of a decode kernel (the int8 one by default)
+    from its committed counter summary (FETCH_SIZE and WRITE_SIZE, each
+    scaled by what the counter reads for a plain copy of known size), or
+    None when the summary is missing or was taken on other kernel sources."""
     try:
-        text = open(COUNTERS_FILE).read()
+        text = open(counters_file or COUNTERS_FILE).read()
         rec = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
     except (OSError, IndexError, ValueError):
         return None
-    if rec.get("kernel_source_sha") != kernel_source_sha():
+    if rec.get("kernel_source_sha") != kernel_source_sha(sources or KERNEL_SOURCES):
         return None
     return rec.get("traffic_bytes_per_launch")
 
@@ -107,7 +110,9 @@ def main():
                     help="target wall time of the CPU-oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the binary16, latency and fixed-iteration runs")
+                    help="skip the binary16, latency, fixed-iteration, batch and serving runs")
+    ap.add_argument("--extras", default="fixed,f16,latency,batched,serving",
+                    help="comma-separated subset of the extra runs to do")
     ap.add_argument("--data-cache", default="",
                     help="npz file holding the generated channel batches: loaded when present, "
                          "written otherwise (saves the generation time of repeated runs)")
@@ -115,6 +120,8 @@ def main():
                     help="run one plain device-to-device copy of this many MiB before timing "
                          "(reference dispatch for calibrating memory counters)")
     args = ap.parse_args()
+
+    extras = set() if args.no_extras else set(x for x in args.extras.split(",") if x)
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -252,7 +259,7 @@ def main():
                              "note": "int8 decoder with the trained per-(iteration, row) weights; "
                                      "bler/mean_iters above are plain beta = 3/4"}
 
-    if not args.no_extras:
+    if "fixed" in extras:
         log("timing int8, fixed 10 iterations")
         w10, l10, eu10 = timed("i8", False, 2, 1)
         result["fixed_iter"] = {
@@ -260,10 +267,25 @@ def main():
             "frac": round(OPS_PER_EDGE_UPDATE * eu10 / (sum(l10) / 1e3) / 1e12 / PEAK_ALU_TOPS, 4),
             "avg_launch_ms": round(float(np.mean(l10)), 4),
         }
+    if "f16" in extras:
         log("timing binary16, early exit")
-        w16, l16, _ = timed("f16", True, 2, 1)
-        result["f16"] = {"gbps": round(2 * len(batches) * n * K / w16 / 1e9, 3),
-                         "avg_launch_ms": round(float(np.mean(l16)), 4)}
+        w16, l16, eu16 = timed("f16", True, 2, 1)
+        ach16 = OPS_PER_EDGE_UPDATE * eu16 / (sum(l16) / 1e3) / 1e12
+        t16 = measured_traffic(COUNTERS_FILE_F16, KERNEL_SOURCES_F16)
+        result["f16"] = {
+            "gbps": round(2 * len(batches) * n * K / w16 / 1e9, 3),
+            "avg_launch_ms": round(float(np.mean(l16)), 4),
+            "roofline": {
+                "bound": "alu", "kernel": "decode_f16_kernel", "achieved": round(ach16, 3),
+                "peak": round(PEAK_ALU_TOPS, 2), "unit": "Top/s",
+                "frac": round(ach16 / PEAK_ALU_TOPS, 4), "traffic": t16,
+                "hbm_tb_per_s": (round(t16 / (float(np.mean(l16)) / 1e3) / 1e12, 3)
+                                 if t16 else None),
+                "per_unit": f"{OPS_PER_EDGE_UPDATE} packed binary16 element ops per edge-update",
+                "units_per_launch": round(eu16 / len(l16)),
+            },
+        }
+    if "latency" in extras:
         # single-codeword latency per iteration (fixed 10 iterations), with
         # one lane per check row and with the low-latency mapping (alpha
         # lanes per check row), at Z = 384 and Z = 128
@@ -299,7 +321,7 @@ def main():
             "note": "one codeword, 10 iterations, p50 over 50 calls, by lanes per check row",
             f"Z{Z}": lat1, "Z128": lat128}
 
-    if not args.no_extras:
+    if "batched" in extras:
         # Mixed-shape batch: 2048 codewords, (bg, Z, rows) drawn per codeword,
         # one persistent launch, captured as a HIP graph with an autotuned grid.
         from synth.mixed import make_mixed
@@ -328,8 +350,13 @@ def main():
                              "ms_per_launch": round(ms, 4), "shapes": len(groups),
                              **plan.info()}
         plan.close()
+    if "serving" in extras:
         log("serving sweep")
         from paper_2009_05534_amd import serve, nwms
+        from synth import LIFTS
+        for bgx in (1, 2):
+            for Zx in LIFTS:
+                ldpc.register(make_graph(bgx, Zx))
         wpath = os.path.join(ROOT, "paper_2009_05534_amd", "weights", "nwms_bg1_z384.npz")
         wq, shapes = None, None
         if os.path.exists(wpath):

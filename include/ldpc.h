@@ -191,9 +191,11 @@ void ldpc_args_init(ldpc_args *a);
 
 /* ldpc_decode_ex -- decode with the options of ldpc_args. Messages kept in
  * device memory take 2*ceil(n_cw/2)*E_pad*Z bytes (int8; E_pad = E with
- * every row's weight rounded up to even) or 2*n_cw*E*Z bytes (binary16),
- * allocated per call with hipMallocAsync on `stream` and released the same
- * way.
+ * every row's weight rounded up to even) or 2*n_cw*Rd*Z bytes (binary16,
+ * where every row's messages are stored exactly as a record of a1, a2 and
+ * per-block sign and argmin flags: Rd = the sum over rows of 3 dwords for
+ * rows of up to 8 blocks, 4 up to 16, 6 up to 32), allocated per call with
+ * hipMallocAsync on `stream` and released the same way.
  * Errors: as ldpc_decode. */
 int ldpc_decode_ex(const ldpc_args *a);
 
@@ -206,10 +208,11 @@ int ldpc_decode_ex(const ldpc_args *a);
  * held on every device the library runs on until the process ends) instead
  * of a per-call allocation. No device or host memory is allocated or freed.
  *   - Limit: the message bytes of ldpc_decode_ex (int8:
- *     2*ceil(n_cw/2)*E_pad*Z + 16 unless the messages are placed in LDS;
- *     binary16: 2*n_cw*E*Z) must not exceed the scratch, else LDPC_EINVAL
- *     and ldpc_last_error_message() names both sizes. At BG1 Z = 384 with
- *     46 rows that is up to 514 int8 or 276 binary16 codewords per call.
+ *     2*ceil(n_cw/2)*E_pad*Z + 16 unless the messages are placed in LDS,
+ *     more with lanes_per_row > 1; binary16: 2*n_cw*Rd*Z) must not exceed
+ *     the scratch, else LDPC_EINVAL and ldpc_last_error_message() names both
+ *     sizes. At BG1 Z = 384 with 46 rows that is up to 514 int8 or 578
+ *     binary16 codewords per call.
  *   - The graph's device tables must already be resident on the current
  *     device (any ldpc_decode / ldpc_decode_ex call of (bg, Z) there uploads
  *     them), else LDPC_ENOGRAPH with a message saying so.

@@ -7,10 +7,14 @@
 // is a single v_pk_*_f16 (rounded to nearest even, no contraction). The
 // posteriors live in LDS as half2 pair words (BG1-shaped at Z = 384:
 // 52,224 bytes, so three codewords fit one CU); the check-to-variable
-// messages (242 kB per codeword at that size) do not fit and stream through
-// device memory as coalesced half2 pair words -- the paper's half-precision
-// decoder met the same wall (§V). Magnitudes are compared as integers on
-// the bit patterns (monotone for non-negative halves).
+// messages do not fit and stream through device memory -- the paper's
+// half-precision decoder met the same wall (§V). Every message of a row is
+// +-a1 or +-a2 (§IV's min / second min), so a lane stores a row's messages
+// exactly as one record: a1 and a2 (half2: rows u and u + Z/2), the sign
+// bit of each block's message and a one-hot argmin flag per block, 3 dwords
+// for rows of up to 8 blocks, 4 up to 16, 6 up to 32 (BG1-shaped: 151
+// dwords per lane and iteration instead of 316). Magnitudes are compared as
+// integers on the bit patterns (monotone for non-negative halves).
 #include "ldpc_internal.h"
 
 namespace ldpc {
@@ -67,24 +71,66 @@ __device__ inline uint32_t normalise(uint32_t m, uint32_t off, h16x2 w) {
     return bits_of(w * v);
 }
 
-// Variable-to-check messages of blocks K0..K1-1: reads first (messages
-// from device memory, then posteriors from LDS), then x = L - R rounded to
+// Message record of a row of W blocks: dwords 0 and 1 hold a1 and a2, then
+// F(W) flag dwords with, per block k and half (bit b of the low half for
+// row u, of the high half for row u + Z/2), the message's sign bit and a
+// one-hot argmin flag:
+//   W <= 8 : one dword, sign at bit k, argmin at bit 8 + k;
+//   W <= 16: sign dword (bit k), argmin dword (bit k);
+//   W <= 32: the same pair for blocks 0..15, then for blocks 16..31.
+template <int W>
+struct Rec {
+    static constexpr int F = W <= 8 ? 1 : (W <= 16 ? 2 : 4);
+    static constexpr int N = 2 + F;
+    // dword and bit of block k's sign and argmin flag
+    static constexpr int sw(int k) { return 2 + (F == 4 ? 2 * (k >> 4) : 0); }
+    static constexpr int sb(int k) { return F == 4 ? (k & 15) : k; }
+    static constexpr int ow(int k) { return F == 1 ? 2 : (F == 2 ? 3 : 3 + 2 * (k >> 4)); }
+    static constexpr int ob(int k) { return F == 1 ? 8 + k : (F == 4 ? (k & 15) : k); }
+};
+
+// Per-half shifts of a pair word (both halves by the same amount; a
+// constant once the callers' loops are unrolled).
+__device__ inline uint32_t shl16(uint32_t v, int sh) {
+    return bits_of(as_u(v) << (u16x2){(unsigned short)sh, (unsigned short)sh});
+}
+__device__ inline uint32_t shr16(uint32_t v, int sh) {
+    return bits_of(as_u(v) >> (u16x2){(unsigned short)sh, (unsigned short)sh});
+}
+
+// Message of block k from the row's record: |R| = a2 on the argmin block,
+// else a1, with the stored sign bit.
+template <int W>
+__device__ inline uint32_t rec_message(const uint32_t *rec, int k) {
+    using RF = Rec<W>;
+    const uint32_t sgn = shl16(rec[RF::sw(k)], 15 - RF::sb(k)) & 0x80008000u;
+    // the argmin flag moved to bit 15 of each half, then spread over the half
+    typedef short s16x2 __attribute__((ext_vector_type(2)));
+    const s16x2 oh = __builtin_bit_cast(s16x2, shl16(rec[RF::ow(k)], 15 - RF::ob(k)));
+    const uint32_t arg = __builtin_bit_cast(uint32_t, oh >> (s16x2){15, 15});
+    return ((rec[1] & arg) | (rec[0] & ~arg)) | sgn;
+}
+
+// Adds block k's sign bit (bit 15 of each half of sgn) and argmin mask
+// (0xFFFF halves of arg) to the record being built.
+template <int W>
+__device__ inline void rec_put(uint32_t *rec, int k, uint32_t sgn, uint32_t arg) {
+    using RF = Rec<W>;
+    rec[RF::sw(k)] |= shr16(sgn, 15 - RF::sb(k));
+    rec[RF::ow(k)] |= arg & ((1u << RF::ob(k)) * 0x00010001u);
+}
+
+// Variable-to-check messages of blocks K0..K1-1: the check-to-variable
+// messages rebuilt from the row's record (all zero in the first
+// iteration), the posteriors read from LDS, then x = L - R rounded to
 // binary16, folded into m1 / m2 / S.
-template <int K0, int K1, bool KEEP_GATHER>
-__device__ __forceinline__ void row_phase1(const uint32_t *__restrict__ Lw,
-                                           const uint32_t *__restrict__ Rb, int ro,
-                                           const uint32_t *md, int e0, int u, int Zh,
-                                           bool first_iter, uint32_t *xv, int *la, uint32_t *sw,
-                                           u16x2 &m1, u16x2 &m2, uint32_t &S) {
+template <int W, int K0, int K1, bool KEEP_GATHER>
+__device__ __forceinline__ void row_phase1(const uint32_t *__restrict__ Lw, const uint32_t *rec,
+                                           const uint32_t *md, int u, int Zh, bool first_iter,
+                                           uint32_t *xv, int *la, uint32_t *sw, u16x2 &m1,
+                                           u16x2 &m2, uint32_t &S) {
     constexpr int n = K1 - K0;
     uint32_t lraw[n], rraw[n], swl[n];
-    if (!first_iter) {
-#pragma unroll
-        for (int i = 0; i < n; ++i) rraw[i] = msg_ld(Rb, e0 + K0 + i, Zh, ro);
-    } else {
-#pragma unroll
-        for (int i = 0; i < n; ++i) rraw[i] = 0;
-    }
 #pragma unroll
     for (int i = 0; i < n; ++i) {
         const Gather g = gather(md[K0 + i], u, Zh);
@@ -94,6 +140,13 @@ __device__ __forceinline__ void row_phase1(const uint32_t *__restrict__ Lw,
             sw[K0 + i] = g.rot;
         }
         lraw[i] = Lw[g.addr];
+    }
+    if (!first_iter) {
+#pragma unroll
+        for (int i = 0; i < n; ++i) rraw[i] = rec_message<W>(rec, K0 + i);
+    } else {
+#pragma unroll
+        for (int i = 0; i < n; ++i) rraw[i] = 0;
     }
     if constexpr (KEEP_GATHER) {
         // Narrow rows (K0 = 0, every edge): each step over all edges at
@@ -147,51 +200,63 @@ __device__ __forceinline__ void row_phase1(const uint32_t *__restrict__ Lw,
 // the int8 kernel the row is branch-free: metadata in one batch of scalar
 // loads, then the reads before any arithmetic; rows wider than 10 blocks
 // read in two halves and recompute their gathers for the write-back.
-// Message of block e for this lane: Rb[e * Zh + ro] (uniform base, 32-bit
-// lane offset).
+// Row record dword j of this lane: Rb[(P + j) * Zh + ro] (uniform base,
+// 32-bit lane offset); keep: store the new record (not in the last
+// iteration, where nothing reads it).
 template <int W>
 __device__ __forceinline__ void row_update_w(uint32_t *__restrict__ Lw, uint32_t *__restrict__ Rb,
                                              int ro, const uint32_t *__restrict__ meta, int e0,
-                                             int u, int Zh, bool first_iter, h16x2 wgt,
-                                             uint32_t off) {
+                                             int P, int u, int Zh, bool first_iter, bool keep,
+                                             h16x2 wgt, uint32_t off) {
+    using RF = Rec<W>;
     constexpr bool kWide = W > 10;
-    uint32_t md[W];
+    uint32_t md[W], rec[RF::N];
 #pragma unroll
     for (int k = 0; k < W; ++k) md[k] = meta[e0 + k];
+    if (!first_iter) {
+#pragma unroll
+        for (int j = 0; j < RF::N; ++j) rec[j] = msg_ld(Rb, P + j, Zh, ro);
+    }
     uint32_t xv[W], sw[W];
     int la[W];
     u16x2 m1 = {0x7C00, 0x7C00}, m2 = {0x7C00, 0x7C00};
     uint32_t S = 0;
     if constexpr (kWide) {
         constexpr int H = (W + 1) / 2;
-        row_phase1<0, H, false>(Lw, Rb, ro, md, e0, u, Zh, first_iter, xv, la, sw, m1, m2, S);
-        row_phase1<H, W, false>(Lw, Rb, ro, md, e0, u, Zh, first_iter, xv, la, sw, m1, m2, S);
+        row_phase1<W, 0, H, false>(Lw, rec, md, u, Zh, first_iter, xv, la, sw, m1, m2, S);
+        row_phase1<W, H, W, false>(Lw, rec, md, u, Zh, first_iter, xv, la, sw, m1, m2, S);
     } else {
-        row_phase1<0, W, true>(Lw, Rb, ro, md, e0, u, Zh, first_iter, xv, la, sw, m1, m2, S);
+        row_phase1<W, 0, W, true>(Lw, rec, md, u, Zh, first_iter, xv, la, sw, m1, m2, S);
     }
     const uint32_t a1 = normalise(bits_of(m1), off, wgt);
     const uint32_t a2 = normalise(bits_of(m2), off, wgt);
     const u16x2 m1p = m1 + (u16x2){1, 1};
+    uint32_t nrec[RF::N];
+    nrec[0] = a1;
+    nrec[1] = a2;
+#pragma unroll
+    for (int j = 2; j < RF::N; ++j) nrec[j] = 0;
     // The write-back one step at a time over groups of edges (all of a
     // narrow row, four of a wide one), for the same reason.
     constexpr int G = kWide ? 4 : W;
 #pragma unroll
     for (int g0 = 0; g0 < W; g0 += G) {
-        uint32_t Rg[G], Lg[G];
+        uint32_t Rg[G], Lg[G], Sg[G], Ag[G];
 #pragma unroll
         for (int i = 0; i < G; ++i) {
             const int k = g0 + i;
             if (k >= W) continue;
             // mask = 0xFFFF on the argmin edge (|x| == m1), else 0.
             const u16x2 t = __builtin_elementwise_sub_sat(m1p, as_u(xv[k] & 0x7FFF7FFFu));
-            Rg[i] = bits_of((u16x2){0, 0} - t);
+            Ag[i] = bits_of((u16x2){0, 0} - t);
         }
 #pragma unroll
         for (int i = 0; i < G; ++i) {
             const int k = g0 + i;
             if (k >= W) continue;
-            const uint32_t mag = (a2 & Rg[i]) | (a1 & ~Rg[i]);
-            Rg[i] = mag | ((S ^ xv[k]) & 0x80008000u);
+            const uint32_t mag = (a2 & Ag[i]) | (a1 & ~Ag[i]);
+            Sg[i] = (S ^ xv[k]) & 0x80008000u;
+            Rg[i] = mag | Sg[i];
             Lg[i] = bits_of(as_h(xv[k]) + as_h(Rg[i]));
         }
 #pragma unroll
@@ -204,8 +269,17 @@ __device__ __forceinline__ void row_update_w(uint32_t *__restrict__ Lw, uint32_t
             } else {
                 Lw[la[k]] = swap_halves(Lg[i], sw[k]);
             }
-            msg_st(Rb, e0 + k, Zh, ro, Rg[i]);
         }
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+            const int k = g0 + i;
+            if (k >= W) continue;
+            rec_put<W>(nrec, k, Sg[i], Ag[i]);
+        }
+    }
+    if (keep) {
+#pragma unroll
+        for (int j = 0; j < RF::N; ++j) msg_st(Rb, P + j, Zh, ro, nrec[j]);
     }
 }
 
@@ -237,14 +311,14 @@ __device__ __forceinline__ uint32_t row_parity_w(const uint32_t *__restrict__ Lw
 
 template <int W, int WMAX>
 __device__ __forceinline__ void row_update(int w, uint32_t *Lw, uint32_t *Rb, int ro,
-                                           const uint32_t *meta, int e0, int u, int Zh,
-                                           bool first_iter, h16x2 wgt, uint32_t off) {
+                                           const uint32_t *meta, int e0, int P, int u, int Zh,
+                                           bool first_iter, bool keep, h16x2 wgt, uint32_t off) {
     if constexpr (W <= WMAX) {
         if (w == W) {
-            row_update_w<W>(Lw, Rb, ro, meta, e0, u, Zh, first_iter, wgt, off);
+            row_update_w<W>(Lw, Rb, ro, meta, e0, P, u, Zh, first_iter, keep, wgt, off);
             return;
         }
-        row_update<W + 1, WMAX>(w, Lw, Rb, ro, meta, e0, u, Zh, first_iter, wgt, off);
+        row_update<W + 1, WMAX>(w, Lw, Rb, ro, meta, e0, P, u, Zh, first_iter, keep, wgt, off);
     }
 }
 
@@ -290,9 +364,11 @@ __global__ __launch_bounds__(512) void decode_f16_kernel(DecodeLaunch p,
     const bool valid = cw < p.n_cw;
     uint32_t *Lw = reinterpret_cast<uint32_t *>(smem + slot * slot_bytes);
     int *flags = reinterpret_cast<int *>(smem + p.cpw * slot_bytes);
-    // Messages: uniform base for the workgroup plus a 32-bit lane offset.
-    uint32_t *Rb = p.msg + (size_t)blockIdx.x * p.cpw * E * Zh;
-    const int ro = slot * E * Zh + u;
+    // Message records: uniform base for the workgroup plus a 32-bit lane
+    // offset; p.E_pad = record dwords per lane and iteration.
+    uint32_t *Rb = p.msg + (size_t)blockIdx.x * p.cpw * p.E_pad * Zh;
+    const int ro = slot * p.E_pad * Zh + u;
+    (void)E;
 
     if (valid) {
         Lw[u] = 0;
@@ -316,12 +392,19 @@ __global__ __launch_bounds__(512) void decode_f16_kernel(DecodeLaunch p,
         uint32_t wt = (uint32_t)(p.beta & 0xFFFF);
         const uint16_t *wrow = nullptr;
         if (p.wh) wrow = p.wh + (size_t)((t < p.w_iters ? t : p.w_iters) - 1) * p.rows;
+        // a barrier only where the next row shares a column with the rows
+        // since the last one (layer groups), and after the last row
+        const uint64_t bar = (p.groups >> 1) | (1ull << (p.rows - 1));
+        const bool keep = t < p.max_iter;  // the last iteration's records are never read
+        int P = 0;
         for (int r = 0; r < p.rows; ++r) {
             const int e0 = row_ptr[r], w = row_ptr[r + 1] - e0;
             if (wrow) wt = wrow[r];
             const h16x2 wgt = as_h(wt * 0x00010001u);
-            if (!done) row_update<2, WMAX>(w, Lw, Rb, ro, meta, e0, u, Zh, t == 1, wgt, off);
-            __syncthreads();
+            if (!done)
+                row_update<2, WMAX>(w, Lw, Rb, ro, meta, e0, P, u, Zh, t == 1, keep, wgt, off);
+            P += f16_record_dwords(w);
+            if ((bar >> r) & 1) __syncthreads();
         }
         if (p.early_exit || t == p.max_iter) {
             if ((int)threadIdx.x < p.cpw) flags[threadIdx.x] = 0;

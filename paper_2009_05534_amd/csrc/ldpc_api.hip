@@ -175,6 +175,12 @@ int prepare_decode(const ldpc_args *a, bool upload, DecodeLaunch &p, bool &msg_i
         p.groups = layer_groups(g.row_ptr.data(), g.col.data(), a->rows);
         p.alpha = a->lanes_per_row > 1 ? a->lanes_per_row : 1;
         if (p.alpha > 1) p.E_pad = ll_message_pair_words(g.row_ptr.data(), a->rows, p.alpha);
+        if (a->precision == LDPC_F16) {
+            // binary16: E_pad counts message record dwords per lane
+            int rec = 0;
+            for (int r = 0; r < a->rows; ++r) rec += f16_record_dwords(g.row_ptr[r + 1] - g.row_ptr[r]);
+            p.E_pad = rec;
+        }
         lds_cap = max_lds_bytes();
     }
     p.llr = a->llr_in;
@@ -251,7 +257,7 @@ int prepare_decode(const ldpc_args *a, bool upload, DecodeLaunch &p, bool &msg_i
     }
     msg_bytes = msg_in_lds ? 0
                 : i8 ? (((size_t)a->n_cw + 1) / 2) * p.E_pad * p.Z * 2 + kMsgTail
-                     : (size_t)a->n_cw * p.E * Zh * 4;
+                     : (size_t)a->n_cw * p.E_pad * Zh * 4;
     return LDPC_OK;
 }
 

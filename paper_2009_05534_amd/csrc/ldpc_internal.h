@@ -50,7 +50,8 @@ struct DecodeLaunch {
     const uint8_t *wq;        // int8 path per-(iteration,row) weights or null
     const uint16_t *wh;       // binary16 path weights or null
     uint32_t *msg;            // check-to-variable messages in device memory
-                              // (binary16: always, [n_cw][E][Zh] words; int8:
+                              // (binary16: always, [n_cw][E_pad][Zh] record
+                              // dwords; int8:
                               // when not kept in LDS, [ceil(n_cw/2)][E_pad*Z]
                               // pair words, see BlockWork; else null)
     int w_iters;
@@ -225,6 +226,12 @@ __host__ __device__ inline int ll_lds_bytes(int n_cols, int Z, int pairs, int al
            2 * alpha * 3 * pairs * Z * 4;
 }
 int ll_message_pair_words(const int32_t *row_ptr, int rows, int alpha);
+
+// binary16 message record of a row of w blocks (a1, a2 and the sign and
+// argmin flag words), in dwords per lane.
+__host__ __device__ inline int f16_record_dwords(int w) {
+    return 2 + (w <= 8 ? 1 : (w <= 16 ? 2 : 4));
+}
 
 // Host launchers; return hipSuccess or the launch error.
 hipError_t launch_decode_i8(const DecodeLaunch &p, hipStream_t stream);
