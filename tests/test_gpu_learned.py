@@ -13,7 +13,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 WEIGHTS = os.path.join(os.path.dirname(__file__), "..", "paper_2009_05534_amd", "weights",
-                       "nwms_bg1_z384.npz")
+                       "nwms_bg1_z384_select.npz")
 N = 1024
 
 
