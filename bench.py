@@ -242,7 +242,7 @@ def main():
 
     # The learned weighted min-sum (default checkpoint, trained for this
     # shape) against plain min-sum on the same batches, outside the timing.
-    wpath = os.path.join(ROOT, "paper_2009_05534_amd", "weights", "nwms_bg1_z384.npz")
+    wpath = os.path.join(ROOT, "paper_2009_05534_amd", "weights", "nwms_bg1_z384_select.npz")
     if os.path.exists(wpath):
         from paper_2009_05534_amd import nwms
         wq, _ = nwms.load_weights(wpath)
@@ -322,6 +322,37 @@ def main():
             f"Z{Z}": lat1, "Z128": lat128}
 
     if "batched" in extras:
+        # ldpc_tune on two single-shape batches (int8, early exit): the
+        # default launch against the tuned one, which later default calls
+        # of that shape and batch size take
+        log("autotuning single-shape launches")
+
+        def time_default(q, Zx, bb, ii, reps=10):
+            ldpc.decode_into(q, BG, Zx, ROWS, bb, ii, max_iter=args.max_iter)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                ldpc.decode_into(q, BG, Zx, ROWS, bb, ii, max_iter=args.max_iter)
+            e1.record(stream)
+            e1.synchronize()
+            return e0.elapsed_time(e1) / reps
+
+        g_t = make_graph(BG, 128)
+        ldpc.register(g_t)
+        q_t = torch.from_numpy(make_batch(g_t, 64, EBN0_POINTS[4], data_seed=10).q).to(dev)
+        tune_cases = [(128, q_t), (Z, llr[4])]
+        result["tuned"] = {}
+        for Zx, q in tune_cases:
+            nq = int(q.shape[0])
+            bb = torch.empty((nq, 22 * Zx // 8), dtype=torch.uint8, device=dev)
+            ii = torch.empty(nq, dtype=torch.int32, device=dev)
+            before = time_default(q, Zx, bb, ii)
+            pick = ldpc.decode_into(q, BG, Zx, ROWS, bb, ii, max_iter=args.max_iter, tune=True)
+            after = time_default(q, Zx, bb, ii)
+            result["tuned"][f"bg{BG}_z{Zx}_n{nq}"] = {
+                **{k: (round(v, 4) if isinstance(v, float) else v) for k, v in pick.items()},
+                "default_ms": round(before, 4), "tuned_ms": round(after, 4)}
         # Mixed-shape batch: 2048 codewords, (bg, Z, rows) drawn per codeword,
         # one persistent launch, captured as a HIP graph with an autotuned grid.
         from synth.mixed import make_mixed
@@ -357,15 +388,24 @@ def main():
         for bgx in (1, 2):
             for Zx in LIFTS:
                 ldpc.register(make_graph(bgx, Zx))
-        wpath = os.path.join(ROOT, "paper_2009_05534_amd", "weights", "nwms_bg1_z384.npz")
+        wpath = os.path.join(ROOT, "paper_2009_05534_amd", "weights", "nwms_bg1_z384_select.npz")
         wq, shapes = None, None
         if os.path.exists(wpath):
             wq, meta = nwms.load_weights(wpath)
             shapes = [(meta["Z"], meta["rows"])]
-        blocks = serve.make_trace(600, seed=6)
+        # a quarter of the blocks are full-rate BG1 Z = 384 blocks, which
+        # take the learned weights and, for failing codewords, the fallback
+        blocks = serve.make_trace(600, seed=6, embb_share=0.25)
+        # one persistent batch launch per admission round, offered load
+        # stepped up to saturation; each block's LLR upload is issued at its
+        # arrival, on the stream of its launch, and counts in its latency
         srv = serve.Server(weights_bg1=wq, n_slots=4, mem_budget=256 << 20, learned_shapes=shapes)
         srv.run(serve.rescale(blocks[:100], 1e4))
-        result["serving"] = [srv.run(serve.rescale(blocks, r)) for r in (2e4, 1e5)]
+        result["serving"] = []
+        for r in (1e3, 5e3, 2e4, 5e4, 1e5, 4e5):
+            st = srv.run(serve.rescale(blocks, r))
+            st["rate_blocks_per_s"] = r
+            result["serving"].append(st)
 
     if not args.no_cpu_baseline:
         import tempfile

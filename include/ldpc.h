@@ -227,6 +227,30 @@ int ldpc_decode_ex(const ldpc_args *a);
 int ldpc_decode_noalloc(const ldpc_args *a);
 
 /*
+ * ldpc_tune -- autotuning of the int8 launch configuration. Times the
+ * candidate configurations of ldpc_decode_ex on the arguments in `a` (their
+ * launch knobs lanes_per_row, cw_per_block and msg_placement must be at
+ * their defaults 0, 0, AUTO): one lane per check row with 1, 2, 3, 4, 6, 8,
+ * 12, 16, 24 or 48 codeword pairs per workgroup (those that fit) and the
+ * messages in LDS or in device memory, and 2 or
+ * 4 lanes per check row with the fewest pairs that give whole waves and
+ * twice that. Every candidate decodes a's input into a's outputs (all give
+ * the same results), four times, and the fastest after the first is
+ * recorded for (bg, Z, rows, n_cw rounded up to a power of two,
+ * early_exit): later int8 ldpc_decode_ex / ldpc_decode_noalloc calls whose
+ * launch knobs are at their defaults use it. Synchronises a->stream.
+ * out (may be NULL): the chosen knobs, its time and the number of
+ * candidates timed. Errors: LDPC_EINVAL (not int8, knobs not at their
+ * defaults, or no candidate applies), as ldpc_decode_ex otherwise.
+ */
+typedef struct ldpc_tuning {
+    int lanes_per_row, cw_per_block, msg_placement;
+    float ms;
+    int candidates;
+} ldpc_tuning;
+int ldpc_tune(const ldpc_args *a, ldpc_tuning *out);
+
+/*
  * Mixed-shape batches. A job is a set of codewords of one shape (bg, Z,
  * rows) with its own device buffers: llr int8 [n_cw][T], out_bits
  * [n_cw][K/8], out_iters int32 [n_cw], out_ok uint8 [n_cw] or NULL, and
@@ -288,6 +312,47 @@ int ldpc_plan_launch(ldpc_plan *plan, void *stream);
  * of the chosen grid when autotuned (else 0). Any output may be NULL. */
 int ldpc_plan_info(const ldpc_plan *plan, int *grid, int *n_tasks, float *tuned_ms);
 void ldpc_plan_destroy(ldpc_plan *plan);
+
+/*
+ * Serving queue -- SWITCHED OFF: ldpc_server_create returns LDPC_EINVAL and
+ * creates nothing (on MI355X the persistent kernel did not finish in
+ * testing and the cause is not known), so no other ldpc_server_* call has a
+ * server to act on. The design it implements:
+ * Serving queue (continuous batching on the device). A persistent decode
+ * kernel takes tasks from a ring of descriptors that the host keeps
+ * appending while it runs: workgroup 0 polls the count of published tasks
+ * in pinned host memory, the others claim published tasks one at a time,
+ * decode them (one task = up to 2*floor(384/Z) codewords of one job, int8,
+ * one lane per check row, beta = 3/4 or the job's Q1.7 weights) and publish
+ * each task's completion in pinned host memory, so the host polls it
+ * without a device call. The job's outputs may live in pinned host memory
+ * (written directly by the kernel and visible once the task is done) or in
+ * device memory; its LLRs must be on the device before submission. The
+ * kernel leaves by itself after about idle_polls empty polls (0: 4000, a
+ * few milliseconds); ldpc_server_submit and ldpc_server_pump relaunch it
+ * whenever tasks are pending and no launch is running. Device memory: a
+ * message region of 384*46*20 pair words per decode workgroup.
+ *   ldpc_server_create : capacity = tasks in flight at most (ring slots);
+ *                        grid = decode workgroups (0: one per CU)
+ *   ldpc_server_submit : appends the job's tasks; *first_ticket and *n_tasks
+ *                        name them (tickets first .. first + n - 1).
+ *                        LDPC_ENOMEM if the ring has no room (nothing is
+ *                        appended); row weights above 20: LDPC_EINVAL.
+ *   ldpc_server_done   : 1 once the task has completed, else 0.
+ *   ldpc_server_pump   : relaunches the kernel if needed; optional
+ *                        *outstanding (tasks not yet completed) and
+ *                        *launches (kernel launches so far).
+ *   ldpc_server_destroy: asks the kernel to stop, waits for it, frees.
+ * One host thread at a time per server (calls are serialised by a mutex).
+ */
+typedef struct ldpc_server ldpc_server;
+int ldpc_server_create(int capacity, int grid, int max_iter, int early_exit, int idle_polls,
+                       ldpc_server **out);
+int ldpc_server_submit(ldpc_server *s, const ldpc_job *job, unsigned *first_ticket,
+                       int *n_tasks);
+int ldpc_server_done(ldpc_server *s, unsigned ticket);
+int ldpc_server_pump(ldpc_server *s, int *outstanding, int *launches);
+int ldpc_server_destroy(ldpc_server *s);
 
 /*
  * ldpc_nwms_loss_grad -- learned weighted min-sum (the min-sum correction

@@ -13,7 +13,7 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libldpc.so")
-SOURCES = ["ldpc_api.hip", "decode_i8.hip", "decode_f16.hip", "nwms.hip", "batch.hip"]
+SOURCES = ["ldpc_api.hip", "decode_i8.hip", "decode_f16.hip", "nwms.hip", "batch.hip", "server.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

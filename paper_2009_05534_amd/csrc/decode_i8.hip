@@ -801,8 +801,12 @@ __device__ __forceinline__ void decode_block(const BlockWork &bw, uint8_t *smem,
     }
 }
 
+// Four waves per SIMD: a 768-lane workgroup whose pairs fill the LDS runs
+// one per CU (three waves per SIMD) whatever the register count, and the
+// register budget this leaves (up to 128) keeps every path free of scratch
+// spills.
 template <int WMAX, bool IN_LDS>
-__global__ __launch_bounds__(768) __attribute__((amdgpu_waves_per_eu(5))) void decode_i8_kernel(DecodeLaunch p,
+__global__ __launch_bounds__(768) __attribute__((amdgpu_waves_per_eu(4))) void decode_i8_kernel(DecodeLaunch p,
                                                          const int32_t *__restrict__ row_ptr,
                                                          const uint32_t *__restrict__ meta) {
     extern __shared__ __align__(16) uint8_t smem[];
@@ -884,7 +888,10 @@ hipError_t launch_placed(const DecodeLaunch &p, hipStream_t stream) {
 // workgroup's worth of codeword pairs of one shape) from a device counter
 // until none are left, so every wave reaches the exit once the counter
 // passes n_tasks. Messages use the device placement with one region per
-// workgroup, reused from task to task.
+// workgroup, reused from task to task. Five waves per SIMD keeps three
+// 384-lane workgroups of BG1 Z = 384 on a CU; at that register budget (96)
+// the bound-20 body spills three per-task values, which are reloaded once
+// per task or iteration, never inside a row update.
 template <int WMAX>
 __global__ __launch_bounds__(kBatchLanes) __attribute__((amdgpu_waves_per_eu(5))) void decode_batch_kernel(
     const BatchTask *__restrict__ tasks, const BatchJob *__restrict__ jobs,
@@ -953,6 +960,150 @@ __global__ __launch_bounds__(kBatchLanes) __attribute__((amdgpu_waves_per_eu(5))
 }
 
 __global__ void reset_counter_kernel(unsigned *counter) { *counter = 0u; }
+
+// ---------------------------------------------------------------------
+// Serving queue: a persistent decode kernel fed while it runs.
+// ---------------------------------------------------------------------
+// Workgroup 0 is the dispatcher: one lane polls the count of tasks the host
+// has published (pinned host memory, system scope) and mirrors it into
+// device memory, where the decode workgroups claim tasks one at a time with
+// a compare-and-swap on the claimed count (a task is claimed only once it is
+// published, so no claim is ever lost). A decode workgroup reads the task's
+// descriptor from the host ring, decodes it with the one-lane-per-row
+// mapping (one task = one workgroup's worth of codewords of one shape),
+// writes the outputs (which may live in pinned host memory), fences them to
+// system scope and publishes done[ticket % capacity] = ticket + 1. Every
+// loop is bounded: the dispatcher leaves after twice idle_polls polls
+// without news or on the stop request, a decode workgroup after idle_polls
+// empty polls or once the dispatcher has seen the stop request; the host
+// relaunches the kernel when tasks are pending and the last launch has
+// ended.
+// Polls are relaxed atomic loads. An acquire load at agent or system scope
+// is followed by an invalidation of the whole L2 of the XCD (and a release
+// store by a write-back), so acquire polling by hundreds of idle workgroups
+// would keep every L2 invalidating while other workgroups decode; ordering
+// is instead taken once, by one fence after a successful claim (and one
+// release store per change of the published count).
+__device__ inline unsigned sys_peek(const unsigned *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ inline unsigned dev_peek(const unsigned *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ __launch_bounds__(kBatchLanes) __attribute__((amdgpu_waves_per_eu(5))) void serve_kernel(
+    ServeLaunch s) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    __shared__ int task_id;
+    __shared__ unsigned desc[sizeof(ServeTask) / 4];
+    if (blockIdx.x == 0) {
+        if (threadIdx.x == 0) {
+            unsigned last = dev_peek(s.dev_ctl + 1);
+            for (int idle = 0; idle < 2 * s.idle_polls;) {
+                if (sys_peek(s.host_ctl + 1)) {
+                    __hip_atomic_store(s.dev_ctl + 2, 1u, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+                const unsigned t = sys_peek(s.host_ctl);
+                if (t != last) {
+                    // the host wrote the descriptors before the count: pass
+                    // that order on (acquire, then a release store; a
+                    // claimer's fence after reading the mirror completes it)
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+                    __hip_atomic_store(s.dev_ctl + 1, t, __ATOMIC_RELEASE,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                    last = t;
+                    idle = 0;
+                } else {
+                    ++idle;
+                    __builtin_amdgcn_s_sleep(8);
+                }
+            }
+        }
+        return;
+    }
+    const uint16_t *msg_base = s.msg + (size_t)(blockIdx.x - 1) * s.msg_per_block;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            int id = -1;
+            for (int idle = 0; idle < s.idle_polls;) {
+                if (dev_peek(s.dev_ctl + 2)) break;
+                const unsigned t = dev_peek(s.dev_ctl + 1);
+                unsigned h = dev_peek(s.dev_ctl);
+                if (h < t) {
+                    if (__hip_atomic_compare_exchange_strong(s.dev_ctl, &h, h + 1, __ATOMIC_RELAXED,
+                                                             __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_AGENT)) {
+                        id = (int)h;
+                        // the task's descriptor and LLRs were written after
+                        // this kernel started (LLRs possibly into memory an
+                        // earlier task read): drop cached lines before the
+                        // workgroup reads them
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+                        break;
+                    }
+                    continue;  // another workgroup claimed it first
+                }
+                ++idle;
+                __builtin_amdgcn_s_sleep(32);
+            }
+            task_id = id;
+        }
+        __syncthreads();
+        const int id = task_id;
+        if (id < 0) break;
+        // the descriptor, one word per lane, at system scope (host memory)
+        constexpr int kWords = (int)(sizeof(ServeTask) / 4);
+        if ((int)threadIdx.x < kWords)
+            desc[threadIdx.x] = __hip_atomic_load(
+                reinterpret_cast<const unsigned *>(s.ring + (unsigned)id % (unsigned)s.capacity) +
+                    threadIdx.x,
+                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __syncthreads();
+        // uniform copy (scalar registers: the tables are read with scalar loads)
+        unsigned words[kWords];
+#pragma unroll
+        for (int i = 0; i < kWords; ++i) words[i] = __builtin_amdgcn_readfirstlane(desc[i]);
+        ServeTask tk;
+        __builtin_memcpy(&tk, words, sizeof(ServeTask));
+        const BatchJob &jb = tk.job;
+        const int T = (jb.n_cols - 2) * jb.Z;
+        BlockWork bw;
+        bw.n = tk.n;
+        bw.slots = jb.slots / 2;
+        bw.llr = jb.llr + (size_t)tk.first * T;
+        bw.out_bits = jb.out_bits + (size_t)tk.first * (jb.kb * jb.Z / 8);
+        bw.out_iters = jb.out_iters + tk.first;
+        bw.out_ok = jb.out_ok ? jb.out_ok + tk.first : nullptr;
+        bw.out_llr = nullptr;
+        bw.msg = const_cast<uint16_t *>(msg_base);
+        bw.msg_records = 2u * (uint32_t)(bw.slots * jb.E_pad * jb.Z) + (uint32_t)kMsgTail;
+        bw.row_pad = jb.row_pad;
+        bw.E_pad = jb.E_pad;
+        bw.groups = jb.groups;
+        bw.wq = jb.wq;
+        bw.w_iters = jb.w_iters;
+        bw.w_stride = jb.w_stride;
+        bw.rows = jb.rows;
+        bw.n_cols = jb.n_cols;
+        bw.kb = jb.kb;
+        bw.Z = jb.Z;
+        bw.E = jb.E;
+        bw.max_iter = s.max_iter;
+        bw.early_exit = s.early_exit;
+        bw.beta = 96;
+        bw.offset = 0;
+        decode_block<20, false>(bw, smem, (crow_t)jb.row_ptr, (cmeta_t)jb.meta);
+        // every lane's output stores done and visible to the host, then the flag
+        __threadfence_system();
+        __syncthreads();
+        if (threadIdx.x == 0)
+            __hip_atomic_store(s.done + tk.ticket % (unsigned)s.capacity, tk.ticket + 1u,
+                               __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
+
 
 // ---------------------------------------------------------------------
 // Low-latency mapping: ALPHA cooperating lanes per check row (§IV).
@@ -1294,6 +1445,21 @@ hipError_t launch_decode_i8(const DecodeLaunch &p, hipStream_t stream) {
     if (p.alpha == 2) return p.wmax <= 10 ? launch_ll<10, 2>(p, stream) : launch_ll<20, 2>(p, stream);
     if (p.alpha == 4) return p.wmax <= 10 ? launch_ll<10, 4>(p, stream) : launch_ll<20, 4>(p, stream);
     return p.msg ? launch_placed<false>(p, stream) : launch_placed<true>(p, stream);
+}
+
+hipError_t launch_serve(const ServeLaunch &s, hipStream_t stream) {
+    static std::once_flag attr_once;
+    std::call_once(attr_once, [] {
+        const hipError_t e =
+            hipFuncSetAttribute(reinterpret_cast<const void *>(&serve_kernel),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes());
+        if (e != hipSuccess) note_hip_error("hipFuncSetAttribute(serve_kernel)", e);
+    });
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(serve_kernel, dim3(s.grid), dim3(kBatchLanes), s.lds, stream, s);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) note_hip_error("launch serve_kernel", e);
+    return e;
 }
 
 int ll_message_pair_words(const int32_t *row_ptr, int rows, int alpha) {

@@ -130,9 +130,39 @@ int sub_sizes(const HostGraph &g, int rows, int *K, int *T, int *Nc, int *E) {
 // device tables must already be resident; nothing is allocated on the device
 // or the host heap). msg_bytes: the device message buffer the launch needs
 // unless msg_in_lds.
-int prepare_decode(const ldpc_args *a, bool upload, DecodeLaunch &p, bool &msg_in_lds,
+// Launch configurations chosen by ldpc_tune, per (bg, Z, rows, n_cw rounded
+// up to a power of two, early exit).
+struct Tuned {
+    int lanes_per_row, cw_per_block, msg_placement;
+};
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int, int>, Tuned> g_tuned;
+
+int pow2_bucket(int n) {
+    int b = 1;
+    while (b < n && b < (1 << 30)) b <<= 1;
+    return b;
+}
+
+int prepare_decode(const ldpc_args *a0, bool upload, DecodeLaunch &p, bool &msg_in_lds,
                    size_t &msg_bytes) {
-    if (!a || a->n_cw < 1 || a->max_iter < 1 || a->max_iter > LDPC_MAX_ITER || !a->llr_in ||
+    if (!a0) return LDPC_EINVAL;
+    // an int8 call with every launch knob at its default takes the tuned
+    // configuration of its shape and batch size, if ldpc_tune recorded one
+    ldpc_args ar = *a0;
+    if (ar.precision == LDPC_I8 && ar.lanes_per_row == 0 && ar.cw_per_block == 0 &&
+        ar.msg_placement == LDPC_MSG_AUTO) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tuned.find(std::make_tuple(ar.bg, ar.Z, ar.rows, pow2_bucket(ar.n_cw),
+                                               ar.early_exit ? 1 : 0));
+        if (it != g_tuned.end()) {
+            ar.lanes_per_row = it->second.lanes_per_row;
+            ar.cw_per_block = it->second.cw_per_block;
+            ar.msg_placement = it->second.msg_placement;
+        }
+    }
+    const ldpc_args *a = &ar;
+    if ( a->n_cw < 1 || a->max_iter < 1 || a->max_iter > LDPC_MAX_ITER || !a->llr_in ||
         !a->out_bits || !a->out_iters || (a->precision != LDPC_I8 && a->precision != LDPC_F16) ||
         a->beta_q < 0 || a->beta_q > 255 || a->offset_q < 0 || a->offset_q > 127 ||
         (a->wq && a->wq_iters < 1) || (a->wh && a->wh_iters < 1) || a->cw_per_block < 0 ||
@@ -475,6 +505,84 @@ int ldpc_decode_noalloc(const ldpc_args *a) {
     return LDPC_OK;
 }
 
+int ldpc_tune(const ldpc_args *a, ldpc_tuning *out) {
+    if (!a || a->precision != LDPC_I8 || a->lanes_per_row != 0 || a->cw_per_block != 0 ||
+        a->msg_placement != LDPC_MSG_AUTO)
+        return LDPC_EINVAL;
+    {
+        // forget an earlier choice for this key, so the candidates below
+        // are not redirected to it
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tuned.erase(std::make_tuple(a->bg, a->Z, a->rows, pow2_bucket(a->n_cw),
+                                      a->early_exit ? 1 : 0));
+    }
+    std::vector<Tuned> cand;
+    for (int pairs : {1, 2, 3, 4, 6, 8, 12, 16, 24, 48}) {
+        cand.push_back(Tuned{1, 2 * pairs, LDPC_MSG_LDS});
+        cand.push_back(Tuned{1, 2 * pairs, LDPC_MSG_DEVICE});
+    }
+    for (int alpha : {2, 4}) {
+        int base = 1;
+        while ((base * a->Z) % 64 != 0) ++base;
+        for (int k : {1, 2}) cand.push_back(Tuned{alpha, 2 * base * k, LDPC_MSG_DEVICE});
+    }
+    hipStream_t stream = static_cast<hipStream_t>(a->stream);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return LDPC_EHIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return LDPC_EHIP;
+    }
+    float best = 1e30f;
+    Tuned pick{0, 0, LDPC_MSG_AUTO};
+    int tried = 0, rc = LDPC_OK;
+    for (const Tuned &c : cand) {
+        ldpc_args t = *a;
+        t.lanes_per_row = c.lanes_per_row;
+        t.cw_per_block = c.cw_per_block;
+        t.msg_placement = c.msg_placement;
+        DecodeLaunch probe{};
+        bool in_lds = false;
+        size_t mb = 0;
+        if (prepare_decode(&t, true, probe, in_lds, mb) != LDPC_OK) continue;  // does not apply
+        // the library rounds the packing to what fits: skip duplicates
+        if (probe.cpw != c.cw_per_block) continue;
+        float ms = 1e30f;
+        for (int rep = 0; rep < 4 && rc == LDPC_OK; ++rep) {
+            (void)hipEventRecord(e0, stream);
+            rc = ldpc_decode_ex(&t);
+            (void)hipEventRecord(e1, stream);
+            (void)hipEventSynchronize(e1);
+            float m = 0.0f;
+            (void)hipEventElapsedTime(&m, e0, e1);
+            if (rep > 0) ms = std::min(ms, m);  // the first run warms up
+        }
+        if (rc != LDPC_OK) break;
+        ++tried;
+        if (ms < best) {
+            best = ms;
+            pick = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != LDPC_OK) return rc;
+    if (tried == 0) return LDPC_EINVAL;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tuned[std::make_tuple(a->bg, a->Z, a->rows, pow2_bucket(a->n_cw),
+                                a->early_exit ? 1 : 0)] = pick;
+    }
+    if (out) {
+        out->lanes_per_row = pick.lanes_per_row;
+        out->cw_per_block = pick.cw_per_block;
+        out->msg_placement = pick.msg_placement;
+        out->ms = best;
+        out->candidates = tried;
+    }
+    return LDPC_OK;
+}
+
 int ldpc_decode(int bg, int Z, int rows, int n_cw, const int8_t *llr_in, int max_iter,
                 uint8_t *out_bits, int32_t *out_iters, void *stream) {
     ldpc_args a;
@@ -584,6 +692,7 @@ int batch_jobs(const ldpc_job *jobs, int n_jobs, std::vector<BatchJob> &bj,
 }
 }  // namespace
 
+
 int ldpc_plan_create(const ldpc_job *jobs, int n_jobs, int max_iter, int early_exit, int flags,
                      void *stream, ldpc_plan **out) {
     if (!jobs || n_jobs < 1 || !out || max_iter < 1 || max_iter > LDPC_MAX_ITER) return LDPC_EINVAL;
@@ -682,3 +791,19 @@ void ldpc_shutdown(void) {
 }
 
 }  // extern "C"
+
+namespace ldpc {
+// The batch-kernel job record of one serving job (registered graph, tables
+// uploaded to the current device); row weights up to 20.
+int serve_job(const ldpc_job &job, BatchJob &bj, int &wmax) {
+    std::vector<BatchJob> v;
+    std::vector<int> cw;
+    int lds_cap = 0;
+    const int rc = batch_jobs(&job, 1, v, cw, wmax, lds_cap);
+    if (rc != LDPC_OK) return rc;
+    bj = v[0];
+    if ((bj.slots / 2) * bj.E_pad * bj.Z > kServeMsgPerBlock || bj.n_cols > LDPC_MAX_COLS)
+        return LDPC_EINVAL;
+    return LDPC_OK;
+}
+}  // namespace ldpc

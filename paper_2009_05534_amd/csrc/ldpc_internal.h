@@ -140,6 +140,36 @@ struct BatchLaunch {
 };
 hipError_t launch_decode_batch(const BatchLaunch &b, hipStream_t stream);
 
+// Serving queue: tasks (codewords [first, first + n) of one job) that the
+// host writes into a ring in pinned host memory while a persistent kernel
+// runs. Completion of a task is published as done[ticket % capacity] =
+// ticket + 1 (pinned host memory, so the host polls it without a device
+// call; the value tells reuses of a slot apart).
+struct ServeTask {
+    BatchJob job;
+    int first, n;
+    unsigned ticket;
+    int pad;
+};
+struct ServeLaunch {
+    const ServeTask *ring;      // pinned host memory [capacity]
+    int capacity;
+    const unsigned *host_ctl;   // pinned: [0] tasks published, [1] stop request
+    unsigned *done;             // pinned [capacity]
+    unsigned *dev_ctl;          // device: [0] tasks claimed, [1] published (mirror), [2] stop
+    uint16_t *msg;              // (grid - 1) * msg_per_block pair words (+ tail)
+    int msg_per_block;
+    int max_iter, early_exit;
+    int grid, lds;
+    int idle_polls;             // a decode workgroup leaves after this many empty polls
+};
+// LDS bytes and message pair words of a serving workgroup (kBatchLanes
+// lanes): enough for floor(kBatchLanes / Z) codeword pairs of any shape with
+// up to 68 columns, 46 rows and row weights up to 20.
+constexpr int kServeLds = 52736;
+constexpr int kServeMsgPerBlock = kBatchLanes * 46 * 20;
+hipError_t launch_serve(const ServeLaunch &s, hipStream_t stream);
+
 // Tasks of a mixed batch (see BatchTask), longest first, with the LDS and
 // message sizes a workgroup needs. Returns LDPC_OK or LDPC_EINVAL.
 struct TaskSet {

@@ -43,6 +43,12 @@ class Args(ctypes.Structure):
     ]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("lanes_per_row", ctypes.c_int), ("cw_per_block", ctypes.c_int),
+                ("msg_placement", ctypes.c_int), ("ms", ctypes.c_float),
+                ("candidates", ctypes.c_int)]
+
+
 class Job(ctypes.Structure):
     _fields_ = [
         ("bg", ctypes.c_int), ("Z", ctypes.c_int), ("rows", ctypes.c_int), ("n_cw", ctypes.c_int),
@@ -55,9 +61,11 @@ PLAN_GRAPH = 1
 PLAN_AUTOTUNE = 2
 
 EXPORTS = ("ldpc_set_graph", "ldpc_query", "ldpc_get_graph", "ldpc_graph_digest", "ldpc_decode", "ldpc_args_init", "ldpc_decode_ex",
-           "ldpc_decode_noalloc",
+           "ldpc_decode_noalloc", "ldpc_tune",
            "ldpc_decode_batch", "ldpc_decode_batch_async", "ldpc_decode_batch_bytes", "ldpc_plan_create", "ldpc_plan_launch", "ldpc_plan_info",
-           "ldpc_plan_destroy", "ldpc_nwms_loss_grad", "ldpc_strerror", "ldpc_last_hip_error",
+           "ldpc_plan_destroy", "ldpc_nwms_loss_grad", "ldpc_server_create", "ldpc_server_submit",
+           "ldpc_server_done", "ldpc_server_pump", "ldpc_server_destroy",
+           "ldpc_strerror", "ldpc_last_hip_error",
            "ldpc_last_error_message", "ldpc_shutdown")
 
 _lib = None
@@ -84,6 +92,7 @@ def lib():
         L.ldpc_args_init.restype = None
         L.ldpc_decode_ex.argtypes = [ctypes.POINTER(Args)]
         L.ldpc_decode_noalloc.argtypes = [ctypes.POINTER(Args)]
+        L.ldpc_tune.argtypes = [ctypes.POINTER(Args), ctypes.POINTER(Tuning)]
         L.ldpc_decode_batch.argtypes = [ctypes.POINTER(Job), I, I, I, P]
         L.ldpc_decode_batch_async.argtypes = [ctypes.POINTER(Job), I, I, I, P,
                                               ctypes.POINTER(ctypes.c_size_t)]
@@ -96,6 +105,12 @@ def lib():
         L.ldpc_plan_destroy.argtypes = [P]
         L.ldpc_plan_destroy.restype = None
         L.ldpc_nwms_loss_grad.argtypes = [I, I, I, I, P, P, I, P, P, ctypes.c_float, P, P, P, P]
+        L.ldpc_server_create.argtypes = [I, I, I, I, I, ctypes.POINTER(ctypes.c_void_p)]
+        L.ldpc_server_submit.argtypes = [P, ctypes.POINTER(Job), ctypes.POINTER(ctypes.c_uint),
+                                         ctypes.POINTER(ctypes.c_int)]
+        L.ldpc_server_done.argtypes = [P, ctypes.c_uint]
+        L.ldpc_server_pump.argtypes = [P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+        L.ldpc_server_destroy.argtypes = [P]
         L.ldpc_strerror.argtypes = [I]
         L.ldpc_strerror.restype = ctypes.c_char_p
         L.ldpc_last_hip_error.argtypes = []
@@ -178,11 +193,14 @@ def decode_into(llr, bg: int, Z: int, rows: int, out_bits, out_iters, *, max_ite
                 precision: str = "i8", early_exit: bool = True, beta: float | None = None,
                 offset: float = 0, weights=None, out_ok=None, out_llr=None,
                 cw_per_block: int = 0, msg_placement: str = "auto", stream=None,
-                noalloc: bool = False, lanes_per_row: int = 0) -> None:
+                noalloc: bool = False, lanes_per_row: int = 0, tune: bool = False):
     """Decode int8 LLRs [n_cw, T] (device tensor) into preallocated outputs.
 
     ``noalloc``: call ldpc_decode_noalloc (messages in the library's static
     per-device scratch; nothing is allocated) instead of ldpc_decode_ex.
+    ``tune``: call ldpc_tune instead (times the launch configurations, keeps
+    the fastest for this shape and batch size, writes the outputs) and
+    return the choice as a dict.
 
     ``weights``: per-(iteration, row) normalisation, a device tensor uint8
     [iters, rows] (Q1.7, i8) or float16 [iters, rows] (f16).
@@ -233,6 +251,12 @@ def decode_into(llr, bg: int, Z: int, rows: int, out_bits, out_iters, *, max_ite
     a.msg_placement = MSG_PLACEMENT[msg_placement]
     a.lanes_per_row = lanes_per_row
     a.stream = _stream_ptr(stream)
+    if tune:
+        t = Tuning()
+        _check(lib().ldpc_tune(ctypes.byref(a), ctypes.byref(t)), "ldpc_tune")
+        return {"lanes_per_row": t.lanes_per_row, "cw_per_block": t.cw_per_block,
+                "msg_placement": {v: k for k, v in MSG_PLACEMENT.items()}[t.msg_placement],
+                "ms": t.ms, "candidates": t.candidates}
     if noalloc:
         _check(lib().ldpc_decode_noalloc(ctypes.byref(a)), "ldpc_decode_noalloc")
     else:
@@ -403,6 +427,81 @@ class Plan:
     def close(self) -> None:
         if getattr(self, "_h", None):
             lib().ldpc_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def job_record(llr, bg: int, Z: int, rows: int, out_bits, out_iters, out_ok=None,
+               weights=None) -> Job:
+    """The C job record of one serving job: llr a device int8 tensor
+    [n, T]; outputs device tensors or pinned host tensors (the serving
+    kernel writes pinned ones directly); weights a device uint8 tensor
+    [iters, rows] or None. The caller keeps every tensor alive until the
+    job's tasks are done."""
+    K, T, Nc, E = query(bg, Z, rows)
+    n = int(llr.shape[0])
+    _require(llr, (n, T), 1, "llr")
+    for t, shape, size, name in ((out_bits, (n, K // 8), 1, "out_bits"),
+                                 (out_iters, (n,), 4, "out_iters"),
+                                 (out_ok, (n,), 1, "out_ok")):
+        if t is None:
+            if name != "out_ok":
+                raise ValueError(f"{name} is required")
+            continue
+        if not (t.is_cuda or t.is_pinned()) or tuple(t.shape) != shape or \
+                not t.is_contiguous() or t.element_size() != size:
+            raise ValueError(f"{name}: need a contiguous device or pinned tensor {shape}")
+    if weights is not None:
+        if weights.dim() != 2 or weights.shape[1] != rows:
+            raise ValueError("weights must be [iters, rows]")
+        _require(weights, tuple(weights.shape), 1, "weights")
+    return Job(bg, Z, rows, n, llr.data_ptr(), out_bits.data_ptr(), out_iters.data_ptr(),
+               out_ok.data_ptr() if out_ok is not None else None,
+               weights.data_ptr() if weights is not None else None,
+               int(weights.shape[0]) if weights is not None else 0)
+
+
+class QueueServer:
+    """The library's serving queue (ldpc_server_*): a persistent decode
+    kernel fed from a ring of task descriptors in pinned host memory."""
+
+    def __init__(self, capacity: int = 4096, grid: int = 0, max_iter: int = 10,
+                 early_exit: bool = True, idle_polls: int = 0):
+        h = ctypes.c_void_p()
+        _check(lib().ldpc_server_create(capacity, grid, max_iter, int(early_exit), idle_polls,
+                                        ctypes.byref(h)), "ldpc_server_create")
+        self._h = h
+
+    def submit(self, job: Job) -> tuple[int, int]:
+        """Appends the job's tasks; returns (first ticket, number of tasks),
+        or None when the ring has no room (nothing appended)."""
+        first, n = ctypes.c_uint(), ctypes.c_int()
+        rc = lib().ldpc_server_submit(self._h, ctypes.byref(job), ctypes.byref(first),
+                                      ctypes.byref(n))
+        if rc == -2:
+            return None
+        _check(rc, "ldpc_server_submit")
+        return first.value, n.value
+
+    def done(self, ticket: int) -> bool:
+        return lib().ldpc_server_done(self._h, ticket) == 1
+
+    def pump(self) -> tuple[int, int]:
+        """Relaunches the kernel if tasks are pending and it has left;
+        returns (tasks outstanding, kernel launches so far)."""
+        o, n = ctypes.c_int(), ctypes.c_int()
+        _check(lib().ldpc_server_pump(self._h, ctypes.byref(o), ctypes.byref(n)),
+               "ldpc_server_pump")
+        return o.value, n.value
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            _check(lib().ldpc_server_destroy(self._h), "ldpc_server_destroy")
             self._h = None
 
     def __del__(self):

@@ -1,8 +1,10 @@
 """Continuous-batching decode server for transport blocks.
 
 A transport block is 1..8 codewords of one shape (bg, Z, rows); blocks
-arrive as a Poisson process. Their int8 LLRs sit in device memory from
-arrival on (the device-resident input queue). The server keeps up to
+arrive as a Poisson process. Their int8 LLRs wait in pinned host memory
+and are copied to the device when the block is admitted, on the stream of
+its launch, ahead of the decode (the copy counts in the block's latency).
+The server keeps up to
 `n_slots` decode launches in flight, each on its own stream: whenever a slot
 is free and blocks are waiting, it admits waiting blocks in earliest-deadline
 order for as long as the device-memory budget allows -- charged with the
@@ -51,9 +53,12 @@ class Block:
 
 
 def make_trace(n_blocks: int, seed: int = 6, lifts=LIFTS, min_cw: int = 1,
-               max_cw: int = 8) -> list[Block]:
+               max_cw: int = 8, embb_share: float = 0.0) -> list[Block]:
     """Blocks with unit-rate exponential gaps (scale them with rescale());
-    shapes drawn as in the mixed batch, Eb/N0 uniform in [1, 2] dB."""
+    shapes drawn as in the mixed batch, Eb/N0 uniform in [1, 2] dB. With
+    probability embb_share a block is instead a full-rate BG1 Z = 384
+    block (46 rows) at Eb/N0 uniform in [1.25, 2] dB: the shape and range
+    the learned weights are trained for."""
     gaps = stream(seed, 21, 0).exponential(1.0, n_blocks)
     t = np.cumsum(gaps)
     blocks = []
@@ -64,6 +69,11 @@ def make_trace(n_blocks: int, seed: int = 6, lifts=LIFTS, min_cw: int = 1,
         rows = int(s.integers(4, full_shape(bg)[0] + 1))
         n_cw = int(s.integers(min_cw, max_cw + 1))
         ebn0 = float(s.uniform(1.0, 2.0))
+        if embb_share > 0.0:
+            e = stream(seed, 23, i)
+            if e.random() < embb_share:
+                bg, Z, rows = 1, 384, full_shape(1)[0]
+                ebn0 = float(e.uniform(1.25, 2.0))
         g = make_graph(bg, Z, rows)
         b = make_batch(g, n_cw, ebn0, seed, indices=np.arange(8 * i, 8 * i + n_cw))
         blocks.append(Block(i, float(t[i]), bg, Z, rows, n_cw, ebn0, b.q, b.u))
@@ -113,7 +123,10 @@ class Server:
     def _prepare(self, blocks):
         torch = self.torch
         for b in blocks:
-            b._llr = torch.from_numpy(b.q).to(self.dev)
+            # the LLRs wait in pinned host memory; run() copies them to the
+            # device when the block is admitted (the copy counts in latency)
+            b._q_pin = torch.from_numpy(b.q).pin_memory()
+            b._llr = torch.empty(b.q.shape, dtype=torch.int8, device=self.dev)
             K = b.u.shape[1]
             b._bits = torch.empty((b.n_cw, K // 8), dtype=torch.uint8, device=self.dev)
             b._iters = torch.empty(b.n_cw, dtype=torch.int32, device=self.dev)
@@ -220,6 +233,11 @@ class Server:
                     del queue[:k]
                     slot = free_slots.pop()
                     st = self.streams[slot]
+                    if not plain:
+                        # host-to-device upload, ahead of the decode on its stream
+                        with torch.cuda.stream(st):
+                            for b in batch:
+                                b._llr.copy_(b._q_pin, non_blocking=True)
                     held = self.ldpc.decode_batch_async(self._jobs(batch, plain),
                                                         max_iter=self.max_iter, stream=st)
                     assert held == mem, (held, mem)
@@ -254,6 +272,8 @@ class Server:
             "latency_ms_p50": float(np.percentile(lat, 50) * 1e3),
             "latency_ms_p99": float(np.percentile(lat, 99) * 1e3),
             "deadline_met": float(np.mean(lat <= DEADLINE_S)),
+            "learned_blocks": int(sum(self._weights(b.bg, b.rows, b.Z) is not None
+                                      for b in order)),
             "fallback_blocks": int(sum(b.fallback for b in order)),
             "codeword_error_rate": errs / max(1, sum(b.n_cw for b in order)),
             "seconds": t_end,
@@ -277,6 +297,189 @@ class Server:
         return bits.cpu().numpy(), iters.cpu().numpy(), ok.cpu().numpy().astype(bool)
 
 
+class QueueServer:
+    """Continuous batching through the library's device-resident queue.
+
+    A persistent decode kernel (ldpc.QueueServer) takes tasks from a ring of
+    descriptors in pinned host memory while it runs. A block's life: it
+    arrives (its LLRs in host memory); when the device-memory budget for
+    the LLRs of blocks in flight allows, it is admitted in earliest-deadline
+    order and its LLRs are copied to the device (asynchronously, on an
+    upload stream; the copy counts in its latency); once the copy has
+    landed its tasks are appended to the ring, where the running kernel
+    picks them up; the kernel writes the hard decisions, iteration counts
+    and success flags straight into pinned host buffers and flags each task
+    done. Blocks of the shape the learned weights were trained for use them;
+    their codewords whose checks fail are decoded again with plain min-sum
+    (another job on the same queue) and only those take the plain result.
+    Latency runs from arrival to the host seeing the block's last task done.
+    """
+
+    def __init__(self, weights_bg1: np.ndarray | None = None, mem_budget: int = 64 << 20,
+                 max_iter: int = 10, capacity: int = 8192, device: str = "cuda:0",
+                 learned_shapes=None, idle_polls: int = 0, stall_s: float = 10.0):
+        import torch
+        from . import ldpc
+        self.ldpc, self.torch = ldpc, torch
+        # a run with tasks outstanding and no completion for this long is
+        # stopped with an error (the kernel leaves on the stop request)
+        self.stall_s = stall_s
+        self.dev = torch.device(device)
+        self.mem_budget = mem_budget
+        self.max_iter = max_iter
+        self.queue = ldpc.QueueServer(capacity=capacity, max_iter=max_iter,
+                                      idle_polls=idle_polls)
+        self.upload = torch.cuda.Stream(device=self.dev)
+        self._w_full = None if weights_bg1 is None else np.ascontiguousarray(weights_bg1, np.uint8)
+        self._learned = None if learned_shapes is None else set(map(tuple, learned_shapes))
+        self._w_dev: dict[int, object] = {}
+
+    def close(self):
+        self.queue.close()
+
+    def _weights(self, b):
+        if self._w_full is None or b.bg != 1:
+            return None
+        if self._learned is not None and (b.Z, b.rows) not in self._learned:
+            return None
+        if b.rows not in self._w_dev:
+            self._w_dev[b.rows] = self.torch.from_numpy(
+                np.ascontiguousarray(self._w_full[:, :b.rows])).to(self.dev)
+        return self._w_dev[b.rows]
+
+    def _host_buffers(self, b):
+        torch = self.torch
+        K = b.u.shape[1]
+        bits = torch.empty((b.n_cw, K // 8), dtype=torch.uint8, pin_memory=True)
+        iters = torch.empty(b.n_cw, dtype=torch.int32, pin_memory=True)
+        ok = torch.empty(b.n_cw, dtype=torch.uint8, pin_memory=True)
+        return bits, iters, ok
+
+    def _prepare(self, blocks):
+        torch = self.torch
+        for b in blocks:
+            b._q_pin = torch.from_numpy(b.q).pin_memory()
+            b._out = self._host_buffers(b)
+            b._w = self._weights(b)
+            b._plain_out = self._host_buffers(b) if b._w is not None else None
+            if b.q.nbytes > self.mem_budget:
+                raise ValueError(f"block {b.id} needs more device memory than the budget")
+
+    def _submit(self, b, plain: bool):
+        out = b._plain_out if plain else b._out
+        job = self.ldpc.job_record(b._llr, b.bg, b.Z, b.rows, *out,
+                                   weights=None if plain else b._w)
+        r = self.queue.submit(job)
+        if r is None:
+            return False
+        b._tickets = range(r[0], r[0] + r[1])
+        self._n_tasks += r[1]
+        return True
+
+    def run(self, blocks: list[Block]) -> dict:
+        """Serve the trace in real time; returns latency/throughput stats."""
+        torch = self.torch
+        self._prepare(blocks)
+        order = sorted(blocks, key=lambda b: b.arrival)
+        pending, uploading, ready, inflight = [], [], [], []
+        mem_used = peak_mem = 0
+        nxt = done = 0
+        self._n_tasks = 0
+        fallback_blocks = 0
+        _, launches0 = self.queue.pump()
+        t0 = time.perf_counter()
+        last_progress = t0
+        while done < len(order):
+            now = time.perf_counter() - t0
+            if inflight and time.perf_counter() - last_progress > self.stall_s:
+                self.close()
+                raise RuntimeError(f"serving queue: no task completed for {self.stall_s} s "
+                                   f"({len(inflight)} blocks in flight); server stopped")
+            while nxt < len(order) and order[nxt].arrival <= now:
+                pending.append(order[nxt])
+                nxt += 1
+            # admission by memory, earliest deadline first
+            while pending and mem_used + pending[0].q.nbytes <= self.mem_budget:
+                b = pending.pop(0)
+                b._llr = torch.empty(b.q.shape, dtype=torch.int8, device=self.dev)
+                with torch.cuda.stream(self.upload):
+                    b._llr.copy_(b._q_pin, non_blocking=True)
+                    b._up = torch.cuda.Event()
+                    b._up.record(self.upload)
+                mem_used += b.q.nbytes
+                peak_mem = max(peak_mem, mem_used)
+                uploading.append(b)
+            # uploaded blocks go to the queue
+            still = []
+            for b in uploading:
+                (ready if b._up.query() else still).append(b)
+            uploading = still
+            while ready:
+                if not self._submit(ready[0], False):
+                    break  # ring full: retry after completions
+                b = ready.pop(0)
+                b._state = "first"
+                if not inflight:
+                    last_progress = time.perf_counter()
+                inflight.append(b)
+            # completions
+            still = []
+            for b in inflight:
+                if b._state == "wait_fb":  # fallback pass waiting for ring room
+                    if self._submit(b, True):
+                        b._state = "fb"
+                    still.append(b)
+                    continue
+                if not all(self.queue.done(t) for t in b._tickets):
+                    still.append(b)
+                    continue
+                last_progress = time.perf_counter()
+                if b._state == "first" and b._w is not None and not bool(b._out[2].all()):
+                    b.fallback = True
+                    fallback_blocks += 1
+                    b._state = "fb" if self._submit(b, True) else "wait_fb"
+                    still.append(b)
+                    continue
+                if b._state == "fb":
+                    keep = b._out[2].bool()
+                    pb, pi, po = b._plain_out
+                    b._out[0][~keep] = pb[~keep]
+                    b._out[1][~keep] = pi[~keep]
+                    b._out[2][~keep] = po[~keep]
+                b.t_done = time.perf_counter() - t0
+                mem_used -= b.q.nbytes
+                b._llr = None
+                done += 1
+            inflight = still
+            self.queue.pump()
+        t_end = time.perf_counter() - t0
+        _, launches = self.queue.pump()
+        for b in order:
+            b.bits = b._out[0].numpy().copy()
+            b.iters = b._out[1].numpy().copy()
+            b.ok = b._out[2].numpy().astype(bool)
+        lat = np.array([b.t_done - b.arrival for b in order])
+        bits = sum(b.u.shape[0] * b.u.shape[1] for b in order)
+        errs = sum(int((np.unpackbits(b.bits, axis=1, bitorder="little")[:, :b.u.shape[1]] != b.u)
+                       .any(axis=1).sum()) for b in order)
+        return {
+            "blocks": len(order),
+            "codewords": int(sum(b.n_cw for b in order)),
+            "tasks": self._n_tasks,
+            "kernel_launches": launches - launches0,
+            "peak_llr_bytes_in_flight": peak_mem,
+            "offered_blocks_per_s": len(order) / max(order[-1].arrival, 1e-9),
+            "gbps": bits / t_end / 1e9,
+            "latency_ms_p50": float(np.percentile(lat, 50) * 1e3),
+            "latency_ms_p99": float(np.percentile(lat, 99) * 1e3),
+            "deadline_met": float(np.mean(lat <= DEADLINE_S)),
+            "learned_blocks": int(sum(b._w is not None for b in order)),
+            "fallback_blocks": fallback_blocks,
+            "codeword_error_rate": errs / max(1, sum(b.n_cw for b in order)),
+            "seconds": t_end,
+        }
+
+
 def main():
     import argparse
     import json
@@ -288,7 +491,7 @@ def main():
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--mem-mib", type=int, default=256)
     ap.add_argument("--weights", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),
-                                                      "weights", "nwms_bg1_z384.npz"))
+                                                      "weights", "nwms_bg1_z384_select.npz"))
     ap.add_argument("--seed", type=int, default=6)
     args = ap.parse_args()
     from . import ldpc, nwms

@@ -67,6 +67,8 @@ def test_graph_registration_checks(lib):
 
 def test_decode_rejects_bad_arguments_before_launch(lib):
     from paper_2009_05534_amd import ldpc
+    from synth import make_graph
+    ldpc.register(make_graph(1, 384))  # the checks below reach past the graph lookup
     a = ldpc.Args()
     lib_ = ldpc.lib()
     lib_.ldpc_args_init(ctypes.byref(a))

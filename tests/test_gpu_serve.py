@@ -109,3 +109,53 @@ def test_memory_budget_limits_admission(server_mod):
     srv2 = serve.Server(n_slots=1, mem_budget=1)
     with pytest.raises(ValueError):
         srv2.run(serve.rescale(serve.make_trace(3, seed=8), 1e3))
+
+
+QUEUE_OFF = "the device queue is switched off: its persistent kernel did not finish on MI355X in two runs (the first cause, acquire polling, was fixed; the second is not known), so this case stays off the GPU"
+
+
+@pytest.mark.skip(reason=QUEUE_OFF)
+@pytest.mark.parametrize("rate", [2e3, 5e4])
+def test_queue_server_equals_oracle(server_mod, rate):
+    # the device-resident queue (persistent kernel fed from a host ring):
+    # every block equals the oracle under the serving policy, the learned
+    # pass and its plain fallback both run, and admission keeps the LLRs in
+    # flight within the budget
+    serve = server_mod
+    blocks = serve.make_trace(120, seed=6)
+    wq = np.random.default_rng(0).integers(40, 112, (10, 46)).astype(np.uint8)
+    budget = 4 << 20
+    srv = serve.QueueServer(weights_bg1=wq, mem_budget=budget)
+    trace = serve.rescale(blocks, rate)
+    print(f"[serve] queue server, {len(trace)} blocks at {rate} blocks/s", flush=True)
+    stats = srv.run(trace)
+    srv.close()
+    assert stats["blocks"] == 120 and stats["latency_ms_p99"] > 0
+    assert 0 < stats["peak_llr_bytes_in_flight"] <= budget
+    assert stats["fallback_blocks"] > 0, stats
+    assert stats["tasks"] >= 120 and stats["kernel_launches"] >= 1
+    for b in trace:
+        rb, ri, ro = oracle_policy(b, wq)
+        assert (b.bits == rb).all(), ("oracle", b.id)
+        assert (b.iters == ri).all(), ("oracle", b.id)
+        assert (b.ok == ro).all(), ("oracle", b.id)
+
+
+@pytest.mark.skip(reason=QUEUE_OFF)
+def test_queue_server_relaunches_after_idle(server_mod):
+    # the persistent kernel leaves once idle (here after ~200 empty polls)
+    # and the next submission starts it again; results stay correct
+    import time
+    serve = server_mod
+    blocks = [b for b in serve.make_trace(60, seed=13)][:12]
+    srv = serve.QueueServer(mem_budget=64 << 20, idle_polls=200)
+    s1 = srv.run(serve.rescale(blocks[:6], 1e4))
+    time.sleep(0.2)  # far longer than the kernel's idle limit
+    _, launches_before = srv.queue.pump()
+    s2 = srv.run(serve.rescale(blocks[6:], 1e4))
+    _, launches_after = srv.queue.pump()
+    srv.close()
+    assert s1["kernel_launches"] >= 1 and launches_after > launches_before
+    for b in blocks:
+        rb, ri, ro = oracle_policy(b, None)
+        assert (b.bits == rb).all() and (b.iters == ri).all() and (b.ok == ro).all(), b.id
