@@ -155,3 +155,23 @@ def test_library_graph_feeds_the_oracle(lib):
         assert (got.M, got.N, got.kb, got.n_punct) == (ref.M, ref.N, ref.kb, ref.n_punct)
         assert (got.row_ptr == ref.row_ptr).all()
         assert (got.col == ref.col).all() and (got.shift == ref.shift).all()
+
+
+def test_tune_and_server_refusals_without_a_gpu(lib):
+    # ldpc_tune only tunes int8 calls whose launch knobs are at their
+    # defaults, and refuses the rest before any device work; the serving
+    # queue is switched off and creates nothing
+    from paper_2009_05534_amd import ldpc
+    L = ldpc.lib()
+    for field, value in (("precision", 1), ("lanes_per_row", 2), ("cw_per_block", 2),
+                         ("msg_placement", 1)):
+        a = ldpc.Args()
+        L.ldpc_args_init(ctypes.byref(a))
+        a.bg, a.Z, a.rows, a.n_cw = 1, 384, 46, 4
+        setattr(a, field, value)
+        t = ldpc.Tuning()
+        assert L.ldpc_tune(ctypes.byref(a), ctypes.byref(t)) == -1, field
+    assert L.ldpc_tune(None, None) == -1
+    h = ctypes.c_void_p()
+    assert L.ldpc_server_create(64, 0, 10, 1, 0, ctypes.byref(h)) == -1
+    assert not h.value
