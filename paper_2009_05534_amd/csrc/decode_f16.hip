@@ -374,7 +374,7 @@ __global__ __launch_bounds__(512) void decode_f16_kernel(DecodeLaunch p,
         Lw[u] = 0;
         Lw[Zh + u] = 0;
         const int8_t *q = p.llr + (size_t)cw * T;
-#pragma unroll 1
+#pragma unroll 8
         for (int c = 2; c < N; ++c) {
             int lo = q[(c - 2) * Z + u], hi = q[(c - 2) * Z + u + Zh];
             lo = lo < -127 ? -127 : lo;

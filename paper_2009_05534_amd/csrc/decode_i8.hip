@@ -93,6 +93,8 @@ struct MsgRow {
     uint32_t ro;                  // device: pair base; LDS: lane's edge-0 byte address
     uint32_t row;                 // device: byte offset of the row in the pair region
     bool keep;                    // false in the last iteration: nothing reads them again
+    bool rmask_on;                // device: AND the loaded message dwords with rmask
+    uint32_t rmask;               //   (clears the bytes of halves that start afresh)
 
     // Loads the row's message dwords d[C0 .. (W + 1) / 2) (device placement;
     // LDS placement loads them all).
@@ -355,6 +357,10 @@ __device__ __forceinline__ void row_update_w(uint8_t *__restrict__ smem, uint32_
             R.template load_rt<ND, kPreDwords>(rd, u, nd);
         else if (ND > kPreDwords)
             R.template load<W, kPreDwords>(rd, u, Z);
+        if (R.rmask_on) {
+#pragma unroll
+            for (int j = 0; j < ND; ++j) rd[j] &= R.rmask;
+        }
     }
     uint32_t xv[W], axv[W], la[W];
     u16x2 m1 = {0x7FFF, 0x7FFF}, m2 = {0x7FFF, 0x7FFF};
@@ -615,6 +621,55 @@ __device__ inline void write_outputs(const BlockWork &bw, const uint8_t *Lp, int
     }
 }
 
+// Outputs of the pair's halves that hold codewords cwA / cwB (absolute
+// indices from bw's output bases; -1 = nothing to write for that half),
+// each with its own iteration count and syndrome flag. Same packing as
+// write_outputs.
+__device__ inline void write_outputs_ids(const BlockWork &bw, const uint8_t *Lp, uint32_t u,
+                                         int cwA, int cwB, int itA, int itB, int okA, int okB) {
+    int Z = bw.Z;
+    __asm__ volatile("" : "+v"(cwA), "+v"(cwB), "+v"(u), "+s"(Z));
+    const int bpc = Z / 8, nbytes = bw.kb * bpc;
+    const int kbytes = bw.kb * Z / 8;
+#pragma unroll 1
+    for (int i = (int)u; i < nbytes; i += Z) {
+        const int c = i / bpc, j = i - c * bpc;
+        const uint2 *w2 = reinterpret_cast<const uint2 *>(Lp + 2 * (c * Z + 8 * j));
+        uint32_t ba = 0, bb = 0;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const uint2 w = w2[h];
+            const uint32_t d0 = w.x, d1 = w.y;
+            ba |= (((d0 >> 7) & 1u) | ((d0 >> 22) & 2u) | ((d1 << 2) >> 7 & 4u) |
+                   ((d1 >> 20) & 8u)) << (4 * h);
+            bb |= (((d0 >> 15) & 1u) | ((d0 >> 30) & 2u) | ((d1 >> 13) & 4u) |
+                   ((d1 >> 28) & 8u)) << (4 * h);
+        }
+        if (cwA >= 0) bw.out_bits[(size_t)cwA * kbytes + i] = (uint8_t)ba;
+        if (cwB >= 0) bw.out_bits[(size_t)cwB * kbytes + i] = (uint8_t)bb;
+    }
+    if (u == 0) {
+        if (cwA >= 0) {
+            bw.out_iters[cwA] = itA;
+            if (bw.out_ok) bw.out_ok[cwA] = (uint8_t)okA;
+        }
+        if (cwB >= 0) {
+            bw.out_iters[cwB] = itB;
+            if (bw.out_ok) bw.out_ok[cwB] = (uint8_t)okB;
+        }
+    }
+    if (bw.out_llr) {
+        const int Nc = bw.n_cols * Z;
+        const uint16_t *Lw = reinterpret_cast<const uint16_t *>(Lp);
+#pragma unroll 1
+        for (int c = 0; c < bw.n_cols; ++c) {
+            const uint16_t v = Lw[c * Z + u];
+            if (cwA >= 0) bw.out_llr[(size_t)cwA * Nc + c * Z + u] = (int8_t)(v & 0xFF);
+            if (cwB >= 0) bw.out_llr[(size_t)cwB * Nc + c * Z + u] = (int8_t)(v >> 8);
+        }
+    }
+}
+
 typedef const __attribute__((address_space(4))) uint32_t *cw32_t;
 
 // Synchronisation of the lanes that decode one block of work: the whole
@@ -645,7 +700,7 @@ __device__ inline int row_weight(const uint8_t *wrow, int r) {
 template <bool IN_LDS>
 __device__ inline MsgRow<IN_LDS> msg_row(uint8_t *smem, uint32_t ro,
                                          __amdgpu_buffer_rsrc_t rsrc, int e0, int p0, int Z) {
-    MsgRow<IN_LDS> R{rsrc, nullptr, 0u, 0u, true};
+    MsgRow<IN_LDS> R{rsrc, nullptr, 0u, 0u, true, false, 0xFFFFFFFFu};
     if (IN_LDS) {
         R.lds = smem;
         R.ro = ro + 2u * (uint32_t)(e0 * Z);
@@ -665,7 +720,8 @@ __device__ __forceinline__ void layer_pass(const BlockWork &bw, uint8_t *smem, u
                                            uint32_t ro, __amdgpu_buffer_rsrc_t rsrc,
                                            crow_t row_ptr, cmeta_t meta, const uint8_t *wrow,
                                            uint32_t u, bool busy, u16x2 off16, uint32_t *pre,
-                                           bool keep) {
+                                           bool keep, bool rmask_on = false,
+                                           uint32_t rmask = 0xFFFFFFFFu) {
     const int Z = bw.Z;
     crow_t row_pad = (crow_t)bw.row_pad;
     // a barrier only where the next row shares a column with the rows since
@@ -688,6 +744,8 @@ __device__ __forceinline__ void layer_pass(const BlockWork &bw, uint8_t *smem, u
         const u16x2 wgt = {(unsigned short)wt, (unsigned short)wt};
         MsgRow<IN_LDS> R = msg_row<IN_LDS>(smem, ro, rsrc, e0, p0, Z);
         R.keep = keep;
+        R.rmask_on = rmask_on;
+        R.rmask = rmask;
         if (busy) {
             row_update_any<WMAX, IN_LDS, FIRST>(w, smem, lb, R, meta, e0, u, Z, wgt, off16, pre);
             // the next row's messages exist unless this is the first
@@ -701,6 +759,57 @@ __device__ __forceinline__ void layer_pass(const BlockWork &bw, uint8_t *smem, u
         p0 = pn;
         p1 = p2;
         (void)rn;
+    }
+}
+
+// Channel LLRs of a pair's two codewords into its pair words (low byte
+// qa's codeword, high byte qb's; columns 0 and 1 are punctured and start at
+// zero), clamped at -127. Eight columns' loads are issued before any of
+// them is used: a loop that waits for each load in turn would spend the
+// memory latency once per column, tens of microseconds per workgroup. A
+// missing codeword (has = false) reads the other pointer's bytes, which
+// are then replaced by zero, so the loads need no branch.
+__device__ inline void load_pair_llrs(uint16_t *Lw, const int8_t *qa, bool hasA,
+                                      const int8_t *qb, bool hasB, int N, int Z, uint32_t u) {
+    Lw[u] = 0;
+    Lw[Z + u] = 0;
+#pragma unroll 1
+    for (int c0 = 2; c0 < N; c0 += 8) {
+        int va[8], vb[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int c = c0 + k < N ? c0 + k : N - 1;
+            va[k] = qa[(c - 2) * Z + u];
+            vb[k] = qb[(c - 2) * Z + u];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if (c0 + k < N) {
+                const int a = hasA ? (va[k] < -127 ? -127 : va[k]) : 0;
+                const int b = hasB ? (vb[k] < -127 ? -127 : vb[k]) : 0;
+                Lw[(c0 + k) * Z + u] = (uint16_t)((a & 0xFF) | ((b & 0xFF) << 8));
+            }
+        }
+    }
+}
+
+// One codeword's channel LLRs into one half of a pair's words: Lb is the
+// byte of this lane's column-0 word that holds the half (pair words are
+// 2 bytes, so column c's byte is at Lb + 2 c Z). Loads batched as above.
+__device__ inline void load_half_llrs(uint8_t *Lb, const int8_t *q, int N, int Z, uint32_t u) {
+    Lb[0] = 0;
+    Lb[2 * Z] = 0;
+#pragma unroll 1
+    for (int c0 = 2; c0 < N; c0 += 8) {
+        int v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int c = c0 + k < N ? c0 + k : N - 1;
+            v[k] = q[(c - 2) * Z + u];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (c0 + k < N) Lb[2 * (c0 + k) * Z] = (uint8_t)(v[k] < -127 ? -127 : v[k]);
     }
 }
 
@@ -741,20 +850,12 @@ __device__ __forceinline__ void decode_block(const BlockWork &bw, uint8_t *smem,
     const __amdgpu_buffer_rsrc_t rsrc =
         __builtin_amdgcn_make_buffer_rsrc(bw.msg, 0, IN_LDS ? 0 : bw.msg_records, 0x00020000);
 
-    // Initialisation: punctured columns 0 and 1 carry no channel LLR.
+    // Initialisation: the pair's channel LLRs (punctured columns 0 and 1
+    // carry none).
     if (validA) {
-        Lw[u] = 0;
-        Lw[Z + u] = 0;
         const int8_t *qa = bw.llr + (size_t)(2 * p) * T;
-        const int8_t *qb = bw.llr + (size_t)(2 * p + 1) * T;
-#pragma unroll 1
-        for (int c = 2; c < N; ++c) {
-            int a = qa[(c - 2) * Z + u];
-            int b = validB ? qb[(c - 2) * Z + u] : 0;
-            a = a < -127 ? -127 : a;
-            b = b < -127 ? -127 : b;
-            Lw[c * Z + u] = (uint16_t)((a & 0xFF) | ((b & 0xFF) << 8));
-        }
+        const int8_t *qb = validB ? bw.llr + (size_t)(2 * p + 1) * T : qa;
+        load_pair_llrs(Lw, qa, true, qb, validB, N, Z, u);
     }
     block_sync<WAVE>();
 
@@ -799,6 +900,155 @@ __device__ __forceinline__ void decode_block(const BlockWork &bw, uint8_t *smem,
             if (flags[2 * bw.slots]) break;
         }
     }
+}
+
+// Persistent schedule for int8 decodes with early exit and device-placed
+// messages: the grid holds only as many workgroups as run at once, and each
+// half of each codeword pair takes the next codeword from a device counter
+// as soon as its own finishes (all checks hold, or max_iter), so no lane
+// waits for a slower partner or for the slowest codeword of its block, and
+// no workgroup waits for the launch's last wave of blocks. A fresh half
+// starts at its iteration 1 while its partner continues: its posteriors
+// are loaded over its bytes of the pair words, and in its first round its
+// bytes of every message dword this lane loads (those of the codeword
+// before) are masked to zero, so it reads zero messages exactly as a
+// codeword that starts with its pair. Every half's arithmetic depends only on its own codeword,
+// so the results are those of any other schedule. Plain normalisation only
+// (per-iteration weights would differ between the halves). The loop ends
+// once no half holds a codeword; each round advances every held codeword
+// by one iteration and the counter only grows, so it ends after at most
+// max_iter rounds per codeword handed to the workgroup.
+template <int WMAX>
+__device__ __forceinline__ void decode_refill(const BlockWork &bw, uint8_t *smem, crow_t row_ptr,
+                                              cmeta_t meta, unsigned *counter, int n_total) {
+    static_assert(WMAX <= kMetaPad, "row metadata window exceeds the table padding");
+    const int Z = bw.Z;
+    const int N = bw.n_cols, T = (N - 2) * Z;
+    const int pair_bytes = lds_bytes_i8_pair_post(N, Z);
+    const int tid = (int)threadIdx.x;
+    const int p = tid / Z;
+    const uint32_t u = tid - p * Z;
+    uint8_t *Lp = smem + p * pair_bytes;
+    uint16_t *Lw = reinterpret_cast<uint16_t *>(Lp);
+    const uint32_t lb = (uint32_t)(p * pair_bytes) + 2u * u;
+    const uint32_t ro = 2u * (uint32_t)(p * bw.E_pad * Z);
+    int *flags = reinterpret_cast<int *>(smem + bw.slots * pair_bytes);
+    int *held = flags + 2 * bw.slots + 2;  // codeword index per half, -1 = none
+    const __amdgpu_buffer_rsrc_t rsrc =
+        __builtin_amdgcn_make_buffer_rsrc(bw.msg, 0, bw.msg_records, 0x00020000);
+    crow_t row_pad = (crow_t)bw.row_pad;
+
+    if (tid == 0) {
+        const int want = 2 * bw.slots;
+        const unsigned base = atomicAdd(counter, (unsigned)want);
+        for (int h = 0; h < want; ++h)
+            held[h] = (long)base + h < (long)n_total ? (int)(base + (unsigned)h) : -1;
+    }
+    __syncthreads();
+    int idA = held[2 * p], idB = held[2 * p + 1];
+    load_pair_llrs(Lw, bw.llr + (size_t)(idA >= 0 ? idA : 0) * T, idA >= 0,
+                   bw.llr + (size_t)(idB >= 0 ? idB : 0) * T, idB >= 0, N, Z, u);
+    __syncthreads();
+
+    const u16x2 off16 = {(unsigned short)(bw.offset << 8), (unsigned short)(bw.offset << 8)};
+    uint32_t pre[kPreDwords] = {0u, 0u, 0u, 0u};
+    int tA = 1, tB = 1;  // the iteration each half runs next
+    uint32_t rkeep = 0xFFFFFFFFu;  // message bytes kept this round (fresh halves: none)
+    for (bool first = true;; first = false) {
+        const bool actA = idA >= 0, actB = idB >= 0;
+        const bool busy = actA || actB;
+        // a wave-uniform switch: some lane of this wave holds a fresh half
+        const bool masked = __ballot(rkeep != 0xFFFFFFFFu) != 0;
+        // messages are always stored: a half may go on after this round
+        if (first)
+            layer_pass<WMAX, false, true, false>(bw, smem, lb, ro, rsrc, row_ptr, meta, nullptr, u,
+                                                 busy, off16, pre, true);
+        else
+            layer_pass<WMAX, false, false, false>(bw, smem, lb, ro, rsrc, row_ptr, meta, nullptr,
+                                                  u, busy, off16, pre, true, masked, rkeep);
+        rkeep = 0xFFFFFFFFu;
+        if (tid < 2 * bw.slots) flags[tid] = 0;
+        __syncthreads();
+        if (busy)
+            syndrome_mark<WMAX>(smem, lb, row_ptr, meta, bw.rows, u, Z, flags + 2 * p, actA, actB);
+        __syncthreads();
+        const bool holdsA = flags[2 * p] == 0, holdsB = flags[2 * p + 1] == 0;
+        const bool finA = actA && (holdsA || tA >= bw.max_iter);
+        const bool finB = actB && (holdsB || tB >= bw.max_iter);
+        if (finA || finB)
+            write_outputs_ids(bw, Lp, u, finA ? idA : -1, finB ? idB : -1, tA, tB, holdsA ? 1 : 0,
+                              holdsB ? 1 : 0);
+        // the next codewords for the halves that finished (one lane per pair)
+        if (u == 0 && (finA || finB)) {
+            const unsigned need = (finA ? 1u : 0u) + (finB ? 1u : 0u);
+            unsigned base = atomicAdd(counter, need);
+            if (finA) {
+                held[2 * p] = (long)base < (long)n_total ? (int)base : -1;
+                ++base;
+            }
+            if (finB) held[2 * p + 1] = (long)base < (long)n_total ? (int)base : -1;
+        }
+        __syncthreads();
+        const int nA = finA ? held[2 * p] : idA, nB = finB ? held[2 * p + 1] : idB;
+        const bool freshA = finA && nA >= 0, freshB = finB && nB >= 0;
+        if (freshA || freshB) {
+            // the new codewords' channel LLRs over their bytes of the pair words
+            if (freshA) load_half_llrs(Lp + 2 * u, bw.llr + (size_t)nA * T, N, Z, u);
+            if (freshB) load_half_llrs(Lp + 2 * u + 1, bw.llr + (size_t)nB * T, N, Z, u);
+            // the fresh halves' bytes of the messages this lane loads in
+            // the next round (those of the codewords before) read as zero
+            rkeep = (freshA ? 0xFF00FF00u : 0xFFFFFFFFu) & (freshB ? 0x00FF00FFu : 0xFFFFFFFFu);
+#pragma unroll
+            for (int j = 0; j < kPreDwords; ++j) pre[j] &= rkeep;
+        }
+        if (finA) {
+            idA = nA;
+            tA = 1;
+        } else if (actA) {
+            ++tA;
+        }
+        if (finB) {
+            idB = nB;
+            tB = 1;
+        } else if (actB) {
+            ++tB;
+        }
+        if (!__syncthreads_or(idA >= 0 || idB >= 0)) break;
+    }
+}
+
+template <int WMAX>
+__global__ __launch_bounds__(768) __attribute__((amdgpu_waves_per_eu(4))) void decode_i8_refill_kernel(
+    DecodeLaunch p, const int32_t *__restrict__ row_ptr, const uint32_t *__restrict__ meta) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    BlockWork bw;
+    bw.n = p.cpw;
+    bw.slots = p.cpw / 2;
+    bw.llr = p.llr;
+    bw.out_bits = p.out_bits;
+    bw.out_iters = p.out_iters;
+    bw.out_ok = p.out_ok;
+    bw.out_llr = static_cast<int8_t *>(p.out_llr);
+    // this workgroup's message region: cpw / 2 pairs
+    const size_t region = (size_t)(p.cpw / 2) * p.E_pad * p.Z;  // pair words
+    bw.msg = reinterpret_cast<uint16_t *>(p.msg) + (size_t)blockIdx.x * region;
+    bw.msg_records = (uint32_t)(2 * region);
+    bw.row_pad = p.row_pad;
+    bw.E_pad = p.E_pad;
+    bw.groups = p.groups;
+    bw.wq = nullptr;
+    bw.w_iters = 0;
+    bw.w_stride = p.rows;
+    bw.rows = p.rows;
+    bw.n_cols = p.n_cols;
+    bw.kb = p.kb;
+    bw.Z = p.Z;
+    bw.E = p.E;
+    bw.max_iter = p.max_iter;
+    bw.early_exit = 1;
+    bw.beta = p.beta;
+    bw.offset = p.offset;
+    decode_refill<WMAX>(bw, smem, (crow_t)row_ptr, (cmeta_t)meta, p.counter, p.n_cw);
 }
 
 // Four waves per SIMD: a 768-lane workgroup whose pairs fill the LDS runs
@@ -882,6 +1132,32 @@ hipError_t launch_placed(const DecodeLaunch &p, hipStream_t stream) {
     if (p.wmax <= 10) return launch_w<10, IN_LDS>(p, stream);
     if (p.wmax <= 20) return launch_w<20, IN_LDS>(p, stream);
     return launch_w<32, IN_LDS>(p, stream);
+}
+
+__global__ void reset_counter_kernel(unsigned *counter);
+
+template <int WMAX>
+hipError_t launch_refill_w(const DecodeLaunch &p, hipStream_t stream) {
+    const int pairs = p.cpw / 2;
+    const int lds = pairs * lds_bytes_i8_pair_post(p.n_cols, p.Z) + lds_flags_bytes_i8(pairs);
+    static std::once_flag attr_once;
+    std::call_once(attr_once, [] {
+        const hipError_t e = hipFuncSetAttribute(
+            reinterpret_cast<const void *>(&decode_i8_refill_kernel<WMAX>),
+            hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes());
+        if (e != hipSuccess) note_hip_error("hipFuncSetAttribute(decode_i8_refill_kernel)", e);
+    });
+    if (p.cpw < 2 || (p.cpw & 1) || pairs * p.Z > 768 || p.grid < 1 || !p.counter || !p.msg) {
+        note_hip_error("decode_i8_refill_kernel: bad launch shape", hipErrorInvalidValue);
+        return hipErrorInvalidValue;
+    }
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, stream, p.counter);
+    hipLaunchKernelGGL((decode_i8_refill_kernel<WMAX>), dim3(p.grid), dim3(pairs * p.Z), lds,
+                       stream, p, p.row_ptr, p.meta);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) note_hip_error("launch decode_i8_refill_kernel", e);
+    return e;
 }
 
 // Persistent mixed-shape decode: each workgroup takes tasks (up to a
@@ -1318,18 +1594,9 @@ __device__ __forceinline__ void decode_block_ll(const BlockWork &bw, uint8_t *sm
         __builtin_amdgcn_make_buffer_rsrc(bw.msg, 0, bw.msg_records, 0x00020000);
 
     if (a == 0 && validA) {
-        Lw[u] = 0;
-        Lw[Z + u] = 0;
         const int8_t *qa = bw.llr + (size_t)(2 * p) * T;
-        const int8_t *qb = bw.llr + (size_t)(2 * p + 1) * T;
-#pragma unroll 1
-        for (int c = 2; c < N; ++c) {
-            int va = qa[(c - 2) * Z + u];
-            int vb = validB ? qb[(c - 2) * Z + u] : 0;
-            va = va < -127 ? -127 : va;
-            vb = vb < -127 ? -127 : vb;
-            Lw[c * Z + u] = (uint16_t)((va & 0xFF) | ((vb & 0xFF) << 8));
-        }
+        const int8_t *qb = validB ? bw.llr + (size_t)(2 * p + 1) * T : qa;
+        load_pair_llrs(Lw, qa, true, qb, validB, N, Z, u);
     }
     __syncthreads();
 
@@ -1444,6 +1711,11 @@ hipError_t launch_ll(const DecodeLaunch &p, hipStream_t stream) {
 hipError_t launch_decode_i8(const DecodeLaunch &p, hipStream_t stream) {
     if (p.alpha == 2) return p.wmax <= 10 ? launch_ll<10, 2>(p, stream) : launch_ll<20, 2>(p, stream);
     if (p.alpha == 4) return p.wmax <= 10 ? launch_ll<10, 4>(p, stream) : launch_ll<20, 4>(p, stream);
+    if (p.refill) {
+        if (p.wmax <= 10) return launch_refill_w<10>(p, stream);
+        if (p.wmax <= 20) return launch_refill_w<20>(p, stream);
+        return launch_refill_w<32>(p, stream);
+    }
     return p.msg ? launch_placed<false>(p, stream) : launch_placed<true>(p, stream);
 }
 

@@ -145,7 +145,7 @@ int pow2_bucket(int n) {
 }
 
 int prepare_decode(const ldpc_args *a0, bool upload, DecodeLaunch &p, bool &msg_in_lds,
-                   size_t &msg_bytes) {
+                   size_t &msg_bytes, bool allow_refill = false) {
     if (!a0) return LDPC_EINVAL;
     // an int8 call with every launch knob at its default takes the tuned
     // configuration of its shape and batch size, if ldpc_tune recorded one
@@ -168,7 +168,9 @@ int prepare_decode(const ldpc_args *a0, bool upload, DecodeLaunch &p, bool &msg_
         (a->wq && a->wq_iters < 1) || (a->wh && a->wh_iters < 1) || a->cw_per_block < 0 ||
         a->msg_placement < LDPC_MSG_AUTO || a->msg_placement > LDPC_MSG_DEVICE ||
         (a->lanes_per_row != 0 && a->lanes_per_row != 1 && a->lanes_per_row != 2 &&
-         a->lanes_per_row != 4))
+         a->lanes_per_row != 4) ||
+        (a->schedule != LDPC_SCHED_AUTO && a->schedule != LDPC_SCHED_STATIC) ||
+        a->max_workgroups < 0)
         return LDPC_EINVAL;
     g_msg[0] = '\0';
     int lds_cap = 0;
@@ -244,14 +246,15 @@ int prepare_decode(const ldpc_args *a0, bool upload, DecodeLaunch &p, bool &msg_
         // Codewords go in pairs of Z lanes. Message placement: LDS when two
         // pairs' full state fits a CU, else device memory so that several
         // pairs share a CU.
-        const int full = lds_bytes_i8_pair(p.n_cols, p.E, p.Z) + 8;
+        // per pair: its LDS state plus its four flag / index words
+        const int full = lds_bytes_i8_pair(p.n_cols, p.E, p.Z) + 16;
         if (a->msg_placement == LDPC_MSG_LDS)
             msg_in_lds = true;
         else if (a->msg_placement == LDPC_MSG_DEVICE)
             msg_in_lds = false;
         else
             msg_in_lds = 2 * full + 8 <= lds_cap;
-        const int per_pair = msg_in_lds ? full : lds_bytes_i8_pair_post(p.n_cols, p.Z) + 8;
+        const int per_pair = msg_in_lds ? full : lds_bytes_i8_pair_post(p.n_cols, p.Z) + 16;
         int pairs = (a->cw_per_block + 1) / 2;
         // Default: about 256 lanes per workgroup with the whole state in LDS,
         // else about 768 (two pairs per workgroup at the largest lift, one
@@ -288,6 +291,29 @@ int prepare_decode(const ldpc_args *a0, bool upload, DecodeLaunch &p, bool &msg_
     msg_bytes = msg_in_lds ? 0
                 : i8 ? (((size_t)a->n_cw + 1) / 2) * p.E_pad * p.Z * 2 + kMsgTail
                      : (size_t)a->n_cw * p.E_pad * Zh * 4;
+    // Persistent schedule: as many workgroups as run at once (LDS-bound:
+    // one 768-lane workgroup per CU at the largest lifts), each with a
+    // message region for its own pairs, then the codeword counter.
+    p.refill = 0;
+    p.grid = 0;
+    p.counter = nullptr;
+    if (allow_refill && i8 && p.alpha == 1 && !msg_in_lds && a->early_exit && !a->wq &&
+        a->cw_per_block == 0 && a->schedule == LDPC_SCHED_AUTO) {
+        const int pairs = cpw / 2;
+        const int lds = pairs * lds_bytes_i8_pair_post(p.n_cols, p.Z) + lds_flags_bytes_i8(pairs);
+        const int waves = (pairs * p.Z + 63) / 64;
+        int dev = 0, cus = 1;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        // four waves per SIMD at most (the kernel's register budget)
+        const int per_cu = std::max(1, std::min(lds_cap / std::max(lds, 1), 16 / waves));
+        long grid = std::min<long>(((long)a->n_cw + cpw - 1) / cpw, (long)std::max(cus, 1) * per_cu);
+        if (a->max_workgroups > 0) grid = std::min<long>(grid, a->max_workgroups);
+        const size_t region = (size_t)pairs * p.E_pad * p.Z * 2;  // bytes
+        p.refill = 1;
+        p.grid = (int)grid;
+        msg_bytes = (((size_t)grid * region + kMsgTail + 255) & ~(size_t)255) + 256;
+    }
     return LDPC_OK;
 }
 
@@ -460,7 +486,7 @@ int ldpc_decode_ex(const ldpc_args *a) {
     DecodeLaunch p{};
     bool msg_in_lds = false;
     size_t msg_bytes = 0;
-    int rc = prepare_decode(a, true, p, msg_in_lds, msg_bytes);
+    int rc = prepare_decode(a, true, p, msg_in_lds, msg_bytes, true);
     if (rc != LDPC_OK) return rc;
     hipStream_t stream = static_cast<hipStream_t>(a->stream);
     const bool i8 = a->precision == LDPC_I8;
@@ -470,6 +496,9 @@ int ldpc_decode_ex(const ldpc_args *a) {
         p.msg_bytes = msg_bytes;
         e = hipMallocAsync(&msg, msg_bytes, stream);
         if (e != hipSuccess) return hip_fail(e, "hipMallocAsync(messages)");
+        // the persistent schedule's codeword counter: the last 256 bytes
+        if (p.refill)
+            p.counter = reinterpret_cast<unsigned *>(static_cast<uint8_t *>(msg) + msg_bytes - 256);
     }
     p.msg = static_cast<uint32_t *>(msg);
     e = i8 ? launch_decode_i8(p, stream) : launch_decode_f16(p, stream);
@@ -516,7 +545,9 @@ int ldpc_tune(const ldpc_args *a, ldpc_tuning *out) {
         g_tuned.erase(std::make_tuple(a->bg, a->Z, a->rows, pow2_bucket(a->n_cw),
                                       a->early_exit ? 1 : 0));
     }
-    std::vector<Tuned> cand;
+    // first the library's default launch (the persistent schedule where it
+    // applies): if it wins, nothing is recorded
+    std::vector<Tuned> cand{Tuned{0, 0, LDPC_MSG_AUTO}};
     for (int pairs : {1, 2, 3, 4, 6, 8, 12, 16, 24, 48}) {
         cand.push_back(Tuned{1, 2 * pairs, LDPC_MSG_LDS});
         cand.push_back(Tuned{1, 2 * pairs, LDPC_MSG_DEVICE});
@@ -544,9 +575,9 @@ int ldpc_tune(const ldpc_args *a, ldpc_tuning *out) {
         DecodeLaunch probe{};
         bool in_lds = false;
         size_t mb = 0;
-        if (prepare_decode(&t, true, probe, in_lds, mb) != LDPC_OK) continue;  // does not apply
+        if (prepare_decode(&t, true, probe, in_lds, mb, true) != LDPC_OK) continue;  // does not apply
         // the library rounds the packing to what fits: skip duplicates
-        if (probe.cpw != c.cw_per_block) continue;
+        if (c.cw_per_block != 0 && probe.cpw != c.cw_per_block) continue;
         float ms = 1e30f;
         for (int rep = 0; rep < 4 && rc == LDPC_OK; ++rep) {
             (void)hipEventRecord(e0, stream);
@@ -568,15 +599,24 @@ int ldpc_tune(const ldpc_args *a, ldpc_tuning *out) {
     (void)hipEventDestroy(e1);
     if (rc != LDPC_OK) return rc;
     if (tried == 0) return LDPC_EINVAL;
-    {
+    const bool is_default = pick.cw_per_block == 0;
+    int schedule = LDPC_SCHED_STATIC;
+    if (is_default) {
+        DecodeLaunch probe{};
+        bool in_lds = false;
+        size_t mb = 0;
+        if (prepare_decode(a, true, probe, in_lds, mb, true) == LDPC_OK && probe.refill)
+            schedule = LDPC_SCHED_AUTO;
+    } else {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tuned[std::make_tuple(a->bg, a->Z, a->rows, pow2_bucket(a->n_cw),
                                 a->early_exit ? 1 : 0)] = pick;
     }
     if (out) {
-        out->lanes_per_row = pick.lanes_per_row;
+        out->lanes_per_row = pick.lanes_per_row > 0 ? pick.lanes_per_row : 1;
         out->cw_per_block = pick.cw_per_block;
         out->msg_placement = pick.msg_placement;
+        out->schedule = schedule;
         out->ms = best;
         out->candidates = tried;
     }

@@ -67,6 +67,12 @@ struct DecodeLaunch {
     int wmax;                 // max row weight over the kept rows
     uint64_t groups;          // int8: bit r set = row r starts a new layer
                               // group (see layer_groups)
+    int refill;               // int8: persistent schedule (see
+                              // decode_i8_refill_kernel): `grid` workgroups,
+                              // each with a msg region of cpw / 2 pairs,
+                              // taking codewords from *counter
+    int grid;
+    unsigned *counter;        // refill: codewords handed out (reset per launch)
 };
 
 // A workgroup's share of an int8 decode: n codewords of one shape held as
@@ -166,7 +172,7 @@ struct ServeLaunch {
 // LDS bytes and message pair words of a serving workgroup (kBatchLanes
 // lanes): enough for floor(kBatchLanes / Z) codeword pairs of any shape with
 // up to 68 columns, 46 rows and row weights up to 20.
-constexpr int kServeLds = 52736;
+constexpr int kServeLds = 53248;
 constexpr int kServeMsgPerBlock = kBatchLanes * 46 * 20;
 hipError_t launch_serve(const ServeLaunch &s, hipStream_t stream);
 
@@ -209,7 +215,10 @@ __host__ __device__ inline int lds_bytes_i8_pair(int n_cols, int E, int Z) {
 __host__ __device__ inline int lds_bytes_i8_pair_post(int n_cols, int Z) { return 2 * n_cols * Z; }
 // The int8 workgroup's flag words after its pairs: one syndrome flag per
 // codeword and one workgroup-wide "all finished" word (plus padding).
-__host__ __device__ inline int lds_flags_bytes_i8(int pairs) { return 4 * (2 * pairs + 2); }
+// LDS words after the pairs' posteriors: per codeword a failing-check flag,
+// one workgroup flag, one spare word, and (refill schedule) per codeword the
+// index of the codeword it holds.
+__host__ __device__ inline int lds_flags_bytes_i8(int pairs) { return 4 * (4 * pairs + 2); }
 __host__ __device__ inline int lds_bytes_f16(int n_cols, int Z) { return n_cols * Z * 2; }
 
 // Layer groups: consecutive block rows that share no block column read and

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libldpc.so")
 LDPC_I8 = 0
 LDPC_F16 = 1
 MSG_PLACEMENT = {"auto": 0, "lds": 1, "device": 2}
+SCHEDULE = {"auto": 0, "static": 1}
 _ERRORS = {-1: "invalid argument", -2: "out of memory", -3: "HIP runtime error",
            -4: "no graph registered for (bg, Z)"}
 
@@ -39,14 +40,15 @@ class Args(ctypes.Structure):
         ("out_bits", ctypes.c_void_p), ("out_iters", ctypes.c_void_p),
         ("out_ok", ctypes.c_void_p), ("out_llr", ctypes.c_void_p),
         ("cw_per_block", ctypes.c_int), ("msg_placement", ctypes.c_int),
-        ("lanes_per_row", ctypes.c_int), ("stream", ctypes.c_void_p),
+        ("lanes_per_row", ctypes.c_int), ("schedule", ctypes.c_int),
+        ("max_workgroups", ctypes.c_int), ("stream", ctypes.c_void_p),
     ]
 
 
 class Tuning(ctypes.Structure):
     _fields_ = [("lanes_per_row", ctypes.c_int), ("cw_per_block", ctypes.c_int),
-                ("msg_placement", ctypes.c_int), ("ms", ctypes.c_float),
-                ("candidates", ctypes.c_int)]
+                ("msg_placement", ctypes.c_int), ("schedule", ctypes.c_int),
+                ("ms", ctypes.c_float), ("candidates", ctypes.c_int)]
 
 
 class Job(ctypes.Structure):
@@ -193,7 +195,8 @@ def decode_into(llr, bg: int, Z: int, rows: int, out_bits, out_iters, *, max_ite
                 precision: str = "i8", early_exit: bool = True, beta: float | None = None,
                 offset: float = 0, weights=None, out_ok=None, out_llr=None,
                 cw_per_block: int = 0, msg_placement: str = "auto", stream=None,
-                noalloc: bool = False, lanes_per_row: int = 0, tune: bool = False):
+                noalloc: bool = False, lanes_per_row: int = 0, tune: bool = False,
+                schedule: str = "auto", max_workgroups: int = 0):
     """Decode int8 LLRs [n_cw, T] (device tensor) into preallocated outputs.
 
     ``noalloc``: call ldpc_decode_noalloc (messages in the library's static
@@ -250,12 +253,17 @@ def decode_into(llr, bg: int, Z: int, rows: int, out_bits, out_iters, *, max_ite
     a.cw_per_block = cw_per_block
     a.msg_placement = MSG_PLACEMENT[msg_placement]
     a.lanes_per_row = lanes_per_row
+    if schedule not in SCHEDULE:
+        raise ValueError("schedule must be 'auto' or 'static'")
+    a.schedule = SCHEDULE[schedule]
+    a.max_workgroups = max_workgroups
     a.stream = _stream_ptr(stream)
     if tune:
         t = Tuning()
         _check(lib().ldpc_tune(ctypes.byref(a), ctypes.byref(t)), "ldpc_tune")
         return {"lanes_per_row": t.lanes_per_row, "cw_per_block": t.cw_per_block,
                 "msg_placement": {v: k for k, v in MSG_PLACEMENT.items()}[t.msg_placement],
+                "schedule": "auto" if t.schedule == 0 else "static",
                 "ms": t.ms, "candidates": t.candidates}
     if noalloc:
         _check(lib().ldpc_decode_noalloc(ctypes.byref(a)), "ldpc_decode_noalloc")
@@ -267,7 +275,7 @@ def decode(llr, bg: int, Z: int, rows: int, *, max_iter: int = 10, precision: st
            early_exit: bool = True, beta: float | None = None, offset: float = 0, weights=None,
            want_ok: bool = True, want_llr: bool = False, cw_per_block: int = 0,
            msg_placement: str = "auto", stream=None, noalloc: bool = False,
-           lanes_per_row: int = 0):
+           lanes_per_row: int = 0, schedule: str = "auto", max_workgroups: int = 0):
     """Allocate outputs with torch on llr's device and decode (through
     ldpc_decode_noalloc when ``noalloc``; the outputs are still allocated
     here, by torch).
@@ -290,7 +298,8 @@ def decode(llr, bg: int, Z: int, rows: int, *, max_iter: int = 10, precision: st
     decode_into(llr, bg, Z, rows, bits, iters, max_iter=max_iter, precision=precision,
                 early_exit=early_exit, beta=beta, offset=offset, weights=weights, out_ok=ok,
                 out_llr=out, cw_per_block=cw_per_block, msg_placement=msg_placement,
-                stream=stream, noalloc=noalloc, lanes_per_row=lanes_per_row)
+                stream=stream, noalloc=noalloc, lanes_per_row=lanes_per_row,
+                schedule=schedule, max_workgroups=max_workgroups)
     return bits, iters, (ok.bool() if ok is not None else None), out
 
 
