@@ -205,7 +205,9 @@ void ldpc_args_init(ldpc_args *a);
 
 /* ldpc_decode_ex -- decode with the options of ldpc_args. Messages kept in
  * device memory take 2*ceil(n_cw/2)*E_pad*Z bytes (int8; E_pad = E with
- * every row's weight rounded up to even) or 2*n_cw*Rd*Z bytes (binary16,
+ * every row's weight rounded up to even; under the persistent schedule
+ * 2*G*P*E_pad*Z bytes plus at most 528 for G workgroups of P pairs, G at
+ * most the workgroups that run at once) or 2*n_cw*Rd*Z bytes (binary16,
  * where every row's messages are stored exactly as a record of a1, a2 and
  * per-block sign and argmin flags: Rd = the sum over rows of 3 dwords for
  * rows of up to 8 blocks, 4 up to 16, 6 up to 32), allocated per call with
@@ -221,6 +223,8 @@ int ldpc_decode_ex(const ldpc_args *a);
  * LDPC_NOALLOC_SCRATCH_BYTES (64 MiB, part of the library's code object,
  * held on every device the library runs on until the process ends) instead
  * of a per-call allocation. No device or host memory is allocated or freed.
+ *   - Always the static schedule (one fixed block of codewords per
+ *     workgroup).
  *   - Limit: the message bytes of ldpc_decode_ex (int8:
  *     2*ceil(n_cw/2)*E_pad*Z + 16 unless the messages are placed in LDS,
  *     more with lanes_per_row > 1; binary16: 2*n_cw*Rd*Z) must not exceed
