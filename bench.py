@@ -125,8 +125,9 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(codewords are independent; see the sharding note in DESIGN.md)",
+        print("bench.py measures one GPU: the decoder has no multi-GPU path "
+              "(codewords are independent, so a batch would shard by codeword ranges "
+              "with no communication between GPUs)",
               file=sys.stderr)
         sys.exit(2)
 
