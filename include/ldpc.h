@@ -178,16 +178,17 @@ typedef struct ldpc_args {
                                pairs per workgroup (default: the fewest pairs
                                that give whole waves); else LDPC_EINVAL.
                                Results are identical for every alpha. */
-    int schedule;           /* int8 with early exit, one lane per row,
-                               device-placed messages, plain normalisation
-                               and cw_per_block = 0: LDPC_SCHED_AUTO (0, the
-                               default) = persistent workgroups, as many as
-                               run at once, whose codeword pairs take the
-                               next codeword as soon as one of theirs
-                               finishes; LDPC_SCHED_STATIC (1) = one fixed
-                               block of codewords per workgroup (always the
-                               case outside those conditions). Results are
-                               identical under both. */
+    int schedule;           /* LDPC_SCHED_STATIC (0, the default) = one
+                               fixed block of codewords per workgroup;
+                               LDPC_SCHED_PERSISTENT (1) = as many
+                               workgroups as run at once, whose codeword
+                               pairs take the next codeword as soon as one
+                               of theirs finishes (int8 with early exit, one
+                               lane per row, device-placed messages, plain
+                               normalisation and cw_per_block = 0, else
+                               LDPC_EINVAL; message memory for the resident
+                               workgroups only). Results are identical under
+                               both. */
     int max_workgroups;     /* persistent schedule: at most this many
                                workgroups (0 = as many as fit the device) */
     void *stream;
@@ -196,8 +197,8 @@ typedef struct ldpc_args {
 #define LDPC_MSG_AUTO 0
 #define LDPC_MSG_LDS 1
 #define LDPC_MSG_DEVICE 2
-#define LDPC_SCHED_AUTO 0
-#define LDPC_SCHED_STATIC 1
+#define LDPC_SCHED_STATIC 0
+#define LDPC_SCHED_PERSISTENT 1
 
 /* Fill `a` with the defaults above (beta 3/4, no offset, early exit on,
  * int8, 10 iterations, no optional outputs). */
@@ -248,9 +249,9 @@ int ldpc_decode_noalloc(const ldpc_args *a);
  * ldpc_tune -- autotuning of the int8 launch configuration. Times the
  * candidate configurations of ldpc_decode_ex on the arguments in `a` (their
  * launch knobs lanes_per_row, cw_per_block and msg_placement must be at
- * their defaults 0, 0, AUTO): the library's default launch (the persistent
- * schedule where it applies; if it is fastest nothing is recorded and
- * out->cw_per_block is 0), one lane per check row with 1, 2, 3, 4, 6, 8,
+ * their defaults 0, 0, AUTO, and schedule static): the library's default
+ * launch (if it is fastest nothing is recorded and out->cw_per_block is
+ * 0), the persistent schedule where it applies, one lane per check row with 1, 2, 3, 4, 6, 8,
  * 12, 16, 24 or 48 codeword pairs per workgroup (those that fit) and the
  * messages in LDS or in device memory, and 2 or
  * 4 lanes per check row with the fewest pairs that give whole waves and
@@ -265,7 +266,7 @@ int ldpc_decode_noalloc(const ldpc_args *a);
  */
 typedef struct ldpc_tuning {
     int lanes_per_row, cw_per_block, msg_placement;
-    int schedule; /* LDPC_SCHED_AUTO: the persistent schedule won */
+    int schedule; /* LDPC_SCHED_PERSISTENT: the persistent schedule won */
     float ms;
     int candidates;
 } ldpc_tuning;

@@ -762,54 +762,45 @@ __device__ __forceinline__ void layer_pass(const BlockWork &bw, uint8_t *smem, u
     }
 }
 
-// Channel LLRs of a pair's two codewords into its pair words (low byte
-// qa's codeword, high byte qb's; columns 0 and 1 are punctured and start at
-// zero), clamped at -127. Eight columns' loads are issued before any of
-// them is used: a loop that waits for each load in turn would spend the
-// memory latency once per column, tens of microseconds per workgroup. A
-// missing codeword (has = false) reads the other pointer's bytes, which
-// are then replaced by zero, so the loads need no branch.
-__device__ inline void load_pair_llrs(uint16_t *Lw, const int8_t *qa, bool hasA,
-                                      const int8_t *qb, bool hasB, int N, int Z, uint32_t u) {
-    Lw[u] = 0;
-    Lw[Z + u] = 0;
+// One codeword's channel LLRs into one half of a pair's words (half 0: the
+// low bytes, codeword 2p; half 1: the high bytes), clamped at -127, with
+// the punctured columns 0 and 1 at zero; q == nullptr (no codeword) writes
+// zeros. The pair's Z lanes read the codeword's (N - 2) Z bytes as
+// consecutive dwords (lane u takes dwords u, u + Z, u + 2Z, ...: every load
+// coalesced, KB of a lane's loads in flight together) and scatter the
+// bytes to their pair words: LLR byte j is variable 2Z + j, LDS byte
+// 2 (2Z + j) + half. KB trades registers for round trips: a whole codeword
+// (up to 17 dwords per lane) is one round trip.
+template <int KB>
+__device__ inline void load_half_llrs(uint8_t *Lpair, int half, const int8_t *q, int N, int Z,
+                                      uint32_t u) {
+    constexpr int kMaxK = (68 - 2 + 3) / 4 + 1;  // dwords per lane for up to 68 columns
+    uint8_t *Lh = Lpair + half;
+    Lh[2 * u] = 0;
+    Lh[2 * (Z + (int)u)] = 0;
+    const int nd = (N - 2) * Z / 4;  // Z is a multiple of 8
+    const uint32_t *q32 = reinterpret_cast<const uint32_t *>(q);
 #pragma unroll 1
-    for (int c0 = 2; c0 < N; c0 += 8) {
-        int va[8], vb[8];
+    for (int k0 = 0; k0 < kMaxK; k0 += KB) {
+        if (k0 * Z >= nd) break;
+        uint32_t v[KB];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int c = c0 + k < N ? c0 + k : N - 1;
-            va[k] = qa[(c - 2) * Z + u];
-            vb[k] = qb[(c - 2) * Z + u];
+        for (int k = 0; k < KB; ++k) {
+            const int idx = (k0 + k) * Z + (int)u;
+            v[k] = q ? q32[idx < nd ? idx : nd - 1] : 0u;
         }
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            if (c0 + k < N) {
-                const int a = hasA ? (va[k] < -127 ? -127 : va[k]) : 0;
-                const int b = hasB ? (vb[k] < -127 ? -127 : vb[k]) : 0;
-                Lw[(c0 + k) * Z + u] = (uint16_t)((a & 0xFF) | ((b & 0xFF) << 8));
+        for (int k = 0; k < KB; ++k) {
+            const int idx = (k0 + k) * Z + (int)u;
+            if (idx < nd) {
+                uint8_t *dst = Lh + 2 * (2 * Z + 4 * idx);
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int x = (int)(int8_t)(v[k] >> (8 * b));
+                    dst[2 * b] = (uint8_t)(x < -127 ? -127 : x);
+                }
             }
         }
-    }
-}
-
-// One codeword's channel LLRs into one half of a pair's words: Lb is the
-// byte of this lane's column-0 word that holds the half (pair words are
-// 2 bytes, so column c's byte is at Lb + 2 c Z). Loads batched as above.
-__device__ inline void load_half_llrs(uint8_t *Lb, const int8_t *q, int N, int Z, uint32_t u) {
-    Lb[0] = 0;
-    Lb[2 * Z] = 0;
-#pragma unroll 1
-    for (int c0 = 2; c0 < N; c0 += 8) {
-        int v[8];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int c = c0 + k < N ? c0 + k : N - 1;
-            v[k] = q[(c - 2) * Z + u];
-        }
-#pragma unroll
-        for (int k = 0; k < 8; ++k)
-            if (c0 + k < N) Lb[2 * (c0 + k) * Z] = (uint8_t)(v[k] < -127 ? -127 : v[k]);
     }
 }
 
@@ -853,9 +844,8 @@ __device__ __forceinline__ void decode_block(const BlockWork &bw, uint8_t *smem,
     // Initialisation: the pair's channel LLRs (punctured columns 0 and 1
     // carry none).
     if (validA) {
-        const int8_t *qa = bw.llr + (size_t)(2 * p) * T;
-        const int8_t *qb = validB ? bw.llr + (size_t)(2 * p + 1) * T : qa;
-        load_pair_llrs(Lw, qa, true, qb, validB, N, Z, u);
+        load_half_llrs<17>(Lp, 0, bw.llr + (size_t)(2 * p) * T, N, Z, u);
+        load_half_llrs<17>(Lp, 1, validB ? bw.llr + (size_t)(2 * p + 1) * T : nullptr, N, Z, u);
     }
     block_sync<WAVE>();
 
@@ -946,8 +936,8 @@ __device__ __forceinline__ void decode_refill(const BlockWork &bw, uint8_t *smem
     }
     __syncthreads();
     int idA = held[2 * p], idB = held[2 * p + 1];
-    load_pair_llrs(Lw, bw.llr + (size_t)(idA >= 0 ? idA : 0) * T, idA >= 0,
-                   bw.llr + (size_t)(idB >= 0 ? idB : 0) * T, idB >= 0, N, Z, u);
+    load_half_llrs<4>(Lp, 0, idA >= 0 ? bw.llr + (size_t)idA * T : nullptr, N, Z, u);
+    load_half_llrs<4>(Lp, 1, idB >= 0 ? bw.llr + (size_t)idB * T : nullptr, N, Z, u);
     __syncthreads();
 
     const u16x2 off16 = {(unsigned short)(bw.offset << 8), (unsigned short)(bw.offset << 8)};
@@ -993,8 +983,9 @@ __device__ __forceinline__ void decode_refill(const BlockWork &bw, uint8_t *smem
         const bool freshA = finA && nA >= 0, freshB = finB && nB >= 0;
         if (freshA || freshB) {
             // the new codewords' channel LLRs over their bytes of the pair words
-            if (freshA) load_half_llrs(Lp + 2 * u, bw.llr + (size_t)nA * T, N, Z, u);
-            if (freshB) load_half_llrs(Lp + 2 * u + 1, bw.llr + (size_t)nB * T, N, Z, u);
+            // (four dwords at a time: the round's state is still live)
+            if (freshA) load_half_llrs<4>(Lp, 0, bw.llr + (size_t)nA * T, N, Z, u);
+            if (freshB) load_half_llrs<4>(Lp, 1, bw.llr + (size_t)nB * T, N, Z, u);
             // the fresh halves' bytes of the messages this lane loads in
             // the next round (those of the codewords before) read as zero
             rkeep = (freshA ? 0xFF00FF00u : 0xFFFFFFFFu) & (freshB ? 0x00FF00FFu : 0xFFFFFFFFu);
@@ -1594,9 +1585,8 @@ __device__ __forceinline__ void decode_block_ll(const BlockWork &bw, uint8_t *sm
         __builtin_amdgcn_make_buffer_rsrc(bw.msg, 0, bw.msg_records, 0x00020000);
 
     if (a == 0 && validA) {
-        const int8_t *qa = bw.llr + (size_t)(2 * p) * T;
-        const int8_t *qb = validB ? bw.llr + (size_t)(2 * p + 1) * T : qa;
-        load_pair_llrs(Lw, qa, true, qb, validB, N, Z, u);
+        load_half_llrs<17>(Lp, 0, bw.llr + (size_t)(2 * p) * T, N, Z, u);
+        load_half_llrs<17>(Lp, 1, validB ? bw.llr + (size_t)(2 * p + 1) * T : nullptr, N, Z, u);
     }
     __syncthreads();
 

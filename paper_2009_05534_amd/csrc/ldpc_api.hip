@@ -133,7 +133,7 @@ int sub_sizes(const HostGraph &g, int rows, int *K, int *T, int *Nc, int *E) {
 // Launch configurations chosen by ldpc_tune, per (bg, Z, rows, n_cw rounded
 // up to a power of two, early exit).
 struct Tuned {
-    int lanes_per_row, cw_per_block, msg_placement;
+    int lanes_per_row, cw_per_block, msg_placement, schedule;
 };
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int, int, int>, Tuned> g_tuned;
@@ -151,7 +151,8 @@ int prepare_decode(const ldpc_args *a0, bool upload, DecodeLaunch &p, bool &msg_
     // configuration of its shape and batch size, if ldpc_tune recorded one
     ldpc_args ar = *a0;
     if (ar.precision == LDPC_I8 && ar.lanes_per_row == 0 && ar.cw_per_block == 0 &&
-        ar.msg_placement == LDPC_MSG_AUTO) {
+        ar.msg_placement == LDPC_MSG_AUTO && ar.schedule == LDPC_SCHED_STATIC &&
+        ar.max_workgroups == 0) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tuned.find(std::make_tuple(ar.bg, ar.Z, ar.rows, pow2_bucket(ar.n_cw),
                                                ar.early_exit ? 1 : 0));
@@ -159,6 +160,7 @@ int prepare_decode(const ldpc_args *a0, bool upload, DecodeLaunch &p, bool &msg_
             ar.lanes_per_row = it->second.lanes_per_row;
             ar.cw_per_block = it->second.cw_per_block;
             ar.msg_placement = it->second.msg_placement;
+            ar.schedule = it->second.schedule;
         }
     }
     const ldpc_args *a = &ar;
@@ -169,7 +171,7 @@ int prepare_decode(const ldpc_args *a0, bool upload, DecodeLaunch &p, bool &msg_
         a->msg_placement < LDPC_MSG_AUTO || a->msg_placement > LDPC_MSG_DEVICE ||
         (a->lanes_per_row != 0 && a->lanes_per_row != 1 && a->lanes_per_row != 2 &&
          a->lanes_per_row != 4) ||
-        (a->schedule != LDPC_SCHED_AUTO && a->schedule != LDPC_SCHED_STATIC) ||
+        (a->schedule != LDPC_SCHED_STATIC && a->schedule != LDPC_SCHED_PERSISTENT) ||
         a->max_workgroups < 0)
         return LDPC_EINVAL;
     g_msg[0] = '\0';
@@ -252,8 +254,8 @@ int prepare_decode(const ldpc_args *a0, bool upload, DecodeLaunch &p, bool &msg_
             msg_in_lds = true;
         else if (a->msg_placement == LDPC_MSG_DEVICE)
             msg_in_lds = false;
-        else
-            msg_in_lds = 2 * full + 8 <= lds_cap;
+        else  // the persistent schedule places messages in device memory
+            msg_in_lds = a->schedule != LDPC_SCHED_PERSISTENT && 2 * full + 8 <= lds_cap;
         const int per_pair = msg_in_lds ? full : lds_bytes_i8_pair_post(p.n_cols, p.Z) + 16;
         int pairs = (a->cw_per_block + 1) / 2;
         // Default: about 256 lanes per workgroup with the whole state in LDS,
@@ -297,8 +299,15 @@ int prepare_decode(const ldpc_args *a0, bool upload, DecodeLaunch &p, bool &msg_
     p.refill = 0;
     p.grid = 0;
     p.counter = nullptr;
-    if (allow_refill && i8 && p.alpha == 1 && !msg_in_lds && a->early_exit && !a->wq &&
-        a->cw_per_block == 0 && a->schedule == LDPC_SCHED_AUTO) {
+    if (a->schedule == LDPC_SCHED_PERSISTENT) {
+        if (!allow_refill || !i8 || p.alpha != 1 || msg_in_lds || !a->early_exit || a->wq ||
+            a->cw_per_block != 0) {
+            snprintf(g_msg, sizeof(g_msg),
+                     "the persistent schedule needs int8 with early exit, one lane per row, "
+                     "device-placed messages, plain normalisation and the default packing "
+                     "(and is not available to ldpc_decode_noalloc)");
+            return LDPC_EINVAL;
+        }
         const int pairs = cpw / 2;
         const int lds = pairs * lds_bytes_i8_pair_post(p.n_cols, p.Z) + lds_flags_bytes_i8(pairs);
         const int waves = (pairs * p.Z + 63) / 64;
@@ -536,7 +545,8 @@ int ldpc_decode_noalloc(const ldpc_args *a) {
 
 int ldpc_tune(const ldpc_args *a, ldpc_tuning *out) {
     if (!a || a->precision != LDPC_I8 || a->lanes_per_row != 0 || a->cw_per_block != 0 ||
-        a->msg_placement != LDPC_MSG_AUTO)
+        a->msg_placement != LDPC_MSG_AUTO || a->schedule != LDPC_SCHED_STATIC ||
+        a->max_workgroups != 0)
         return LDPC_EINVAL;
     {
         // forget an earlier choice for this key, so the candidates below
@@ -545,17 +555,18 @@ int ldpc_tune(const ldpc_args *a, ldpc_tuning *out) {
         g_tuned.erase(std::make_tuple(a->bg, a->Z, a->rows, pow2_bucket(a->n_cw),
                                       a->early_exit ? 1 : 0));
     }
-    // first the library's default launch (the persistent schedule where it
-    // applies): if it wins, nothing is recorded
-    std::vector<Tuned> cand{Tuned{0, 0, LDPC_MSG_AUTO}};
+    // first the library's default launch: if it wins, nothing is recorded
+    std::vector<Tuned> cand{Tuned{0, 0, LDPC_MSG_AUTO, LDPC_SCHED_STATIC},
+                            Tuned{1, 0, LDPC_MSG_AUTO, LDPC_SCHED_PERSISTENT}};
     for (int pairs : {1, 2, 3, 4, 6, 8, 12, 16, 24, 48}) {
-        cand.push_back(Tuned{1, 2 * pairs, LDPC_MSG_LDS});
-        cand.push_back(Tuned{1, 2 * pairs, LDPC_MSG_DEVICE});
+        cand.push_back(Tuned{1, 2 * pairs, LDPC_MSG_LDS, LDPC_SCHED_STATIC});
+        cand.push_back(Tuned{1, 2 * pairs, LDPC_MSG_DEVICE, LDPC_SCHED_STATIC});
     }
     for (int alpha : {2, 4}) {
         int base = 1;
         while ((base * a->Z) % 64 != 0) ++base;
-        for (int k : {1, 2}) cand.push_back(Tuned{alpha, 2 * base * k, LDPC_MSG_DEVICE});
+        for (int k : {1, 2})
+            cand.push_back(Tuned{alpha, 2 * base * k, LDPC_MSG_DEVICE, LDPC_SCHED_STATIC});
     }
     hipStream_t stream = static_cast<hipStream_t>(a->stream);
     hipEvent_t e0, e1;
@@ -565,13 +576,14 @@ int ldpc_tune(const ldpc_args *a, ldpc_tuning *out) {
         return LDPC_EHIP;
     }
     float best = 1e30f;
-    Tuned pick{0, 0, LDPC_MSG_AUTO};
+    Tuned pick{0, 0, LDPC_MSG_AUTO, LDPC_SCHED_STATIC};
     int tried = 0, rc = LDPC_OK;
     for (const Tuned &c : cand) {
         ldpc_args t = *a;
         t.lanes_per_row = c.lanes_per_row;
         t.cw_per_block = c.cw_per_block;
         t.msg_placement = c.msg_placement;
+        t.schedule = c.schedule;
         DecodeLaunch probe{};
         bool in_lds = false;
         size_t mb = 0;
@@ -599,15 +611,8 @@ int ldpc_tune(const ldpc_args *a, ldpc_tuning *out) {
     (void)hipEventDestroy(e1);
     if (rc != LDPC_OK) return rc;
     if (tried == 0) return LDPC_EINVAL;
-    const bool is_default = pick.cw_per_block == 0;
-    int schedule = LDPC_SCHED_STATIC;
-    if (is_default) {
-        DecodeLaunch probe{};
-        bool in_lds = false;
-        size_t mb = 0;
-        if (prepare_decode(a, true, probe, in_lds, mb, true) == LDPC_OK && probe.refill)
-            schedule = LDPC_SCHED_AUTO;
-    } else {
+    const bool is_default = pick.lanes_per_row == 0;
+    if (!is_default) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tuned[std::make_tuple(a->bg, a->Z, a->rows, pow2_bucket(a->n_cw),
                                 a->early_exit ? 1 : 0)] = pick;
@@ -616,7 +621,7 @@ int ldpc_tune(const ldpc_args *a, ldpc_tuning *out) {
         out->lanes_per_row = pick.lanes_per_row > 0 ? pick.lanes_per_row : 1;
         out->cw_per_block = pick.cw_per_block;
         out->msg_placement = pick.msg_placement;
-        out->schedule = schedule;
+        out->schedule = pick.schedule;
         out->ms = best;
         out->candidates = tried;
     }

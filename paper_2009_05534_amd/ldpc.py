@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libldpc.so")
 LDPC_I8 = 0
 LDPC_F16 = 1
 MSG_PLACEMENT = {"auto": 0, "lds": 1, "device": 2}
-SCHEDULE = {"auto": 0, "static": 1}
+SCHEDULE = {"static": 0, "persistent": 1}
 _ERRORS = {-1: "invalid argument", -2: "out of memory", -3: "HIP runtime error",
            -4: "no graph registered for (bg, Z)"}
 
@@ -196,7 +196,7 @@ def decode_into(llr, bg: int, Z: int, rows: int, out_bits, out_iters, *, max_ite
                 offset: float = 0, weights=None, out_ok=None, out_llr=None,
                 cw_per_block: int = 0, msg_placement: str = "auto", stream=None,
                 noalloc: bool = False, lanes_per_row: int = 0, tune: bool = False,
-                schedule: str = "auto", max_workgroups: int = 0):
+                schedule: str = "static", max_workgroups: int = 0):
     """Decode int8 LLRs [n_cw, T] (device tensor) into preallocated outputs.
 
     ``noalloc``: call ldpc_decode_noalloc (messages in the library's static
@@ -254,7 +254,7 @@ def decode_into(llr, bg: int, Z: int, rows: int, out_bits, out_iters, *, max_ite
     a.msg_placement = MSG_PLACEMENT[msg_placement]
     a.lanes_per_row = lanes_per_row
     if schedule not in SCHEDULE:
-        raise ValueError("schedule must be 'auto' or 'static'")
+        raise ValueError("schedule must be 'static' or 'persistent'")
     a.schedule = SCHEDULE[schedule]
     a.max_workgroups = max_workgroups
     a.stream = _stream_ptr(stream)
@@ -263,7 +263,7 @@ def decode_into(llr, bg: int, Z: int, rows: int, out_bits, out_iters, *, max_ite
         _check(lib().ldpc_tune(ctypes.byref(a), ctypes.byref(t)), "ldpc_tune")
         return {"lanes_per_row": t.lanes_per_row, "cw_per_block": t.cw_per_block,
                 "msg_placement": {v: k for k, v in MSG_PLACEMENT.items()}[t.msg_placement],
-                "schedule": "auto" if t.schedule == 0 else "static",
+                "schedule": "persistent" if t.schedule == 1 else "static",
                 "ms": t.ms, "candidates": t.candidates}
     if noalloc:
         _check(lib().ldpc_decode_noalloc(ctypes.byref(a)), "ldpc_decode_noalloc")
@@ -275,7 +275,7 @@ def decode(llr, bg: int, Z: int, rows: int, *, max_iter: int = 10, precision: st
            early_exit: bool = True, beta: float | None = None, offset: float = 0, weights=None,
            want_ok: bool = True, want_llr: bool = False, cw_per_block: int = 0,
            msg_placement: str = "auto", stream=None, noalloc: bool = False,
-           lanes_per_row: int = 0, schedule: str = "auto", max_workgroups: int = 0):
+           lanes_per_row: int = 0, schedule: str = "static", max_workgroups: int = 0):
     """Allocate outputs with torch on llr's device and decode (through
     ldpc_decode_noalloc when ``noalloc``; the outputs are still allocated
     here, by torch).

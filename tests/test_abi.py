@@ -164,7 +164,7 @@ def test_tune_and_server_refusals_without_a_gpu(lib):
     from paper_2009_05534_amd import ldpc
     L = ldpc.lib()
     for field, value in (("precision", 1), ("lanes_per_row", 2), ("cw_per_block", 2),
-                         ("msg_placement", 1)):
+                         ("msg_placement", 1), ("schedule", 1), ("max_workgroups", 4)):
         a = ldpc.Args()
         L.ldpc_args_init(ctypes.byref(a))
         a.bg, a.Z, a.rows, a.n_cw = 1, 384, 46, 4

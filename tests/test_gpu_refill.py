@@ -1,5 +1,6 @@
-"""The persistent int8 schedule (codeword pairs take the next codeword as
-soon as one of theirs finishes) against the CPU oracle, through the C ABI:
+"""The persistent int8 schedule (opt-in: codeword pairs take the next
+codeword as soon as one of theirs finishes) against the CPU oracle, through
+the C ABI:
 few workgroups over many codewords, so that every half of every pair is
 refilled several times with codewords that need different iteration
 counts; bit-exact hard decisions, posteriors, iteration counts and flags,
@@ -36,7 +37,7 @@ def test_refill_equals_oracle(bg, Z, rows, n, mw, ebn0):
     g = _graph(bg, Z, rows)
     b = make_batch(g, n, ebn0, data_seed=500 + Z + rows)
     print(f"[refill] bg={bg} Z={Z} rows={rows} n={n} workgroups<={mw}", flush=True)
-    got = gpu_decode(bg, Z, rows, b.q, msg_placement="device", max_workgroups=mw)
+    got = gpu_decode(bg, Z, rows, b.q, schedule="persistent", max_workgroups=mw)
     ref = oracle_i8(g, b.q)
     assert len(set(ref[1].tolist())) > 1  # codewords finish at different iterations
     assert_i8_equal(got, ref)
@@ -51,40 +52,42 @@ def test_refill_equals_oracle(bg, Z, rows, n, mw, ebn0):
 def test_refill_options(opts):
     g = _graph(1, 64, 30)
     b = make_batch(g, 90, 1.25, data_seed=17)
-    got = gpu_decode(1, 64, 30, b.q, msg_placement="device", max_workgroups=1, **opts)
+    got = gpu_decode(1, 64, 30, b.q, schedule="persistent", max_workgroups=1, **opts)
     assert_i8_equal(got, oracle_i8(g, b.q, **opts))
 
 
 def test_refill_equals_static_full_grid():
     g = _graph(1, 384, 46)
     b = make_batch(g, 700, 1.75, data_seed=31)
-    a = gpu_decode(1, 384, 46, b.q)
-    s = gpu_decode(1, 384, 46, b.q, schedule="static")
+    a = gpu_decode(1, 384, 46, b.q, schedule="persistent")
+    s = gpu_decode(1, 384, 46, b.q)
     assert_i8_equal(a, s)
     idx = np.random.default_rng(7).choice(700, 16, replace=False)
     assert_i8_equal(tuple(x[idx] for x in a), oracle_i8(g, b.q[idx]))
 
 
-def test_refill_small_and_weighted():
-    # fewer codewords than one workgroup holds; per-row weights take the
-    # static schedule (results equal either way)
+def test_refill_small_batches():
+    # fewer codewords than one workgroup holds
     g = _graph(2, 96, 42)
     for n in (1, 3):
         b = make_batch(g, n, 1.5, data_seed=40 + n)
-        assert_i8_equal(gpu_decode(2, 96, 42, b.q, msg_placement="device", max_workgroups=1),
+        assert_i8_equal(gpu_decode(2, 96, 42, b.q, schedule="persistent", max_workgroups=1),
                         oracle_i8(g, b.q))
-    b = make_batch(g, 30, 1.5, data_seed=44)
-    w = np.random.default_rng(3).integers(40, 120, (4, 42)).astype(np.uint8)
-    assert_i8_equal(gpu_decode(2, 96, 42, b.q, weights=w, msg_placement="device",
-                               max_workgroups=1),
-                    oracle_i8(g, b.q, weights=w))
 
 
 def test_schedule_refusals():
     from paper_2009_05534_amd import ldpc
     g = _graph(1, 64, 30)
     q = make_batch(g, 4, 1.5, data_seed=45).q
-    with pytest.raises(ldpc.LdpcError):
-        gpu_decode(1, 64, 30, q, max_workgroups=-1)
+    w = np.full((2, 30), 96, np.uint8)
+    for kw in (dict(max_workgroups=-1),
+               dict(schedule="persistent", msg_placement="lds"),
+               dict(schedule="persistent", early_exit=False),
+               dict(schedule="persistent", weights=w),
+               dict(schedule="persistent", cw_per_block=4),
+               dict(schedule="persistent", lanes_per_row=2),
+               dict(schedule="persistent", noalloc=True)):
+        with pytest.raises(ldpc.LdpcError):
+            gpu_decode(1, 64, 30, q, **kw)
     with pytest.raises(ValueError):
         gpu_decode(1, 64, 30, q, schedule="dynamic")

@@ -1,7 +1,7 @@
 """ldpc_tune: the launch-configuration autotuner times the int8 candidates
-(lanes per check row, codeword pairs per workgroup, message placement) on a
-shape and batch size, and later default-knob calls of that shape take the
-fastest. Every candidate and the tuned default call give the oracle's
+(lanes per check row, codeword pairs per workgroup, message placement,
+schedule) on a shape and batch size, and later default-knob calls of that
+shape take the fastest. Every candidate and the tuned default call give the oracle's
 results bit for bit."""
 import numpy as np
 import pytest
@@ -38,7 +38,8 @@ def test_tune_then_default_equals_oracle(bg, Z, rows, n):
     torch.cuda.synchronize()
     assert choice["candidates"] >= 2 and choice["ms"] > 0, choice
     assert choice["lanes_per_row"] in (1, 2, 4), choice
-    assert choice["msg_placement"] in ("lds", "device"), choice
+    assert choice["schedule"] in ("static", "persistent"), choice
+    assert choice["msg_placement"] in ("auto", "lds", "device"), choice
     ref = oracle_i8(g, b.q)
     # the tuner's own outputs (those of its last candidate)
     assert_i8_equal((bits.cpu().numpy(), iters.cpu().numpy(), ok.cpu().numpy()),
@@ -47,7 +48,7 @@ def test_tune_then_default_equals_oracle(bg, Z, rows, n):
     assert_i8_equal(gpu_decode(bg, Z, rows, b.q), ref)
     # and the chosen knobs spelled out give the same
     kw = dict(lanes_per_row=choice["lanes_per_row"], cw_per_block=choice["cw_per_block"],
-              msg_placement=choice["msg_placement"])
+              msg_placement=choice["msg_placement"], schedule=choice["schedule"])
     assert_i8_equal(gpu_decode(bg, Z, rows, b.q, **kw), ref)
 
 
@@ -58,6 +59,6 @@ def test_tune_refusals():
     bits = torch.zeros((4, (g.K + 7) // 8), dtype=torch.uint8, device="cuda")
     iters = torch.zeros(4, dtype=torch.int32, device="cuda")
     for kw in (dict(cw_per_block=2), dict(lanes_per_row=2), dict(msg_placement="lds"),
-               dict(precision="f16")):
+               dict(precision="f16"), dict(schedule="persistent"), dict(max_workgroups=2)):
         with pytest.raises(ldpc.LdpcError):
             ldpc.decode_into(q, 1, 64, 30, bits, iters, tune=True, **kw)
