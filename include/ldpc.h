@@ -115,7 +115,9 @@ int ldpc_graph_digest(int bg, int Z, uint64_t *out);
  *   n_cw        : number of codewords (>= 1)
  *   llr_in      : int8 [n_cw][T], channel LLRs of the transmitted bits in
  *                 variable order (punctured columns absent), LLR units of
- *                 1/4 (any value is legal; -128 is read as -127)
+ *                 1/4 (any value is legal; -128 is read as -127); 4-byte
+ *                 aligned (the kernels read it as 32-bit words), else
+ *                 LDPC_EINVAL
  *   max_iter    : 1..64 iterations
  *   out_bits    : uint8 [n_cw][K/8] hard decisions of the K information
  *                 bits (including the punctured ones), packed LSB first
@@ -133,7 +135,7 @@ typedef struct ldpc_args {
     int max_iter;           /* 1..64 */
     int early_exit;         /* 1: stop a codeword once all its checks hold;
                                0: run max_iter iterations (out_ok still set) */
-    const int8_t *llr_in;   /* int8 [n_cw][T] (both precisions) */
+    const int8_t *llr_in;   /* int8 [n_cw][T] (both precisions), 4-byte aligned */
     /* Normalisation of the min-sum magnitude (§III correction factor):
      *   i8  : a = min((w*max(m - offset_q, 0) + 64) >> 7, 127), w = beta_q
      *         or wq[min(t, wq_iters) - 1][r] (Q1.7, 0..255) when wq != NULL
@@ -274,7 +276,8 @@ int ldpc_tune(const ldpc_args *a, ldpc_tuning *out);
 
 /*
  * Mixed-shape batches. A job is a set of codewords of one shape (bg, Z,
- * rows) with its own device buffers: llr int8 [n_cw][T], out_bits
+ * rows) with its own device buffers: llr int8 [n_cw][T] (4-byte aligned,
+ * else LDPC_EINVAL), out_bits
  * [n_cw][K/8], out_iters int32 [n_cw], out_ok uint8 [n_cw] or NULL, and
  * optional per-(iteration, row) Q1.7 weights wq [wq_iters][rows] (NULL:
  * beta = 3/4). All of a batch's jobs are decoded by ONE persistent launch of

@@ -349,6 +349,47 @@ __device__ inline void syndrome_mark(const uint32_t *__restrict__ Lw,
     }
 }
 
+// A codeword's channel LLRs into its posterior words (punctured columns 0
+// and 1 carry none). The lanes read consecutive dwords (lane u: dwords
+// u, u + Zh, u + 2Zh, ...), KB loads in flight per lane, so the whole
+// codeword costs a couple of memory round trips. Dword k*Zh + u starts at
+// byte 2k*Z + 4u: column 2 + 2k (+1 once 4u >= Z), variable 4u mod Z, and
+// its four bytes (Z is a multiple of 8) share one column and one half of
+// the pair words. Each byte, clamped to -127, becomes a binary16 half.
+template <int KB>
+__device__ inline void load_llrs_f16(uint32_t *Lw, const int8_t *q, int N, int Z, int u) {
+    const int Zh = Z >> 1;
+    Lw[u] = 0;
+    Lw[Zh + u] = 0;
+    const int nd = (N - 2) * Z / 4;
+    const int kmax = (N - 1) / 2;  // ceil((N - 2) / 2) dwords per lane at most
+    const int cu = 4 * u >= Z ? 1 : 0, v = 4 * u - cu * Z, hi = v >= Zh ? 1 : 0;
+    // binary16 slot of this lane's first byte; +2 per byte, +4*Zh per k
+    uint16_t *dst0 = reinterpret_cast<uint16_t *>(Lw) + 2 * ((2 + cu) * Zh + v - hi * Zh) + hi;
+    const uint32_t *q32 = reinterpret_cast<const uint32_t *>(q);
+#pragma unroll 1
+    for (int k0 = 0; k0 < kmax; k0 += KB) {
+        uint32_t d[KB];
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+            const int idx = (k0 + k) * Zh + u;
+            d[k] = q32[idx < nd ? idx : nd - 1];
+        }
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+            if ((k0 + k) * Zh + u < nd) {
+                uint16_t *dst = dst0 + 4 * Zh * (k0 + k);
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    int x = (int)(int8_t)(d[k] >> (8 * b));
+                    x = x < -127 ? -127 : x;
+                    dst[2 * b] = __builtin_bit_cast(uint16_t, (_Float16)x);
+                }
+            }
+        }
+    }
+}
+
 template <int WMAX>
 __global__ __launch_bounds__(512) void decode_f16_kernel(DecodeLaunch p,
                                                          const int32_t *__restrict__ row_ptr,
@@ -370,19 +411,7 @@ __global__ __launch_bounds__(512) void decode_f16_kernel(DecodeLaunch p,
     const int ro = slot * p.E_pad * Zh + u;
     (void)E;
 
-    if (valid) {
-        Lw[u] = 0;
-        Lw[Zh + u] = 0;
-        const int8_t *q = p.llr + (size_t)cw * T;
-#pragma unroll 8
-        for (int c = 2; c < N; ++c) {
-            int lo = q[(c - 2) * Z + u], hi = q[(c - 2) * Z + u + Zh];
-            lo = lo < -127 ? -127 : lo;
-            hi = hi < -127 ? -127 : hi;
-            const h16x2 v = {(_Float16)lo, (_Float16)hi};
-            Lw[c * Zh + u] = bits_of(v);
-        }
-    }
+    if (valid) load_llrs_f16<17>(Lw, p.llr + (size_t)cw * T, N, Z, u);
     __syncthreads();
 
     const uint32_t off = (uint32_t)(p.offset & 0xFFFF) * 0x00010001u;

@@ -165,6 +165,7 @@ int prepare_decode(const ldpc_args *a0, bool upload, DecodeLaunch &p, bool &msg_
     }
     const ldpc_args *a = &ar;
     if ( a->n_cw < 1 || a->max_iter < 1 || a->max_iter > LDPC_MAX_ITER || !a->llr_in ||
+        (reinterpret_cast<uintptr_t>(a->llr_in) & 3u) != 0 ||
         !a->out_bits || !a->out_iters || (a->precision != LDPC_I8 && a->precision != LDPC_F16) ||
         a->beta_q < 0 || a->beta_q > 255 || a->offset_q < 0 || a->offset_q > 127 ||
         (a->wq && a->wq_iters < 1) || (a->wh && a->wh_iters < 1) || a->cw_per_block < 0 ||
@@ -701,7 +702,8 @@ int batch_jobs(const ldpc_job *jobs, int n_jobs, std::vector<BatchJob> &bj,
         if (it == g_graphs.end()) return LDPC_ENOGRAPH;
         const HostGraph &g = it->second;
         int E = 0;
-        if (jb.n_cw < 1 || !jb.llr || !jb.out_bits || !jb.out_iters || g.Z > kBatchLanes ||
+        if (jb.n_cw < 1 || !jb.llr || (reinterpret_cast<uintptr_t>(jb.llr) & 3u) != 0 ||
+            !jb.out_bits || !jb.out_iters || g.Z > kBatchLanes ||
             (jb.wq && jb.wq_iters < 1) ||
             sub_sizes(g, jb.rows, nullptr, nullptr, nullptr, &E) != LDPC_OK)
             return LDPC_EINVAL;

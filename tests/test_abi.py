@@ -81,6 +81,14 @@ def test_decode_rejects_bad_arguments_before_launch(lib):
     a.rows = 47
     assert lib_.ldpc_decode_ex(ctypes.byref(a)) == -1
     a.rows = 46
+    a.llr_in = 17  # the LLRs are read as 32-bit words: 4-byte alignment
+    assert lib_.ldpc_decode_ex(ctypes.byref(a)) == -1
+    a.llr_in = 16
+    job = ldpc.Job(bg=1, Z=384, rows=46, n_cw=1, llr=17, out_bits=16, out_iters=16)
+    nb = ctypes.c_size_t()
+    assert lib_.ldpc_decode_batch_bytes(ctypes.byref(job), 1, ctypes.byref(nb)) == -1
+    job.llr = 16  # passes the checks (without a GPU the device tables then fail)
+    assert lib_.ldpc_decode_batch_bytes(ctypes.byref(job), 1, ctypes.byref(nb)) in (0, -3)
     a.bg = 7
     assert lib_.ldpc_decode_ex(ctypes.byref(a)) == -4
     assert lib_.ldpc_strerror(-4) == b"no graph registered for (bg, Z)"
