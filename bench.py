@@ -290,19 +290,19 @@ def main():
         # single-codeword latency per iteration (fixed 10 iterations), with
         # one lane per check row and with the low-latency mapping (alpha
         # lanes per check row), at Z = 384 and Z = 128
-        def one_cw_us_per_iter(bg, Zx, rows, q1, alpha, precision="i8"):
+        def one_cw_us_per_iter(bg, Zx, rows, q1, alpha, precision="i8", pairing="auto"):
             b1 = torch.empty((1, bg_k(bg) * Zx // 8), dtype=torch.uint8, device=dev)
             i1 = torch.empty(1, dtype=torch.int32, device=dev)
             for _ in range(3):
                 ldpc.decode_into(q1, bg, Zx, rows, b1, i1, max_iter=10, early_exit=False,
-                                 lanes_per_row=alpha, precision=precision)
+                                 lanes_per_row=alpha, precision=precision, pairing=pairing)
             torch.cuda.synchronize()
             ts = []
             for _ in range(50):
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 e0.record(stream)
                 ldpc.decode_into(q1, bg, Zx, rows, b1, i1, max_iter=10, early_exit=False,
-                                 lanes_per_row=alpha, precision=precision)
+                                 lanes_per_row=alpha, precision=precision, pairing=pairing)
                 e1.record(stream)
                 e1.synchronize()
                 ts.append(e0.elapsed_time(e1))
@@ -312,17 +312,25 @@ def main():
             return 22 if bg == 1 else 10
 
         one = llr[4][:1].contiguous()
-        lat1 = {str(al): one_cw_us_per_iter(BG, Z, ROWS, one, al) for al in (1, 2)}
+        # one lane per row: check rows u and u + Z/2 of the codeword per lane
+        # (the default for one codeword at lifts above 256) and codeword
+        # pairs (the codeword in one half of every lane)
+        lat1 = {"1": one_cw_us_per_iter(BG, Z, ROWS, one, 1, pairing="rows"),
+                "1_codeword_pairs": one_cw_us_per_iter(BG, Z, ROWS, one, 1, pairing="codewords"),
+                "2": one_cw_us_per_iter(BG, Z, ROWS, one, 2)}
         g128 = make_graph(BG, 128)
         ldpc.register(g128)
         q128 = torch.from_numpy(make_batch(g128, 1, EBN0_POINTS[4], data_seed=9).q).to(dev)
         lat128 = {str(al): one_cw_us_per_iter(BG, 128, ROWS, q128, al) for al in (1, 2, 4)}
+        lat128["1_row_pairs"] = one_cw_us_per_iter(BG, 128, ROWS, q128, 1, pairing="rows")
         result["latency_ms"]["single_codeword_us_per_iter_p50"] = min(lat1.values())
         # binary16: one codeword on Z/2 lanes (two check rows per lane)
         lat16 = {f"Z{Z}": one_cw_us_per_iter(BG, Z, ROWS, one, 0, "f16"),
                  "Z128": one_cw_us_per_iter(BG, 128, ROWS, q128, 0, "f16")}
         result["latency_ms"]["single_codeword_us_per_iter"] = {
-            "note": "one codeword, 10 iterations, p50 over 50 calls, by lanes per check row",
+            "note": "one codeword, 10 iterations, p50 over 50 calls, by lanes per check row "
+                    "(int8 '1': check rows u and u + Z/2 per lane at Z = 384, codeword pairs at "
+                    "Z = 128; '1_codeword_pairs' / '1_row_pairs': the other pairing)",
             f"Z{Z}": lat1, "Z128": lat128, "f16": lat16}
 
     if "batched" in extras:

@@ -193,6 +193,22 @@ typedef struct ldpc_args {
                                both. */
     int max_workgroups;     /* persistent schedule: at most this many
                                workgroups (0 = as many as fit the device) */
+    int pairing;            /* int8: what shares a lane's two 16-bit halves.
+                               LDPC_PAIR_CODEWORDS (1): two codewords (the
+                               same check row of each; Z lanes per pair).
+                               LDPC_PAIR_ROWS (2): check rows u and u + Z/2
+                               of one codeword (Z/2 lanes per codeword,
+                               cw_per_block codewords per workgroup, default
+                               1; the static schedule, one lane per row and
+                               device-placed messages, else LDPC_EINVAL): for
+                               small batches of large lifts, where a pair's
+                               2Z lanes would put two waves on some of a
+                               CU's SIMDs. LDPC_PAIR_AUTO (0, the default):
+                               row pairs when Z > 256, n_cw is at most the
+                               device's CU count, one lane per row, the
+                               static schedule, cw_per_block 0 and message
+                               placement AUTO; else codeword pairs.
+                               Results are identical under both. */
     void *stream;
 } ldpc_args;
 
@@ -201,6 +217,9 @@ typedef struct ldpc_args {
 #define LDPC_MSG_DEVICE 2
 #define LDPC_SCHED_STATIC 0
 #define LDPC_SCHED_PERSISTENT 1
+#define LDPC_PAIR_AUTO 0
+#define LDPC_PAIR_CODEWORDS 1
+#define LDPC_PAIR_ROWS 2
 
 /* Fill `a` with the defaults above (beta 3/4, no offset, early exit on,
  * int8, 10 iterations, no optional outputs). */
@@ -208,7 +227,8 @@ void ldpc_args_init(ldpc_args *a);
 
 /* ldpc_decode_ex -- decode with the options of ldpc_args. Messages kept in
  * device memory take 2*ceil(n_cw/2)*E_pad*Z bytes (int8; E_pad = E with
- * every row's weight rounded up to even; under the persistent schedule
+ * every row's weight rounded up to even; n_cw*E_pad*Z + 16 with row pairs;
+ * under the persistent schedule
  * 2*G*P*E_pad*Z bytes plus at most 528 for G workgroups of P pairs, G at
  * most the workgroups that run at once) or 2*n_cw*Rd*Z bytes (binary16,
  * where every row's messages are stored exactly as a record of a1, a2 and
@@ -250,14 +270,15 @@ int ldpc_decode_noalloc(const ldpc_args *a);
 /*
  * ldpc_tune -- autotuning of the int8 launch configuration. Times the
  * candidate configurations of ldpc_decode_ex on the arguments in `a` (their
- * launch knobs lanes_per_row, cw_per_block and msg_placement must be at
- * their defaults 0, 0, AUTO, and schedule static): the library's default
- * launch (if it is fastest nothing is recorded and out->cw_per_block is
- * 0), the persistent schedule where it applies, one lane per check row with 1, 2, 3, 4, 6, 8,
- * 12, 16, 24 or 48 codeword pairs per workgroup (those that fit) and the
- * messages in LDS or in device memory, and 2 or
- * 4 lanes per check row with the fewest pairs that give whole waves and
- * twice that. Every candidate decodes a's input into a's outputs (all give
+ * launch knobs lanes_per_row, cw_per_block, msg_placement and pairing must
+ * be at their defaults 0, 0, AUTO, AUTO, and schedule static): the
+ * library's default launch (if it is fastest nothing is recorded and
+ * out->cw_per_block is 0), the persistent schedule where it applies, one
+ * lane per check row with 1, 2, 3, 4, 6, 8, 12, 16, 24 or 48 codeword
+ * pairs per workgroup (those that fit) and the messages in LDS or in
+ * device memory, 2 or 4 lanes per check row with the fewest pairs that
+ * give whole waves and twice that, and row pairs with 1, 2 or 4 codewords
+ * per workgroup. Every candidate decodes a's input into a's outputs (all give
  * the same results), four times, and the fastest after the first is
  * recorded for (bg, Z, rows, n_cw rounded up to a power of two,
  * early_exit): later int8 ldpc_decode_ex / ldpc_decode_noalloc calls whose
@@ -269,6 +290,9 @@ int ldpc_decode_noalloc(const ldpc_args *a);
 typedef struct ldpc_tuning {
     int lanes_per_row, cw_per_block, msg_placement;
     int schedule; /* LDPC_SCHED_PERSISTENT: the persistent schedule won */
+    int pairing;  /* LDPC_PAIR_ROWS: row pairs won (cw_per_block codewords
+                     per workgroup); LDPC_PAIR_CODEWORDS: codeword pairs;
+                     AUTO: the default launch won */
     float ms;
     int candidates;
 } ldpc_tuning;

@@ -41,6 +41,8 @@ __device__ inline uint32_t bits_of(u16x2 v) { return __builtin_bit_cast(uint32_t
 // v_perm selectors (source bytes 0..3 = the word, 0x0c = zero byte).
 constexpr uint32_t kUnpack = 0x010c000cu;  // pair word -> (b0 << 8, b1 << 24)
 constexpr uint32_t kPack = 0x0c0c0301u;    // inverse of kUnpack
+constexpr uint32_t kUnpackSw = 0x000c010cu;  // pair word -> (b1 << 8, b0 << 24)
+constexpr uint32_t kPackSw = 0x0c0c0103u;    // inverse of kUnpackSw
 
 __device__ inline uint32_t perm(uint32_t word, uint32_t sel) {
     return __builtin_amdgcn_perm(0u, word, sel);
@@ -68,6 +70,22 @@ __device__ inline uint32_t gather(uint32_t md, uint32_t off, uint32_t lb, uint32
                                   uint32_t Z) {
     const uint32_t wrap = U >= md ? 2u * Z : 0u;
     return lb + off - wrap;
+}
+
+// Row-pair layout (one codeword; lane u of its Zh = Z/2 lanes owns check
+// rows u and u + Zh, the low and high halves of its packed registers; pair
+// word p of column c holds variables p (low byte) and p + Zh (high byte)).
+// Block metadata md = 2(c*Zh + s_lo) | s_hi << 15 | (Zh - s_lo) << 16 for
+// the shift s = s_lo + Zh*s_hi: the address is the pair kernel's gather
+// with Zh for Z and the offset in bits [0, 15), and the word's halves
+// arrive swapped (row u's variable in the high byte) when
+// [u + s_lo >= Zh] xor s_hi.
+__device__ inline bool rp_swapped(uint32_t md, uint32_t U) {
+    return (U >= md) != ((md & 0x8000u) != 0u);
+}
+template <bool RP>
+constexpr uint32_t off_mask() {
+    return RP ? 0x7FFFu : 0xFFFFu;
 }
 
 __device__ inline uint32_t lds_ld16(const uint8_t *smem, uint32_t a) {
@@ -238,19 +256,29 @@ constexpr uint32_t kPack2 = 0x07050301u;     // (R_k, R_k+1) -> pair words k, k+
 // Variable-to-check messages of blocks K0..K1-1 of the row from the
 // check-to-variable message dwords rd (already loaded), the posterior reads
 // issued first, then x = sat(L - R), folded into m1 / m2 / S.
-template <int K0, int K1, bool KEEP_GATHER>
+// RP: the row-pair layout; each edge's unpack selector follows its swap,
+// and (KEEP_GATHER) ps keeps the matching pack selector for the write-back.
+template <int K0, int K1, bool KEEP_GATHER, bool RP = false>
 __device__ __forceinline__ void row_phase1(const uint8_t *__restrict__ smem, uint32_t lb,
                                            const uint32_t *rd, const uint32_t *md,
                                            const uint32_t *mo, uint32_t u,
                                            int Z, int wr, uint32_t *xv, uint32_t *axv,
-                                           uint32_t *la, u16x2 &m1, u16x2 &m2, uint32_t &S) {
+                                           uint32_t *la, uint32_t *ps, u16x2 &m1, u16x2 &m2,
+                                           uint32_t &S) {
     constexpr int n = K1 - K0;
-    uint32_t lraw[n];
+    uint32_t lraw[n], us[n];
 #pragma unroll
     for (int i = 0; i < n; ++i) {
         if (K0 + i < wr) {  // wr: the row's weight (below K1 in the generic path)
             const uint32_t a = gather(md[K0 + i], mo[K0 + i], lb, lane_key(u), (uint32_t)Z);
             if (KEEP_GATHER) la[K0 + i] = a;
+            if constexpr (RP) {
+                const bool sw = rp_swapped(md[K0 + i], lane_key(u));
+                us[i] = sw ? kUnpackSw : kUnpack;
+                if (KEEP_GATHER) ps[K0 + i] = sw ? kPackSw : kPack;
+            } else {
+                us[i] = kUnpack;
+            }
             lraw[i] = lds_ld16(smem, a);
         }
     }
@@ -261,7 +289,7 @@ __device__ __forceinline__ void row_phase1(const uint8_t *__restrict__ smem, uin
         s16x2 x[n];
 #pragma unroll
         for (int k = 0; k < n; ++k)
-            x[k] = __builtin_elementwise_sub_sat(as_s(perm(lraw[k], kUnpack)),
+            x[k] = __builtin_elementwise_sub_sat(as_s(perm(lraw[k], RP ? us[k] : kUnpack)),
                                                  as_s(perm(rd[k >> 1], (k & 1) ? kUnpackHi : kUnpack)));
 #pragma unroll
         for (int k = 0; k < n; ++k)
@@ -303,7 +331,7 @@ __device__ __forceinline__ void row_phase1(const uint8_t *__restrict__ smem, uin
     for (int i = 0; i < n; ++i) {
         const int k = K0 + i;
         if (k < wr) {
-            const s16x2 L = as_s(perm(lraw[i], kUnpack));
+            const s16x2 L = as_s(perm(lraw[i], RP ? us[i] : kUnpack));
             const s16x2 Rm = as_s(perm(rd[k >> 1], (k & 1) ? kUnpackHi : kUnpack));
             s16x2 x = __builtin_elementwise_sub_sat(L, Rm);
             x = __builtin_elementwise_max(x, (s16x2){-127 * 256, -127 * 256});
@@ -328,7 +356,8 @@ __device__ __forceinline__ void row_phase1(const uint8_t *__restrict__ smem, uin
 // register count low enough for several pairs per CU.
 // GEN: W is only an upper bound and wr the row's weight; blocks k >= wr are
 // skipped by scalar branches.
-template <int W, bool IN_LDS, bool FIRST, bool GEN = false>
+// RP: the row-pair layout (rows u and u + Zh of one codeword; Z is Zh).
+template <int W, bool IN_LDS, bool FIRST, bool GEN = false, bool RP = false>
 __device__ __forceinline__ void row_update_w(uint8_t *__restrict__ smem, uint32_t lb,
                                              const MsgRow<IN_LDS> &R, cmeta_t meta, int e0,
                                              uint32_t u, int Z, u16x2 wgt, u16x2 off16,
@@ -339,7 +368,7 @@ __device__ __forceinline__ void row_update_w(uint8_t *__restrict__ smem, uint32_
 #pragma unroll
     for (int k = 0; k < W; ++k) {
         md[k] = meta[e0 + k];  // the table is padded
-        mo[k] = md[k] & 0xFFFFu;
+        mo[k] = md[k] & off_mask<RP>();
     }
     // This row's check-to-variable messages (none in the first iteration).
     constexpr int ND = (W + 1) / 2;
@@ -362,18 +391,18 @@ __device__ __forceinline__ void row_update_w(uint8_t *__restrict__ smem, uint32_
             for (int j = 0; j < ND; ++j) rd[j] &= R.rmask;
         }
     }
-    uint32_t xv[W], axv[W], la[W];
+    uint32_t xv[W], axv[W], la[W], ps[RP ? W : 1];
     u16x2 m1 = {0x7FFF, 0x7FFF}, m2 = {0x7FFF, 0x7FFF};
     uint32_t S = 0;
     if constexpr (kWide) {
         constexpr int H = (W + 1) / 2;
-        row_phase1<0, H, false>(smem, lb, rd, md, mo, u, Z, wrow, xv, axv, la, m1, m2, S);
+        row_phase1<0, H, false, RP>(smem, lb, rd, md, mo, u, Z, wrow, xv, axv, la, ps, m1, m2, S);
         // keep the halves apart: the scheduler would otherwise issue every
         // read of the row up front and hold both halves' registers at once
         __builtin_amdgcn_sched_barrier(0);
-        row_phase1<H, W, false>(smem, lb, rd, md, mo, u, Z, wrow, xv, axv, la, m1, m2, S);
+        row_phase1<H, W, false, RP>(smem, lb, rd, md, mo, u, Z, wrow, xv, axv, la, ps, m1, m2, S);
     } else {
-        row_phase1<0, W, true>(smem, lb, rd, md, mo, u, Z, wrow, xv, axv, la, m1, m2, S);
+        row_phase1<0, W, true, RP>(smem, lb, rd, md, mo, u, Z, wrow, xv, axv, la, ps, m1, m2, S);
     }
     const u16x2 a1 = normalise(m1, off16, wgt);
     const u16x2 a2 = normalise(m2, off16, wgt);
@@ -405,7 +434,7 @@ __device__ __forceinline__ void row_update_w(uint8_t *__restrict__ smem, uint32_
             Lv[k] = __builtin_elementwise_max(__builtin_elementwise_add_sat(as_s(xv[k]), Rv[k]),
                                               (s16x2){-127 * 256, -127 * 256});
 #pragma unroll
-        for (int k = 0; k < W; ++k) lds_st16(smem, la[k], perm(bits_of(Lv[k]), kPack));
+        for (int k = 0; k < W; ++k) lds_st16(smem, la[k], perm(bits_of(Lv[k]), RP ? ps[k] : kPack));
 #pragma unroll
         for (int j = 0; j < ND; ++j)
             sd[j] = 2 * j + 1 < W ? __builtin_amdgcn_perm(bits_of(Rv[2 * j + 1]), bits_of(Rv[2 * j]), kPack2)
@@ -446,7 +475,10 @@ __device__ __forceinline__ void row_update_w(uint8_t *__restrict__ smem, uint32_
             if (k >= W || k >= wrow) continue;
             const uint32_t a =
                 kWide ? gather(md[k], mo[k], lb, lane_key(u), (uint32_t)Z) : la[k];
-            lds_st16(smem, a, perm(bits_of(Lg[i]), kPack));
+            uint32_t psel = kPack;
+            if constexpr (RP)
+                psel = kWide ? (rp_swapped(md[k], lane_key(u)) ? kPackSw : kPack) : ps[k];
+            lds_st16(smem, a, perm(bits_of(Lg[i]), psel));
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -480,36 +512,45 @@ __device__ __forceinline__ void row_update_w(uint8_t *__restrict__ smem, uint32_
 // Parity of check row u over a row of exactly W blocks for both codewords:
 // the XOR of the raw pair words, whose bits 7 and 15 are the hard decisions
 // [L_v < 0] of the two codewords.
-template <int W>
+// RP (row-pair layout): each word is unpacked in its lane's row order
+// first, so the hard decisions of rows u and u + Zh land in bits 15 and 31.
+template <int W, bool RP = false>
 __device__ __forceinline__ uint32_t row_parity_w(const uint8_t *__restrict__ smem, uint32_t lb,
                                                  cmeta_t meta, int e0, uint32_t u, int Z) {
     uint32_t md[W], mo[W], raw[W];
 #pragma unroll
     for (int k = 0; k < W; ++k) {
         md[k] = meta[e0 + k];
-        mo[k] = md[k] & 0xFFFFu;
+        mo[k] = md[k] & off_mask<RP>();
     }
 #pragma unroll
     for (int k = 0; k < W; ++k)
         raw[k] = lds_ld16(smem, gather(md[k], mo[k], lb, lane_key(u), (uint32_t)Z));
     uint32_t acc = 0;
 #pragma unroll
-    for (int k = 0; k < W; ++k) acc ^= raw[k];
+    for (int k = 0; k < W; ++k) {
+        if constexpr (RP)
+            acc ^= perm(raw[k], rp_swapped(md[k], lane_key(u)) ? kUnpackSw : kUnpack);
+        else
+            acc ^= raw[k];
+    }
     return acc;
 }
 
 // Scalar dispatch on the row weight w in [W, WMAX].
-template <int W, int WMAX, bool IN_LDS, bool FIRST>
+template <int W, int WMAX, bool IN_LDS, bool FIRST, bool RP = false>
 __device__ __forceinline__ void row_update(int w, uint8_t *smem, uint32_t lb,
                                            const MsgRow<IN_LDS> &R, cmeta_t meta, int e0,
                                            uint32_t u, int Z, u16x2 wgt, u16x2 off16,
                                            const uint32_t *pre) {
     if constexpr (W <= WMAX) {
         if (w == W) {
-            row_update_w<W, IN_LDS, FIRST>(smem, lb, R, meta, e0, u, Z, wgt, off16, pre);
+            row_update_w<W, IN_LDS, FIRST, false, RP>(smem, lb, R, meta, e0, u, Z, wgt, off16,
+                                                      pre);
             return;
         }
-        row_update<W + 1, WMAX, IN_LDS, FIRST>(w, smem, lb, R, meta, e0, u, Z, wgt, off16, pre);
+        row_update<W + 1, WMAX, IN_LDS, FIRST, RP>(w, smem, lb, R, meta, e0, u, Z, wgt, off16,
+                                                   pre);
     }
 }
 
@@ -517,31 +558,32 @@ __device__ __forceinline__ void row_update(int w, uint8_t *smem, uint32_t lb,
 // (and 19, the core rows of BG1-shaped graphs); other wide rows run through
 // one bound-WMAX body with scalar guards, which keeps the kernel's register
 // allocation to a few row shapes.
-template <int WMAX, bool IN_LDS, bool FIRST>
+template <int WMAX, bool IN_LDS, bool FIRST, bool RP = false>
 __device__ __forceinline__ void row_update_any(int w, uint8_t *smem, uint32_t lb,
                                                const MsgRow<IN_LDS> &R, cmeta_t meta, int e0,
                                                uint32_t u, int Z, u16x2 wgt, u16x2 off16,
                                                const uint32_t *pre) {
     if constexpr (WMAX <= 10) {
-        row_update<2, WMAX, IN_LDS, FIRST>(w, smem, lb, R, meta, e0, u, Z, wgt, off16, pre);
+        row_update<2, WMAX, IN_LDS, FIRST, RP>(w, smem, lb, R, meta, e0, u, Z, wgt, off16, pre);
     } else {
         constexpr int kCore = WMAX >= 19 ? 19 : WMAX;
         if (w <= 10)
-            row_update<2, 10, IN_LDS, FIRST>(w, smem, lb, R, meta, e0, u, Z, wgt, off16, pre);
+            row_update<2, 10, IN_LDS, FIRST, RP>(w, smem, lb, R, meta, e0, u, Z, wgt, off16, pre);
         else if (w == kCore)
-            row_update_w<kCore, IN_LDS, FIRST>(smem, lb, R, meta, e0, u, Z, wgt, off16, pre);
+            row_update_w<kCore, IN_LDS, FIRST, false, RP>(smem, lb, R, meta, e0, u, Z, wgt, off16,
+                                                          pre);
         else
-            row_update_w<WMAX, IN_LDS, FIRST, true>(smem, lb, R, meta, e0, u, Z, wgt, off16,
-                                                    pre, w);
+            row_update_w<WMAX, IN_LDS, FIRST, true, RP>(smem, lb, R, meta, e0, u, Z, wgt, off16,
+                                                        pre, w);
     }
 }
 
-template <int W, int WMAX>
+template <int W, int WMAX, bool RP = false>
 __device__ __forceinline__ uint32_t row_parity(int w, const uint8_t *smem, uint32_t lb,
                                                cmeta_t meta, int e0, uint32_t u, int Z) {
     if constexpr (W <= WMAX) {
-        if (w == W) return row_parity_w<W>(smem, lb, meta, e0, u, Z);
-        return row_parity<W + 1, WMAX>(w, smem, lb, meta, e0, u, Z);
+        if (w == W) return row_parity_w<W, RP>(smem, lb, meta, e0, u, Z);
+        return row_parity<W + 1, WMAX, RP>(w, smem, lb, meta, e0, u, Z);
     }
     return 0;
 }
@@ -553,14 +595,15 @@ __device__ __forceinline__ uint32_t row_parity(int w, const uint8_t *smem, uint3
 // the rows as soon as every codeword its lanes serve is decided (marked by
 // any wave) -- only codewords whose checks all hold need the full sweep,
 // which keeps the check cheap in the iterations before convergence.
-template <int WMAX>
+// RP: rows u and u + Zh of one codeword (needA), either failing marks fl[0].
+template <int WMAX, bool RP = false>
 __device__ __forceinline__ void syndrome_mark(const uint8_t *__restrict__ smem, uint32_t lb,
                                      crow_t row_ptr, cmeta_t meta, int rows, uint32_t u, int Z,
                                      volatile int *fl, bool needA, bool needB) {
     for (int r = 0; r < rows; ++r) {
         const int e0 = row_ptr[r], w = row_ptr[r + 1] - e0;
-        const uint32_t par = row_parity<2, WMAX>(w, smem, lb, meta, e0, u, Z);
-        if (needA && (par & 0x80u)) fl[0] = 1;
+        const uint32_t par = row_parity<2, WMAX, RP>(w, smem, lb, meta, e0, u, Z);
+        if (needA && (par & (RP ? 0x80008000u : 0x80u))) fl[0] = 1;
         if (needB && (par & 0x8000u)) fl[1] = 1;
         const bool open = (needA && fl[0] == 0) || (needB && fl[1] == 0);
         if (__ballot(open) == 0) break;
@@ -670,6 +713,82 @@ __device__ inline void write_outputs_ids(const BlockWork &bw, const uint8_t *Lp,
     }
 }
 
+// Row-pair layout: one codeword's channel LLRs into its pair words (word p
+// of column c: variable p in the low byte, p + Zh in the high byte; the
+// punctured columns 0 and 1 at zero), clamped at -127. The codeword's Zh
+// lanes read its (N - 2) Z bytes as consecutive dwords, lane u taking
+// dwords u, u + Zh, ...: dword k*Zh + u starts at byte 2k*Z + 4u, i.e.
+// column 2 + 2k (+1 once 4u >= Z), variable 4u mod Z, and its four bytes
+// (Z a multiple of 8) share one column and one half of the pair words, so
+// each lane's destinations are a fixed LDS byte plus 4*Zh per k and 2 per
+// byte.
+template <int KB>
+__device__ inline void load_rp_llrs(uint8_t *Lc, const int8_t *q, int N, int Z, uint32_t u) {
+    const int Zh = Z >> 1;
+    uint16_t *Lw = reinterpret_cast<uint16_t *>(Lc);
+    Lw[u] = 0;
+    Lw[Zh + (int)u] = 0;
+    const int nd = (N - 2) * Z / 4;
+    const int kmax = (N - 1) / 2;  // ceil((N - 2) / 2) dwords per lane at most
+    const int cu = 4 * (int)u >= Z ? 1 : 0, v = 4 * (int)u - cu * Z, hi = v >= Zh ? 1 : 0;
+    uint8_t *dst0 = Lc + 2 * ((2 + cu) * Zh + v - hi * Zh) + hi;
+    const uint32_t *q32 = reinterpret_cast<const uint32_t *>(q);
+#pragma unroll 1
+    for (int k0 = 0; k0 < kmax; k0 += KB) {
+        uint32_t d[KB];
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+            const int idx = (k0 + k) * Zh + (int)u;
+            d[k] = q32[idx < nd ? idx : nd - 1];
+        }
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+            if ((k0 + k) * Zh + (int)u < nd) {
+                uint8_t *dst = dst0 + 4 * Zh * (k0 + k);
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int x = (int)(int8_t)(d[k] >> (8 * b));
+                    dst[2 * b] = (uint8_t)(x < -127 ? -127 : x);
+                }
+            }
+        }
+    }
+}
+
+// Row-pair layout: outputs of codeword cw (index from bw's output bases)
+// from its pair words Lc; bw.Z is Zh. Same output formats as write_outputs.
+__device__ inline void write_outputs_rp(const BlockWork &bw, const uint8_t *Lc, int cw,
+                                        uint32_t u, int iters, int ok) {
+    int Zh = bw.Z;
+    __asm__ volatile("" : "+v"(cw), "+v"(u), "+s"(Zh));
+    const int Z = 2 * Zh, bpc = Z / 8, nbytes = bw.kb * bpc;
+#pragma unroll 1
+    for (int i = (int)u; i < nbytes; i += Zh) {
+        const int c = i / bpc, j = i - c * bpc;
+        uint32_t byte = 0;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const int v = 8 * j + b, hi = v >= Zh ? 1 : 0;
+            byte |= (uint32_t)(Lc[2 * (c * Zh + v - hi * Zh) + hi] >> 7) << b;
+        }
+        bw.out_bits[(size_t)cw * nbytes + i] = (uint8_t)byte;
+    }
+    if (u == 0) {
+        bw.out_iters[cw] = iters;
+        if (bw.out_ok) bw.out_ok[cw] = (uint8_t)ok;
+    }
+    if (bw.out_llr) {
+        const int Nc = bw.n_cols * Z;
+        const uint16_t *Lw = reinterpret_cast<const uint16_t *>(Lc);
+#pragma unroll 1
+        for (int c = 0; c < bw.n_cols; ++c) {
+            const uint16_t w = Lw[c * Zh + (int)u];
+            bw.out_llr[(size_t)cw * Nc + c * Z + u] = (int8_t)(w & 0xFF);
+            bw.out_llr[(size_t)cw * Nc + c * Z + u + Zh] = (int8_t)(w >> 8);
+        }
+    }
+}
+
 typedef const __attribute__((address_space(4))) uint32_t *cw32_t;
 
 // Synchronisation of the lanes that decode one block of work: the whole
@@ -715,7 +834,7 @@ __device__ inline MsgRow<IN_LDS> msg_row(uint8_t *smem, uint32_t ro,
 // barrier between layers that share a block column. wrow: this iteration's
 // per-row Q1.7 weights or null (bw.beta for every row). keep: whether the
 // check-to-variable messages are stored (not in the last iteration).
-template <int WMAX, bool IN_LDS, bool FIRST, bool WAVE>
+template <int WMAX, bool IN_LDS, bool FIRST, bool WAVE, bool RP = false>
 __device__ __forceinline__ void layer_pass(const BlockWork &bw, uint8_t *smem, uint32_t lb,
                                            uint32_t ro, __amdgpu_buffer_rsrc_t rsrc,
                                            crow_t row_ptr, cmeta_t meta, const uint8_t *wrow,
@@ -747,7 +866,8 @@ __device__ __forceinline__ void layer_pass(const BlockWork &bw, uint8_t *smem, u
         R.rmask_on = rmask_on;
         R.rmask = rmask;
         if (busy) {
-            row_update_any<WMAX, IN_LDS, FIRST>(w, smem, lb, R, meta, e0, u, Z, wgt, off16, pre);
+            row_update_any<WMAX, IN_LDS, FIRST, RP>(w, smem, lb, R, meta, e0, u, Z, wgt, off16,
+                                                    pre);
             // the next row's messages exist unless this is the first
             // iteration; after the last row, only if another iteration runs
             if (!IN_LDS && (last ? keep : !FIRST))
@@ -888,6 +1008,71 @@ __device__ __forceinline__ void decode_block(const BlockWork &bw, uint8_t *smem,
             if (!(doneA && doneB)) flags[2 * bw.slots] = 0;
             block_sync<WAVE>();
             if (flags[2 * bw.slots]) break;
+        }
+    }
+}
+
+// Row-pair decoding (§II: the Z check rows of a block row are independent):
+// codeword i of the workgroup's bw.n occupies lanes [i*Zh, (i+1)*Zh), Zh =
+// Z/2 = bw.Z, and lane u updates its check rows u and u + Zh as the two
+// halves of its packed registers, the same arithmetic as the pair kernel
+// (the pair kernel with Zh lanes, the row-pair metadata and per-edge
+// unpack / pack selectors). For small batches of large lifts: a pair's 2Z
+// lanes would put two waves on some SIMDs of a CU, where one codeword's Zh
+// lanes leave every wave a SIMD of its own. Device-placed messages,
+// [codeword][E_pad * Zh] pair words. Every thread of the workgroup must
+// call it; lanes past the last codeword only join the barriers.
+template <int WMAX>
+__device__ __forceinline__ void decode_rp(const BlockWork &bw, uint8_t *smem, crow_t row_ptr,
+                                          cmeta_t meta) {
+    static_assert(WMAX <= kMetaPad, "row metadata window exceeds the table padding");
+    const int Zh = bw.Z, Z = 2 * Zh;
+    const int N = bw.n_cols, T = (N - 2) * Z;
+    const int cw_bytes = lds_bytes_i8_pair_post(N, Zh);
+    const int tid = (int)threadIdx.x;
+    const int i = tid / Zh;
+    const uint32_t u = tid - i * Zh;
+    const bool valid = i < bw.n;
+    const int is = valid ? i : 0;  // keeps idle lanes' addresses in range
+    uint8_t *Lc = smem + is * cw_bytes;
+    const uint32_t lb = (uint32_t)(is * cw_bytes) + 2u * u;
+    const uint32_t ro = 2u * (uint32_t)(is * bw.E_pad * Zh);
+    int *flags = reinterpret_cast<int *>(smem + bw.slots * cw_bytes);
+    const __amdgpu_buffer_rsrc_t rsrc =
+        __builtin_amdgcn_make_buffer_rsrc(bw.msg, 0, bw.msg_records, 0x00020000);
+    if (valid) load_rp_llrs<17>(Lc, bw.llr + (size_t)i * T, N, Z, u);
+    __syncthreads();
+
+    const u16x2 off16 = {(unsigned short)(bw.offset << 8), (unsigned short)(bw.offset << 8)};
+    bool done = !valid;
+    uint32_t pre[kPreDwords] = {0u, 0u, 0u, 0u};
+    for (int t = 1; t <= bw.max_iter; ++t) {
+        const uint8_t *wrow = nullptr;
+        if (bw.wq) wrow = bw.wq + (size_t)((t < bw.w_iters ? t : bw.w_iters) - 1) * bw.w_stride;
+        const bool busy = !done;
+        if (t == 1)
+            layer_pass<WMAX, false, true, false, true>(bw, smem, lb, ro, rsrc, row_ptr, meta, wrow,
+                                                       u, busy, off16, pre, t < bw.max_iter);
+        else
+            layer_pass<WMAX, false, false, false, true>(bw, smem, lb, ro, rsrc, row_ptr, meta,
+                                                        wrow, u, busy, off16, pre,
+                                                        t < bw.max_iter);
+        if (bw.early_exit || t == bw.max_iter) {
+            // flags[0, slots): a failing check per codeword; flags[slots]:
+            // stays 1 while every codeword of the workgroup is finished
+            if (tid <= bw.slots) flags[tid] = tid == bw.slots;
+            __syncthreads();
+            if (busy)
+                syndrome_mark<WMAX, true>(smem, lb, row_ptr, meta, bw.rows, u, Zh, flags + i, true,
+                                          false);
+            __syncthreads();
+            const bool holds = flags[is] == 0;
+            const bool fin = !done && (t == bw.max_iter || holds);
+            if (fin) write_outputs_rp(bw, Lc, i, u, t, holds);
+            done = done || fin;
+            if (!done) flags[bw.slots] = 0;
+            __syncthreads();
+            if (flags[bw.slots]) break;
         }
     }
 }
@@ -1123,6 +1308,72 @@ hipError_t launch_placed(const DecodeLaunch &p, hipStream_t stream) {
     if (p.wmax <= 10) return launch_w<10, IN_LDS>(p, stream);
     if (p.wmax <= 20) return launch_w<20, IN_LDS>(p, stream);
     return launch_w<32, IN_LDS>(p, stream);
+}
+
+// Row-pair kernel: p.cpw codewords of Z/2 lanes per workgroup (see
+// decode_rp); p.meta is the row-pair metadata table.
+template <int WMAX>
+__global__ __launch_bounds__(768) __attribute__((amdgpu_waves_per_eu(4))) void decode_i8_rp_kernel(
+    DecodeLaunch p, const int32_t *__restrict__ row_ptr, const uint32_t *__restrict__ meta) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    const int Zh = p.Z / 2, T = (p.n_cols - 2) * p.Z, first = blockIdx.x * p.cpw;
+    BlockWork bw;
+    bw.n = p.n_cw - first < p.cpw ? p.n_cw - first : p.cpw;
+    bw.slots = p.cpw;
+    bw.llr = p.llr + (size_t)first * T;
+    bw.out_bits = p.out_bits + (size_t)first * (p.kb * p.Z / 8);
+    bw.out_iters = p.out_iters + first;
+    bw.out_ok = p.out_ok ? p.out_ok + first : nullptr;
+    bw.out_llr = p.out_llr ? static_cast<int8_t *>(p.out_llr) + (size_t)first * p.n_cols * p.Z
+                           : nullptr;
+    bw.msg = reinterpret_cast<uint16_t *>(p.msg) + (size_t)first * p.E_pad * Zh;
+    {
+        // this workgroup's codewords up to the end of the allocation
+        const size_t base = (size_t)first * p.E_pad * Zh * 2;
+        const size_t full = (size_t)p.cpw * p.E_pad * Zh * 2;
+        const size_t left = p.msg_bytes - base;
+        bw.msg_records = (uint32_t)(left < full ? left : full);
+    }
+    bw.row_pad = p.row_pad;
+    bw.E_pad = p.E_pad;
+    bw.groups = p.groups;
+    bw.wq = p.wq;
+    bw.w_iters = p.w_iters;
+    bw.w_stride = p.rows;
+    bw.rows = p.rows;
+    bw.n_cols = p.n_cols;
+    bw.kb = p.kb;
+    bw.Z = Zh;
+    bw.E = p.E;
+    bw.max_iter = p.max_iter;
+    bw.early_exit = p.early_exit;
+    bw.beta = p.beta;
+    bw.offset = p.offset;
+    decode_rp<WMAX>(bw, smem, (crow_t)row_ptr, (cmeta_t)meta);
+}
+
+template <int WMAX>
+hipError_t launch_rp_w(const DecodeLaunch &p, hipStream_t stream) {
+    const int Zh = p.Z / 2;
+    const int lds = p.cpw * lds_bytes_i8_pair_post(p.n_cols, Zh) + lds_flags_bytes_i8(p.cpw);
+    static std::once_flag attr_once;
+    std::call_once(attr_once, [] {
+        const hipError_t e = hipFuncSetAttribute(
+            reinterpret_cast<const void *>(&decode_i8_rp_kernel<WMAX>),
+            hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes());
+        if (e != hipSuccess) note_hip_error("hipFuncSetAttribute(decode_i8_rp_kernel)", e);
+    });
+    if (p.cpw < 1 || p.cpw * Zh > 768 || Zh % 4 != 0 || !p.msg || lds > max_lds_bytes()) {
+        note_hip_error("decode_i8_rp_kernel: bad workgroup shape", hipErrorInvalidValue);
+        return hipErrorInvalidValue;
+    }
+    const int blocks = (p.n_cw + p.cpw - 1) / p.cpw;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL((decode_i8_rp_kernel<WMAX>), dim3(blocks), dim3(p.cpw * Zh), lds, stream,
+                       p, p.row_ptr, p.meta);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) note_hip_error("launch decode_i8_rp_kernel", e);
+    return e;
 }
 
 __global__ void reset_counter_kernel(unsigned *counter);
@@ -1438,7 +1689,9 @@ __device__ __forceinline__ void ll_row_w(uint8_t *__restrict__ smem, uint32_t lb
                 for (int j = 0; j < ND && j < kPreDwords; ++j) rd[j] = pre[j];
                 if (ND > kPreDwords) R.template load<W, kPreDwords>(rd, u, Z);
             }
-            row_phase1<0, W, true>(smem, lb, rd, md, mo, u, Z, W, xv, axv, la, m1, m2, S);
+            uint32_t ps_unused[1];
+            row_phase1<0, W, true>(smem, lb, rd, md, mo, u, Z, W, xv, axv, la, ps_unused, m1, m2,
+                                   S);
         }
     }
     // exchange of the chunk partials
@@ -1701,6 +1954,11 @@ hipError_t launch_ll(const DecodeLaunch &p, hipStream_t stream) {
 hipError_t launch_decode_i8(const DecodeLaunch &p, hipStream_t stream) {
     if (p.alpha == 2) return p.wmax <= 10 ? launch_ll<10, 2>(p, stream) : launch_ll<20, 2>(p, stream);
     if (p.alpha == 4) return p.wmax <= 10 ? launch_ll<10, 4>(p, stream) : launch_ll<20, 4>(p, stream);
+    if (p.rowpair) {
+        if (p.wmax <= 10) return launch_rp_w<10>(p, stream);
+        if (p.wmax <= 20) return launch_rp_w<20>(p, stream);
+        return launch_rp_w<32>(p, stream);
+    }
     if (p.refill) {
         if (p.wmax <= 10) return launch_refill_w<10>(p, stream);
         if (p.wmax <= 20) return launch_refill_w<20>(p, stream);

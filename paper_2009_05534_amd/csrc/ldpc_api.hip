@@ -26,6 +26,7 @@ struct DevTables {
     uint32_t *meta = nullptr;     // [E_full + kMetaPad] row-pair layout
     uint32_t *meta_row = nullptr; // [E_full + kMetaPad] one row per lane
     uint32_t *meta_i8 = nullptr;  // [E_full + kMetaPad] int8 codeword pairs
+    uint32_t *meta_i8rp = nullptr;  // [E_full + kMetaPad] int8 row pairs
     int32_t *row_pad = nullptr;   // [m_rows + 1] prefix of even-padded row weights
 };
 
@@ -49,11 +50,13 @@ void free_tables(DevTables &t) {
     if (t.meta) (void)hipFree(t.meta);
     if (t.meta_row) (void)hipFree(t.meta_row);
     if (t.meta_i8) (void)hipFree(t.meta_i8);
+    if (t.meta_i8rp) (void)hipFree(t.meta_i8rp);
     if (t.row_pad) (void)hipFree(t.row_pad);
     t.row_ptr = nullptr;
     t.meta = nullptr;
     t.meta_row = nullptr;
     t.meta_i8 = nullptr;
+    t.meta_i8rp = nullptr;
     t.row_pad = nullptr;
 }
 
@@ -85,11 +88,12 @@ int tables_for(const HostGraph &g, DevTables **out, bool upload = true) {
     const int Zh = g.Z / 2;
     const int E = g.row_ptr.back();
     std::vector<uint32_t> meta(E + kMetaPad, 0u), meta_row(E + kMetaPad, 0u),
-        meta_i8(E + kMetaPad, 0u);
+        meta_i8(E + kMetaPad, 0u), meta_i8rp(E + kMetaPad, 0u);
     for (int e2 = 0; e2 < E; ++e2) {
         meta[e2] = pack_meta(g.col[e2], g.shift[e2], Zh);
         meta_row[e2] = pack_meta_row(g.col[e2], g.shift[e2], g.Z);
         meta_i8[e2] = pack_meta_i8(g.col[e2], g.shift[e2], g.Z);
+        meta_i8rp[e2] = pack_meta_i8rp(g.col[e2], g.shift[e2], Zh);
     }
     const std::vector<int32_t> row_pad = padded_row_ptr(g);
     DevTables t;
@@ -100,6 +104,7 @@ int tables_for(const HostGraph &g, DevTables **out, bool upload = true) {
         (e = hipMalloc(&t.meta, sizeof(uint32_t) * meta.size())) != hipSuccess ||
         (e = hipMalloc(&t.meta_row, sizeof(uint32_t) * meta_row.size())) != hipSuccess ||
         (e = hipMalloc(&t.meta_i8, sizeof(uint32_t) * meta_i8.size())) != hipSuccess ||
+        (e = hipMalloc(&t.meta_i8rp, sizeof(uint32_t) * meta_i8rp.size())) != hipSuccess ||
         (e = hipMemcpy(t.row_ptr, g.row_ptr.data(), sizeof(int32_t) * g.row_ptr.size(),
                        hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(t.meta, meta.data(), sizeof(uint32_t) * meta.size(),
@@ -107,6 +112,8 @@ int tables_for(const HostGraph &g, DevTables **out, bool upload = true) {
         (e = hipMemcpy(t.meta_row, meta_row.data(), sizeof(uint32_t) * meta_row.size(),
                        hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(t.meta_i8, meta_i8.data(), sizeof(uint32_t) * meta_i8.size(),
+                       hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(t.meta_i8rp, meta_i8rp.data(), sizeof(uint32_t) * meta_i8rp.size(),
                        hipMemcpyHostToDevice)) != hipSuccess) {
         free_tables(t);
         return hip_fail(e);
@@ -133,7 +140,7 @@ int sub_sizes(const HostGraph &g, int rows, int *K, int *T, int *Nc, int *E) {
 // Launch configurations chosen by ldpc_tune, per (bg, Z, rows, n_cw rounded
 // up to a power of two, early exit).
 struct Tuned {
-    int lanes_per_row, cw_per_block, msg_placement, schedule;
+    int lanes_per_row, cw_per_block, msg_placement, schedule, pairing;
 };
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int, int, int>, Tuned> g_tuned;
@@ -144,6 +151,33 @@ int pow2_bucket(int n) {
     return b;
 }
 
+// Whether an int8 call decodes with the row-pair kernel: on request
+// (LDPC_PAIR_ROWS; the static schedule, one lane per row and device-placed
+// messages, else the caller gets LDPC_EINVAL), or by default for small
+// batches of large lifts, where a codeword pair's 2Z lanes would put two
+// waves on some SIMDs of a CU: Z > 256, no more codewords than CUs, one
+// lane per row, the static schedule and the default packing and message
+// placement. Sets g_msg when a request cannot be met.
+bool use_row_pairs(const ldpc_args *a, int Z) {
+    const bool can = a->schedule == LDPC_SCHED_STATIC && a->lanes_per_row <= 1 &&
+                     a->msg_placement != LDPC_MSG_LDS;
+    if (a->pairing == LDPC_PAIR_ROWS) {
+        if (!can)
+            snprintf(g_msg, sizeof(g_msg),
+                     "row pairs need the static schedule, one lane per row and device-placed "
+                     "messages");
+        return can;
+    }
+    if (a->pairing != LDPC_PAIR_AUTO || !can || Z <= 256 || a->cw_per_block != 0 ||
+        a->msg_placement != LDPC_MSG_AUTO)
+        return false;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return false;
+    return a->n_cw <= cus;
+}
+
 int prepare_decode(const ldpc_args *a0, bool upload, DecodeLaunch &p, bool &msg_in_lds,
                    size_t &msg_bytes, bool allow_refill = false) {
     if (!a0) return LDPC_EINVAL;
@@ -152,7 +186,7 @@ int prepare_decode(const ldpc_args *a0, bool upload, DecodeLaunch &p, bool &msg_
     ldpc_args ar = *a0;
     if (ar.precision == LDPC_I8 && ar.lanes_per_row == 0 && ar.cw_per_block == 0 &&
         ar.msg_placement == LDPC_MSG_AUTO && ar.schedule == LDPC_SCHED_STATIC &&
-        ar.max_workgroups == 0) {
+        ar.max_workgroups == 0 && ar.pairing == LDPC_PAIR_AUTO) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tuned.find(std::make_tuple(ar.bg, ar.Z, ar.rows, pow2_bucket(ar.n_cw),
                                                ar.early_exit ? 1 : 0));
@@ -161,6 +195,7 @@ int prepare_decode(const ldpc_args *a0, bool upload, DecodeLaunch &p, bool &msg_
             ar.cw_per_block = it->second.cw_per_block;
             ar.msg_placement = it->second.msg_placement;
             ar.schedule = it->second.schedule;
+            ar.pairing = it->second.pairing;
         }
     }
     const ldpc_args *a = &ar;
@@ -173,10 +208,12 @@ int prepare_decode(const ldpc_args *a0, bool upload, DecodeLaunch &p, bool &msg_
         (a->lanes_per_row != 0 && a->lanes_per_row != 1 && a->lanes_per_row != 2 &&
          a->lanes_per_row != 4) ||
         (a->schedule != LDPC_SCHED_STATIC && a->schedule != LDPC_SCHED_PERSISTENT) ||
-        a->max_workgroups < 0)
+        a->max_workgroups < 0 || a->pairing < LDPC_PAIR_AUTO || a->pairing > LDPC_PAIR_ROWS ||
+        (a->pairing == LDPC_PAIR_ROWS && a->precision != LDPC_I8))
         return LDPC_EINVAL;
     g_msg[0] = '\0';
     int lds_cap = 0;
+    const uint32_t *meta_rp = nullptr;
     {
         std::lock_guard<std::mutex> lk(g_mu);
         auto it = g_graphs.find({a->bg, a->Z});
@@ -201,6 +238,7 @@ int prepare_decode(const ldpc_args *a0, bool upload, DecodeLaunch &p, bool &msg_
         p.row_pad = t->row_pad;
         p.E_pad = e_pad;
         p.meta = a->precision == LDPC_I8 ? t->meta_i8 : t->meta;
+        meta_rp = t->meta_i8rp;
         p.rows = a->rows;
         p.n_cols = g.kb + a->rows;
         p.kb = g.kb;
@@ -230,6 +268,8 @@ int prepare_decode(const ldpc_args *a0, bool upload, DecodeLaunch &p, bool &msg_
     const bool i8 = a->precision == LDPC_I8;
     int cpw = 0;
     msg_in_lds = false;
+    const bool rowpair = i8 && use_row_pairs(a, p.Z);
+    if (a->pairing == LDPC_PAIR_ROWS && !rowpair) return LDPC_EINVAL;
     if (p.alpha > 1) {
         // Low-latency mapping: alpha lanes per check row, device-placed
         // messages, whole waves per chunk group (pairs * Z a multiple of 64).
@@ -245,6 +285,16 @@ int prepare_decode(const ldpc_args *a0, bool upload, DecodeLaunch &p, bool &msg_
             ll_lds_bytes(p.n_cols, p.Z, pairs, p.alpha) > lds_cap)
             return LDPC_EINVAL;
         cpw = 2 * pairs;
+    } else if (rowpair) {
+        // One codeword per Z/2 lanes (row pairs), device-placed messages.
+        p.rowpair = 1;
+        p.meta = meta_rp;
+        const int per_cw = lds_bytes_i8_pair_post(p.n_cols, Zh) + 16;
+        cpw = a->cw_per_block > 0 ? a->cw_per_block : 1;
+        cpw = std::min(cpw, (lds_cap - 8) / per_cw);
+        cpw = std::min(cpw, 768 / Zh);
+        cpw = std::min(cpw, a->n_cw);
+        if (cpw < 1) return LDPC_EINVAL;
     } else if (i8) {
         // Codewords go in pairs of Z lanes. Message placement: LDS when two
         // pairs' full state fits a CU, else device memory so that several
@@ -292,6 +342,7 @@ int prepare_decode(const ldpc_args *a0, bool upload, DecodeLaunch &p, bool &msg_
         p.offset = a->offset_h;
     }
     msg_bytes = msg_in_lds ? 0
+                : p.rowpair ? (size_t)a->n_cw * p.E_pad * Zh * 2 + kMsgTail
                 : i8 ? (((size_t)a->n_cw + 1) / 2) * p.E_pad * p.Z * 2 + kMsgTail
                      : (size_t)a->n_cw * p.E_pad * Zh * 4;
     // Persistent schedule: as many workgroups as run at once (LDS-bound:
@@ -547,7 +598,7 @@ int ldpc_decode_noalloc(const ldpc_args *a) {
 int ldpc_tune(const ldpc_args *a, ldpc_tuning *out) {
     if (!a || a->precision != LDPC_I8 || a->lanes_per_row != 0 || a->cw_per_block != 0 ||
         a->msg_placement != LDPC_MSG_AUTO || a->schedule != LDPC_SCHED_STATIC ||
-        a->max_workgroups != 0)
+        a->max_workgroups != 0 || a->pairing != LDPC_PAIR_AUTO)
         return LDPC_EINVAL;
     {
         // forget an earlier choice for this key, so the candidates below
@@ -557,18 +608,23 @@ int ldpc_tune(const ldpc_args *a, ldpc_tuning *out) {
                                       a->early_exit ? 1 : 0));
     }
     // first the library's default launch: if it wins, nothing is recorded
-    std::vector<Tuned> cand{Tuned{0, 0, LDPC_MSG_AUTO, LDPC_SCHED_STATIC},
-                            Tuned{1, 0, LDPC_MSG_AUTO, LDPC_SCHED_PERSISTENT}};
+    std::vector<Tuned> cand{
+        Tuned{0, 0, LDPC_MSG_AUTO, LDPC_SCHED_STATIC, LDPC_PAIR_AUTO},
+        Tuned{1, 0, LDPC_MSG_AUTO, LDPC_SCHED_PERSISTENT, LDPC_PAIR_CODEWORDS}};
     for (int pairs : {1, 2, 3, 4, 6, 8, 12, 16, 24, 48}) {
-        cand.push_back(Tuned{1, 2 * pairs, LDPC_MSG_LDS, LDPC_SCHED_STATIC});
-        cand.push_back(Tuned{1, 2 * pairs, LDPC_MSG_DEVICE, LDPC_SCHED_STATIC});
+        cand.push_back(Tuned{1, 2 * pairs, LDPC_MSG_LDS, LDPC_SCHED_STATIC, LDPC_PAIR_CODEWORDS});
+        cand.push_back(
+            Tuned{1, 2 * pairs, LDPC_MSG_DEVICE, LDPC_SCHED_STATIC, LDPC_PAIR_CODEWORDS});
     }
     for (int alpha : {2, 4}) {
         int base = 1;
         while ((base * a->Z) % 64 != 0) ++base;
         for (int k : {1, 2})
-            cand.push_back(Tuned{alpha, 2 * base * k, LDPC_MSG_DEVICE, LDPC_SCHED_STATIC});
+            cand.push_back(Tuned{alpha, 2 * base * k, LDPC_MSG_DEVICE, LDPC_SCHED_STATIC,
+                                 LDPC_PAIR_CODEWORDS});
     }
+    for (int cws : {1, 2, 4})
+        cand.push_back(Tuned{1, cws, LDPC_MSG_DEVICE, LDPC_SCHED_STATIC, LDPC_PAIR_ROWS});
     hipStream_t stream = static_cast<hipStream_t>(a->stream);
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return LDPC_EHIP;
@@ -577,7 +633,7 @@ int ldpc_tune(const ldpc_args *a, ldpc_tuning *out) {
         return LDPC_EHIP;
     }
     float best = 1e30f;
-    Tuned pick{0, 0, LDPC_MSG_AUTO, LDPC_SCHED_STATIC};
+    Tuned pick{0, 0, LDPC_MSG_AUTO, LDPC_SCHED_STATIC, LDPC_PAIR_AUTO};
     int tried = 0, rc = LDPC_OK;
     for (const Tuned &c : cand) {
         ldpc_args t = *a;
@@ -585,6 +641,7 @@ int ldpc_tune(const ldpc_args *a, ldpc_tuning *out) {
         t.cw_per_block = c.cw_per_block;
         t.msg_placement = c.msg_placement;
         t.schedule = c.schedule;
+        t.pairing = c.pairing;
         DecodeLaunch probe{};
         bool in_lds = false;
         size_t mb = 0;
@@ -623,6 +680,7 @@ int ldpc_tune(const ldpc_args *a, ldpc_tuning *out) {
         out->cw_per_block = pick.cw_per_block;
         out->msg_placement = pick.msg_placement;
         out->schedule = pick.schedule;
+        out->pairing = pick.pairing;
         out->ms = best;
         out->candidates = tried;
     }

@@ -72,6 +72,10 @@ struct DecodeLaunch {
                               // each with a msg region of cpw / 2 pairs,
                               // taking codewords from *counter
     int grid;
+    int rowpair;              // int8: the row-pair kernel (decode_i8_rp_kernel:
+                              // cpw codewords of Z/2 lanes per workgroup,
+                              // meta = pack_meta_i8rp, msg = [n_cw][E_pad*Z/2]
+                              // pair words)
     unsigned *counter;        // refill: codewords handed out (reset per launch)
 };
 
@@ -247,6 +251,18 @@ inline uint64_t layer_groups(const int32_t *row_ptr, const int16_t *col, int row
 // which wraps for u >= Z - s).
 __host__ __device__ inline uint32_t pack_meta_i8(int c, int s, int Z) {
     return (uint32_t)(2 * (c * Z + s)) | ((uint32_t)(Z - s) << 16);
+}
+
+// Per-block metadata for the int8 row-pair kernel (one codeword; lane u of
+// its Zh = Z/2 lanes owns check rows u and u + Zh; pair word p of column c
+// holds variables p and p + Zh): for the shift s = s_lo + Zh*s_hi (s_lo <
+// Zh), bits [0, 15) the byte offset 2(c*Zh + s_lo) of the pair word before
+// the wrap, bit 15 s_hi, bits [16, 25) the wrap threshold Zh - s_lo (lane u
+// reads pair word c*Zh + (u + s_lo) mod Zh, which wraps for u >= Zh - s_lo).
+__host__ __device__ inline uint32_t pack_meta_i8rp(int c, int s, int Zh) {
+    const int s_lo = s % Zh;
+    return (uint32_t)(2 * (c * Zh + s_lo)) | ((uint32_t)(s / Zh) << 15) |
+           ((uint32_t)(Zh - s_lo) << 16);
 }
 
 // Per-block metadata for the one-check-row-per-lane learned min-sum:

@@ -18,6 +18,7 @@ LDPC_I8 = 0
 LDPC_F16 = 1
 MSG_PLACEMENT = {"auto": 0, "lds": 1, "device": 2}
 SCHEDULE = {"static": 0, "persistent": 1}
+PAIRING = {"auto": 0, "codewords": 1, "rows": 2}
 _ERRORS = {-1: "invalid argument", -2: "out of memory", -3: "HIP runtime error",
            -4: "no graph registered for (bg, Z)"}
 
@@ -41,14 +42,15 @@ class Args(ctypes.Structure):
         ("out_ok", ctypes.c_void_p), ("out_llr", ctypes.c_void_p),
         ("cw_per_block", ctypes.c_int), ("msg_placement", ctypes.c_int),
         ("lanes_per_row", ctypes.c_int), ("schedule", ctypes.c_int),
-        ("max_workgroups", ctypes.c_int), ("stream", ctypes.c_void_p),
+        ("max_workgroups", ctypes.c_int), ("pairing", ctypes.c_int),
+        ("stream", ctypes.c_void_p),
     ]
 
 
 class Tuning(ctypes.Structure):
     _fields_ = [("lanes_per_row", ctypes.c_int), ("cw_per_block", ctypes.c_int),
                 ("msg_placement", ctypes.c_int), ("schedule", ctypes.c_int),
-                ("ms", ctypes.c_float), ("candidates", ctypes.c_int)]
+                ("pairing", ctypes.c_int), ("ms", ctypes.c_float), ("candidates", ctypes.c_int)]
 
 
 class Job(ctypes.Structure):
@@ -196,8 +198,12 @@ def decode_into(llr, bg: int, Z: int, rows: int, out_bits, out_iters, *, max_ite
                 offset: float = 0, weights=None, out_ok=None, out_llr=None,
                 cw_per_block: int = 0, msg_placement: str = "auto", stream=None,
                 noalloc: bool = False, lanes_per_row: int = 0, tune: bool = False,
-                schedule: str = "static", max_workgroups: int = 0):
+                schedule: str = "static", max_workgroups: int = 0, pairing: str = "auto"):
     """Decode int8 LLRs [n_cw, T] (device tensor) into preallocated outputs.
+
+    ``pairing`` (int8): "codewords" (two codewords per lane), "rows" (check
+    rows u and u + Z/2 of one codeword per lane) or "auto" (rows for small
+    batches of lifts above 256).
 
     ``noalloc``: call ldpc_decode_noalloc (messages in the library's static
     per-device scratch; nothing is allocated) instead of ldpc_decode_ex.
@@ -257,6 +263,9 @@ def decode_into(llr, bg: int, Z: int, rows: int, out_bits, out_iters, *, max_ite
         raise ValueError("schedule must be 'static' or 'persistent'")
     a.schedule = SCHEDULE[schedule]
     a.max_workgroups = max_workgroups
+    if pairing not in PAIRING:
+        raise ValueError("pairing must be 'auto', 'codewords' or 'rows'")
+    a.pairing = PAIRING[pairing]
     a.stream = _stream_ptr(stream)
     if tune:
         t = Tuning()
@@ -264,6 +273,7 @@ def decode_into(llr, bg: int, Z: int, rows: int, out_bits, out_iters, *, max_ite
         return {"lanes_per_row": t.lanes_per_row, "cw_per_block": t.cw_per_block,
                 "msg_placement": {v: k for k, v in MSG_PLACEMENT.items()}[t.msg_placement],
                 "schedule": "persistent" if t.schedule == 1 else "static",
+                "pairing": {v: k for k, v in PAIRING.items()}[t.pairing],
                 "ms": t.ms, "candidates": t.candidates}
     if noalloc:
         _check(lib().ldpc_decode_noalloc(ctypes.byref(a)), "ldpc_decode_noalloc")
@@ -275,7 +285,8 @@ def decode(llr, bg: int, Z: int, rows: int, *, max_iter: int = 10, precision: st
            early_exit: bool = True, beta: float | None = None, offset: float = 0, weights=None,
            want_ok: bool = True, want_llr: bool = False, cw_per_block: int = 0,
            msg_placement: str = "auto", stream=None, noalloc: bool = False,
-           lanes_per_row: int = 0, schedule: str = "static", max_workgroups: int = 0):
+           lanes_per_row: int = 0, schedule: str = "static", max_workgroups: int = 0,
+           pairing: str = "auto"):
     """Allocate outputs with torch on llr's device and decode (through
     ldpc_decode_noalloc when ``noalloc``; the outputs are still allocated
     here, by torch).
@@ -299,7 +310,7 @@ def decode(llr, bg: int, Z: int, rows: int, *, max_iter: int = 10, precision: st
                 early_exit=early_exit, beta=beta, offset=offset, weights=weights, out_ok=ok,
                 out_llr=out, cw_per_block=cw_per_block, msg_placement=msg_placement,
                 stream=stream, noalloc=noalloc, lanes_per_row=lanes_per_row,
-                schedule=schedule, max_workgroups=max_workgroups)
+                schedule=schedule, max_workgroups=max_workgroups, pairing=pairing)
     return bits, iters, (ok.bool() if ok is not None else None), out
 
 

@@ -84,6 +84,11 @@ def test_decode_rejects_bad_arguments_before_launch(lib):
     a.llr_in = 17  # the LLRs are read as 32-bit words: 4-byte alignment
     assert lib_.ldpc_decode_ex(ctypes.byref(a)) == -1
     a.llr_in = 16
+    a.pairing = 3  # not a pairing
+    assert lib_.ldpc_decode_ex(ctypes.byref(a)) == -1
+    a.pairing, a.precision = 2, 1  # row pairs are int8 only
+    assert lib_.ldpc_decode_ex(ctypes.byref(a)) == -1
+    a.pairing, a.precision = 0, 0
     job = ldpc.Job(bg=1, Z=384, rows=46, n_cw=1, llr=17, out_bits=16, out_iters=16)
     nb = ctypes.c_size_t()
     assert lib_.ldpc_decode_batch_bytes(ctypes.byref(job), 1, ctypes.byref(nb)) == -1

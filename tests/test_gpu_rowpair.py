@@ -1,0 +1,108 @@
+"""The int8 row-pair kernel (one codeword per Z/2 lanes, each lane updating
+check rows u and u + Z/2 as the two halves of its packed registers) against
+the CPU oracle, through the C ABI: bit-exact hard decisions, posteriors,
+iteration counts and flags over lifts whose halves fill whole waves or not
+(Z/2 = 8 .. 192), several codewords per workgroup with a ragged last
+workgroup, the normalisation options, and the same results as codeword
+pairs."""
+import numpy as np
+import pytest
+
+from synth import make_batch
+
+from test_gpu_parity import _graph, assert_i8_equal, gpu_decode, oracle_i8
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2009_05534_amd import ldpc
+    ldpc.lib()
+    yield
+
+
+@pytest.mark.parametrize("bg,Z,rows,n,cpw,ebn0", [
+    (1, 384, 46, 3, 1, 1.5),
+    (1, 384, 46, 5, 2, 1.25),   # two codewords per workgroup, ragged last one
+    (2, 384, 42, 4, 1, 1.0),
+    (1, 352, 46, 3, 1, 1.75),   # 176 lanes: the third wave is partly idle
+    (2, 256, 30, 6, 3, 1.25),
+    (1, 64, 46, 9, 6, 2.0),
+    (1, 40, 46, 33, 16, 1.5),   # 20 lanes per codeword, 320 per workgroup
+    (1, 24, 20, 17, 3, 1.5),
+    (2, 16, 42, 40, 4, 1.5),
+])
+def test_rowpair_equals_oracle(bg, Z, rows, n, cpw, ebn0):
+    g = _graph(bg, Z, rows)
+    b = make_batch(g, n, ebn0, data_seed=700 + Z + rows)
+    print(f"[rowpair] bg={bg} Z={Z} rows={rows} n={n} cpw={cpw}", flush=True)
+    got = gpu_decode(bg, Z, rows, b.q, pairing="rows", cw_per_block=cpw)
+    assert_i8_equal(got, oracle_i8(g, b.q))
+
+
+@pytest.mark.parametrize("opts", [
+    dict(offset=2),
+    dict(beta=1.0, offset=1),
+    dict(max_iter=1),
+    dict(max_iter=25),
+    dict(early_exit=False),
+])
+def test_rowpair_options(opts):
+    g = _graph(1, 128, 46)
+    b = make_batch(g, 6, 1.25, data_seed=71)
+    got = gpu_decode(1, 128, 46, b.q, pairing="rows", cw_per_block=2, **opts)
+    assert_i8_equal(got, oracle_i8(g, b.q, **opts))
+
+
+def test_rowpair_learned_weights():
+    g = _graph(1, 384, 46)
+    b = make_batch(g, 4, 1.0, data_seed=72)
+    w = np.random.default_rng(3).integers(40, 140, (10, 46)).astype(np.uint8)
+    got = gpu_decode(1, 384, 46, b.q, pairing="rows", weights=w)
+    assert_i8_equal(got, oracle_i8(g, b.q, weights=w))
+
+
+def test_rowpair_saturated_inputs():
+    # every LLR -128 (read as -127) and every LLR +127: saturation on both sides
+    g = _graph(2, 384, 42)
+    for v in (-128, 127):
+        q = np.full((2, g.T), v, np.int8)
+        got = gpu_decode(2, 384, 42, q, pairing="rows", max_iter=4)
+        assert_i8_equal(got, oracle_i8(g, q, max_iter=4))
+
+
+def test_auto_pairing_equals_codeword_pairs():
+    # small batches at Z = 384 take row pairs by default; results are the
+    # same as codeword pairs and the oracle's
+    g = _graph(1, 384, 46)
+    b = make_batch(g, 7, 1.5, data_seed=73)
+    auto = gpu_decode(1, 384, 46, b.q)
+    cw = gpu_decode(1, 384, 46, b.q, pairing="codewords")
+    assert_i8_equal(auto, cw)
+    assert_i8_equal(auto, oracle_i8(g, b.q))
+
+
+def test_rowpair_noalloc():
+    g = _graph(1, 384, 46)
+    b = make_batch(g, 3, 1.5, data_seed=74)
+    a = gpu_decode(1, 384, 46, b.q, pairing="rows")
+    na = gpu_decode(1, 384, 46, b.q, pairing="rows", noalloc=True)
+    assert_i8_equal(na, a)
+
+
+def test_rowpair_refusals():
+    from paper_2009_05534_amd import ldpc
+    g = _graph(1, 64, 30)
+    q = make_batch(g, 4, 1.5, data_seed=75).q
+    for kw in (dict(pairing="rows", msg_placement="lds"),
+               dict(pairing="rows", schedule="persistent"),
+               dict(pairing="rows", lanes_per_row=2),
+               dict(pairing="rows", precision="f16")):
+        with pytest.raises(ldpc.LdpcError):
+            gpu_decode(1, 64, 30, q, **kw)
+    with pytest.raises(ValueError):
+        gpu_decode(1, 64, 30, q, pairing="lanes")

@@ -47,8 +47,10 @@ def test_tune_then_default_equals_oracle(bg, Z, rows, n):
     # the next default call takes the tuned configuration
     assert_i8_equal(gpu_decode(bg, Z, rows, b.q), ref)
     # and the chosen knobs spelled out give the same
+    assert choice["pairing"] in ("auto", "codewords", "rows"), choice
     kw = dict(lanes_per_row=choice["lanes_per_row"], cw_per_block=choice["cw_per_block"],
-              msg_placement=choice["msg_placement"], schedule=choice["schedule"])
+              msg_placement=choice["msg_placement"], schedule=choice["schedule"],
+              pairing=choice["pairing"])
     assert_i8_equal(gpu_decode(bg, Z, rows, b.q, **kw), ref)
 
 
@@ -59,6 +61,7 @@ def test_tune_refusals():
     bits = torch.zeros((4, (g.K + 7) // 8), dtype=torch.uint8, device="cuda")
     iters = torch.zeros(4, dtype=torch.int32, device="cuda")
     for kw in (dict(cw_per_block=2), dict(lanes_per_row=2), dict(msg_placement="lds"),
-               dict(precision="f16"), dict(schedule="persistent"), dict(max_workgroups=2)):
+               dict(precision="f16"), dict(schedule="persistent"), dict(max_workgroups=2),
+               dict(pairing="rows")):
         with pytest.raises(ldpc.LdpcError):
             ldpc.decode_into(q, 1, 64, 30, bits, iters, tune=True, **kw)
