@@ -37,27 +37,39 @@ def oracle_policy(b, wq):
     return np.where(lo[:, None], lb, pb), np.where(lo, li, pi), lo | po
 
 
-@pytest.mark.parametrize("rate", [2e3, 5e4])
-def test_mix_equals_alone_and_oracle(server_mod, rate):
+_ORACLE = {}  # block id -> the oracle's result under the serving policy
+
+
+@pytest.mark.parametrize("rate,speculate", [(2e3, "auto"), (5e4, "auto"), (2e3, True),
+                                            (5e4, False)])
+def test_mix_equals_alone_and_oracle(server_mod, rate, speculate):
     serve = server_mod
     blocks = serve.make_trace(120, seed=6)
     rng = np.random.default_rng(0)
     # weights that leave a share of BG1 codewords failing, so the plain
     # fallback runs on some codewords of a block but not on others
     wq = rng.integers(40, 112, (10, 46)).astype(np.uint8)
-    srv = serve.Server(weights_bg1=wq, n_slots=4, mem_budget=64 << 20)
+    srv = serve.Server(weights_bg1=wq, n_slots=4, mem_budget=64 << 20, speculate=speculate)
     trace = serve.rescale(blocks, rate)
+    print(f"[serve] {len(trace)} blocks at {rate} blocks/s, speculate={speculate}", flush=True)
     stats = srv.run(trace)
     assert stats["blocks"] == 120 and stats["latency_ms_p99"] > 0
     assert 0.0 <= stats["deadline_met"] <= 1.0
     assert stats["fallback_blocks"] > 0, stats
+    n_learned = sum(b.bg == 1 for b in trace)
+    if speculate is True:
+        assert stats["speculated_blocks"] == n_learned, stats
+    if speculate is False:
+        assert stats["speculated_blocks"] == 0, stats
     mixed = 0
     for b in trace:
         bits, iters, ok = srv.decode_alone(b)
         assert (b.bits == bits).all(), b.id
         assert (b.iters == iters).all(), b.id
         assert (b.ok == ok).all(), b.id
-        rb, ri, ro = oracle_policy(b, wq)
+        if b.id not in _ORACLE:
+            _ORACLE[b.id] = oracle_policy(b, wq)
+        rb, ri, ro = _ORACLE[b.id]
         assert (b.bits == rb).all(), ("oracle", b.id)
         assert (b.iters == ri).all(), ("oracle", b.id)
         assert (b.ok == ro).all(), ("oracle", b.id)
