@@ -44,6 +44,10 @@ COUNTERS_FILE = os.path.join(ROOT, "profiles", "decode_i8_bg1_z384_counters.md")
 KERNEL_SOURCES_F16 = ("decode_f16.hip", "ldpc_internal.h")
 COUNTERS_FILE_F16 = os.path.join(ROOT, "profiles", "decode_f16_bg1_z384_counters.md")
 KERNEL_SOURCES = ("decode_i8.hip", "ldpc_internal.h")
+# the kernel the library runs for this workload by default: early-exit
+# decodes at lifts above 256 go to the row-pair kernel (one codeword per
+# workgroup), the others to codeword pairs
+KERNEL_I8 = "decode_i8_rp_kernel"
 
 
 def kernel_source_sha(sources=KERNEL_SOURCES) -> str:
@@ -62,17 +66,20 @@ def kernel_source_sha(sources=KERNEL_SOURCES) -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(counters_file=None, sources=None):
+def measured_traffic(counters_file=None, sources=None, kernel=None):
     """HBM bytes per launch of a decode kernel (the int8 one by default)
     from its committed counter summary (FETCH_SIZE and WRITE_SIZE, each
     scaled by what the counter reads for a plain copy of known size), or
-    None when the summary is missing or was taken on other kernel sources."""
+    None when the summary is missing, names another kernel or was taken on
+    other kernel sources."""
     try:
         text = open(counters_file or COUNTERS_FILE).read()
         rec = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
     except (OSError, IndexError, ValueError):
         return None
     if rec.get("kernel_source_sha") != kernel_source_sha(sources or KERNEL_SOURCES):
+        return None
+    if rec.get("kernel") != (kernel or KERNEL_I8):
         return None
     return rec.get("traffic_bytes_per_launch")
 
@@ -225,7 +232,7 @@ def main():
         },
         "roofline": {
             "bound": "alu",
-            "kernel": "decode_i8_kernel",
+            "kernel": KERNEL_I8,
             "achieved": round(achieved, 3),
             "peak": round(PEAK_ALU_TOPS, 2),
             "unit": "Top/s",

@@ -203,11 +203,14 @@ typedef struct ldpc_args {
                                device-placed messages, else LDPC_EINVAL): for
                                small batches of large lifts, where a pair's
                                2Z lanes would put two waves on some of a
-                               CU's SIMDs. LDPC_PAIR_AUTO (0, the default):
-                               row pairs when Z > 256, n_cw is at most the
-                               device's CU count, one lane per row, the
-                               static schedule, cw_per_block 0 and message
-                               placement AUTO; else codeword pairs.
+                               CU's SIMDs, and for early exit (one codeword
+                               per workgroup leaves its CU as soon as it
+                               converges). LDPC_PAIR_AUTO (0, the default):
+                               row pairs when Z > 256, early exit is on or
+                               n_cw is at most the device's CU count, one
+                               lane per row, the static schedule,
+                               cw_per_block 0 and message placement AUTO;
+                               else codeword pairs.
                                Results are identical under both. */
     void *stream;
 } ldpc_args;

@@ -153,11 +153,14 @@ int pow2_bucket(int n) {
 
 // Whether an int8 call decodes with the row-pair kernel: on request
 // (LDPC_PAIR_ROWS; the static schedule, one lane per row and device-placed
-// messages, else the caller gets LDPC_EINVAL), or by default for small
-// batches of large lifts, where a codeword pair's 2Z lanes would put two
-// waves on some SIMDs of a CU: Z > 256, no more codewords than CUs, one
-// lane per row, the static schedule and the default packing and message
-// placement. Sets g_msg when a request cannot be met.
+// messages, else the caller gets LDPC_EINVAL), or by default at lifts
+// above 256 (one lane per row, the static schedule, the default packing
+// and message placement) when either there are no more codewords than CUs
+// (a codeword pair's 2Z lanes would put two waves on some SIMDs of a CU,
+// where one codeword's Z/2 lanes leave every wave a SIMD of its own) or
+// early exit is on (one codeword per workgroup leaves the CU as soon as
+// it converges, where a workgroup of two codeword pairs runs until the
+// slowest of its four has). Sets g_msg when a request cannot be met.
 bool use_row_pairs(const ldpc_args *a, int Z) {
     const bool can = a->schedule == LDPC_SCHED_STATIC && a->lanes_per_row <= 1 &&
                      a->msg_placement != LDPC_MSG_LDS;
@@ -171,6 +174,7 @@ bool use_row_pairs(const ldpc_args *a, int Z) {
     if (a->pairing != LDPC_PAIR_AUTO || !can || Z <= 256 || a->cw_per_block != 0 ||
         a->msg_placement != LDPC_MSG_AUTO)
         return false;
+    if (a->early_exit) return true;
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
