@@ -5,6 +5,7 @@
 // kernel, then the decode) and replayed, and it can pick its grid size by
 // timing the candidates on its own work (autotuning).
 #include <algorithm>
+#include <cstring>
 #include <vector>
 
 #include "../../include/ldpc.h"
@@ -313,15 +314,16 @@ int batch_async(const std::vector<BatchJob> &jobs, const std::vector<int> &job_c
     b.lanes = lanes;
     b.lds = lds;
     b.wmax = wmax;
-    // pageable sources: the runtime has staged them when the calls return
-    e = hipMemcpyAsync(const_cast<BatchTask *>(b.tasks), tasks.data(), tb, hipMemcpyHostToDevice,
-                       stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(const_cast<BatchJob *>(b.jobs), jobs.data(), jbytes,
-                           hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess && !ts.waves.empty())
-        e = hipMemcpyAsync(const_cast<WaveTask *>(b.waves), ts.waves.data(),
-                           sizeof(WaveTask) * ts.waves.size(), hipMemcpyHostToDevice, stream);
+    // The task, job and wave-task tables and the zeroed task counter as one
+    // host image, moved by one copy (the counter needs no reset kernel).
+    // Pageable source: the runtime has staged it when the call returns.
+    std::vector<uint8_t> img(o_counter + sizeof(unsigned), 0);
+    std::memcpy(img.data(), tasks.data(), tb);
+    std::memcpy(img.data() + tb, jobs.data(), jbytes);
+    if (!ts.waves.empty())
+        std::memcpy(img.data() + o_waves, ts.waves.data(), sizeof(WaveTask) * ts.waves.size());
+    e = hipMemcpyAsync(buf, img.data(), img.size(), hipMemcpyHostToDevice, stream);
+    b.counter_zeroed = 1;
     if (e == hipSuccess) e = launch_decode_batch(b, stream);
     const hipError_t ef = hipFreeAsync(buf, stream);
     if (e != hipSuccess) {

@@ -1997,11 +1997,14 @@ hipError_t launch_decode_batch(const BatchLaunch &b, hipStream_t stream) {
         return hipErrorInvalidValue;
     }
     (void)hipGetLastError();
-    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, stream, b.counter);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) {
-        note_hip_error("launch reset_counter_kernel", e);
-        return e;
+    hipError_t e = hipSuccess;
+    if (!b.counter_zeroed) {
+        hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, stream, b.counter);
+        e = hipGetLastError();
+        if (e != hipSuccess) {
+            note_hip_error("launch reset_counter_kernel", e);
+            return e;
+        }
     }
     static std::once_flag attr_once[2];  // once per process, also under concurrent calls
     const void *fn = b.wmax <= 10 ? reinterpret_cast<const void *>(&decode_batch_kernel<10>)

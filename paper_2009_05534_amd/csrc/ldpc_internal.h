@@ -147,6 +147,8 @@ struct BatchLaunch {
     int msg_per_block;
     int max_iter, early_exit, beta, offset;
     int grid, lanes, lds, wmax;
+    int counter_zeroed;       // 1: *counter is already zero on the stream (no
+                              // reset kernel before the decode)
 };
 hipError_t launch_decode_batch(const BatchLaunch &b, hipStream_t stream);
 
