@@ -1311,9 +1311,13 @@ hipError_t launch_placed(const DecodeLaunch &p, hipStream_t stream) {
 }
 
 // Row-pair kernel: p.cpw codewords of Z/2 lanes per workgroup (see
-// decode_rp); p.meta is the row-pair metadata table.
+// decode_rp); p.meta is the row-pair metadata table. Five waves per SIMD:
+// at Z = 384 six one-codeword workgroups (18 waves, 157 kB of LDS) share a
+// CU; the register budget this leaves (up to 102) spills six values, none
+// inside a row update (the four-wave budget fits five workgroups and was
+// 1.5 % slower).
 template <int WMAX>
-__global__ __launch_bounds__(768) __attribute__((amdgpu_waves_per_eu(4))) void decode_i8_rp_kernel(
+__global__ __launch_bounds__(768) __attribute__((amdgpu_waves_per_eu(5))) void decode_i8_rp_kernel(
     DecodeLaunch p, const int32_t *__restrict__ row_ptr, const uint32_t *__restrict__ meta) {
     extern __shared__ __align__(16) uint8_t smem[];
     const int Zh = p.Z / 2, T = (p.n_cols - 2) * p.Z, first = blockIdx.x * p.cpw;
