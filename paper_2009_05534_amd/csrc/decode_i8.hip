@@ -1414,7 +1414,11 @@ hipError_t launch_refill_w(const DecodeLaunch &p, hipStream_t stream) {
 // 384-lane workgroups of BG1 Z = 384 on a CU; at that register budget (96)
 // the bound-20 body spills three per-task values, which are reloaded once
 // per task or iteration, never inside a row update.
-template <int WMAX>
+// RPT: the variant that also decodes row-pair tasks (nwave = -1), launched
+// only for launches that hold some: its extra path changes the register
+// allocation of the whole kernel (spills inside row updates), which the
+// variant without it keeps clear of.
+template <int WMAX, bool RPT = false>
 __global__ __launch_bounds__(kBatchLanes) __attribute__((amdgpu_waves_per_eu(5))) void decode_batch_kernel(
     const BatchTask *__restrict__ tasks, const BatchJob *__restrict__ jobs,
     const WaveTask *__restrict__ waves, int n_tasks, unsigned *counter, uint16_t *msg_ws,
@@ -1429,11 +1433,40 @@ __global__ __launch_bounds__(kBatchLanes) __attribute__((amdgpu_waves_per_eu(5))
         __syncthreads();
         if (ti >= n_tasks) break;
         const BatchTask tk = tasks[ti];
-        // a whole-workgroup task, or this wave's task of a bundle
-        // (uniform within a wave; readfirstlane lets the compiler know)
+        // a whole-workgroup task, a row-pair task or this wave's task of a
+        // bundle (uniform within a wave; readfirstlane lets the compiler know)
         const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWaveLanes));
         const bool wave_task = tk.nwave > 0;
-        if (!wave_task || wv < tk.nwave) {
+        if (RPT && tk.nwave < 0) {
+            const BatchJob &jb = jobs[tk.job];
+            const int Zh = jb.Z / 2, T = (jb.n_cols - 2) * jb.Z;
+            BlockWork bw;
+            bw.n = 1;
+            bw.slots = 1;
+            bw.llr = jb.llr + (size_t)tk.first * T;
+            bw.out_bits = jb.out_bits + (size_t)tk.first * (jb.kb * jb.Z / 8);
+            bw.out_iters = jb.out_iters + tk.first;
+            bw.out_ok = jb.out_ok ? jb.out_ok + tk.first : nullptr;
+            bw.out_llr = nullptr;
+            bw.msg = msg_ws + (size_t)blockIdx.x * msg_per_block;
+            bw.msg_records = 2u * (uint32_t)(jb.E_pad * Zh) + (uint32_t)kMsgTail;
+            bw.row_pad = jb.row_pad;
+            bw.E_pad = jb.E_pad;
+            bw.groups = jb.groups;
+            bw.wq = jb.wq;
+            bw.w_iters = jb.w_iters;
+            bw.w_stride = jb.w_stride;
+            bw.rows = jb.rows;
+            bw.n_cols = jb.n_cols;
+            bw.kb = jb.kb;
+            bw.Z = Zh;
+            bw.E = jb.E;
+            bw.max_iter = max_iter;
+            bw.early_exit = early_exit;
+            bw.beta = beta;
+            bw.offset = offset;
+            decode_rp<WMAX>(bw, smem, (crow_t)jb.row_ptr, (cmeta_t)jb.meta_rp);
+        } else if (!wave_task || wv < tk.nwave) {
             int job = tk.job, first = tk.first, n = tk.n;
             if (wave_task) {
                 const WaveTask wt = waves[tk.first + wv];
@@ -2010,23 +2043,30 @@ hipError_t launch_decode_batch(const BatchLaunch &b, hipStream_t stream) {
             return e;
         }
     }
-    static std::once_flag attr_once[2];  // once per process, also under concurrent calls
-    const void *fn = b.wmax <= 10 ? reinterpret_cast<const void *>(&decode_batch_kernel<10>)
-                                  : reinterpret_cast<const void *>(&decode_batch_kernel<20>);
-    std::call_once(attr_once[b.wmax <= 10 ? 0 : 1], [fn] {
+    static std::once_flag attr_once[4];  // once per process, also under concurrent calls
+    const int vi = (b.wmax <= 10 ? 0 : 1) + (b.row_pairs ? 2 : 0);
+    const void *fns[4] = {reinterpret_cast<const void *>(&decode_batch_kernel<10, false>),
+                          reinterpret_cast<const void *>(&decode_batch_kernel<20, false>),
+                          reinterpret_cast<const void *>(&decode_batch_kernel<10, true>),
+                          reinterpret_cast<const void *>(&decode_batch_kernel<20, true>)};
+    const void *fn = fns[vi];
+    std::call_once(attr_once[vi], [fn] {
         const hipError_t ea =
             hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes());
         if (ea != hipSuccess) note_hip_error("hipFuncSetAttribute(decode_batch_kernel)", ea);
     });
     (void)hipGetLastError();
-    if (b.wmax <= 10)
-        hipLaunchKernelGGL(decode_batch_kernel<10>, dim3(b.grid), dim3(b.lanes), b.lds, stream,
-                           b.tasks, b.jobs, b.waves, b.n_tasks, b.counter, b.msg, b.msg_per_block,
-                           b.wave_lds, b.wave_msg, b.max_iter, b.early_exit, b.beta, b.offset);
-    else
-        hipLaunchKernelGGL(decode_batch_kernel<20>, dim3(b.grid), dim3(b.lanes), b.lds, stream,
-                           b.tasks, b.jobs, b.waves, b.n_tasks, b.counter, b.msg, b.msg_per_block,
-                           b.wave_lds, b.wave_msg, b.max_iter, b.early_exit, b.beta, b.offset);
+#define LDPC_BATCH_ARGS                                                                          \
+    b.tasks, b.jobs, b.waves, b.n_tasks, b.counter, b.msg, b.msg_per_block, b.wave_lds,         \
+        b.wave_msg, b.max_iter, b.early_exit, b.beta, b.offset
+    const dim3 grid(b.grid), block(b.lanes);
+    switch (vi) {
+        case 0: hipLaunchKernelGGL((decode_batch_kernel<10, false>), grid, block, b.lds, stream, LDPC_BATCH_ARGS); break;
+        case 1: hipLaunchKernelGGL((decode_batch_kernel<20, false>), grid, block, b.lds, stream, LDPC_BATCH_ARGS); break;
+        case 2: hipLaunchKernelGGL((decode_batch_kernel<10, true>), grid, block, b.lds, stream, LDPC_BATCH_ARGS); break;
+        default: hipLaunchKernelGGL((decode_batch_kernel<20, true>), grid, block, b.lds, stream, LDPC_BATCH_ARGS); break;
+    }
+#undef LDPC_BATCH_ARGS
     e = hipGetLastError();
     if (e != hipSuccess) note_hip_error("launch decode_batch_kernel", e);
     return e;

@@ -784,6 +784,7 @@ int batch_jobs(const ldpc_job *jobs, int n_jobs, std::vector<BatchJob> &bj,
         b.E_pad = padded_row_ptr(g)[jb.rows];
         b.groups = layer_groups(g.row_ptr.data(), g.col.data(), jb.rows);
         b.meta = t->meta_i8;
+        b.meta_rp = t->meta_i8rp;
         b.wq = jb.wq;
         b.w_iters = jb.wq ? jb.wq_iters : 0;
         b.w_stride = jb.rows;

@@ -118,13 +118,22 @@ struct BatchJob {
     const int32_t *row_ptr;
     const int32_t *row_pad;
     const uint32_t *meta;
+    const uint32_t *meta_rp;  // row-pair metadata (pack_meta_i8rp)
     const uint8_t *wq;
     uint64_t groups;
     int w_iters, w_stride;
     int rows, n_cols, kb, Z, E, E_pad, slots;
 };
+// Lifts above this decode in the batch kernel as row pairs, one codeword
+// per task (see decode_rp), when the launch's tasks all fit the device's
+// CUs at once: a codeword pair's 2Z lanes would put two waves on some SIMDs
+// of a CU, and a single codeword leaves its workgroup as soon as it
+// converges.
+constexpr int kBatchRowPairZ = 256;
 // A task is either codewords [first, first + n) of job `job` for the whole
-// workgroup (nwave = 0), or a bundle of nwave wave tasks waves[first ..
+// workgroup (nwave = 0), codeword `first` of job `job` as row pairs on the
+// workgroup's first Z/2 lanes (nwave = -1, n = 1), or a bundle of nwave
+// wave tasks waves[first ..
 // first + nwave), one per wave of the workgroup (small lifts: a codeword
 // pair of Z <= 64 fits one wave, so each wave decodes its own shape).
 struct BatchTask {
@@ -149,6 +158,8 @@ struct BatchLaunch {
     int grid, lanes, lds, wmax;
     int counter_zeroed;       // 1: *counter is already zero on the stream (no
                               // reset kernel before the decode)
+    int row_pairs;            // 1: the tasks include row-pair tasks (the
+                              // kernel variant that decodes them)
 };
 hipError_t launch_decode_batch(const BatchLaunch &b, hipStream_t stream);
 
@@ -188,6 +199,7 @@ struct TaskSet {
     std::vector<BatchTask> tasks;
     std::vector<WaveTask> waves;
     int lds = 0, msg_per_block = 0, wave_lds = 0, wave_msg = 0;
+    bool row_pairs = false;  // some tasks are row-pair tasks (nwave = -1)
 };
 int build_tasks(const std::vector<BatchJob> &jobs, const std::vector<int> &job_cw, int lds_cap,
                 TaskSet &ts);

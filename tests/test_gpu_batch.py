@@ -51,17 +51,55 @@ def test_mixed_batch_equals_alone_and_oracle(lib):
             assert (a == b).all(), (gr.bg, gr.Z, gr.rows)
 
 
+def _shape_jobs(ldpc, shapes, ebn0, seed):
+    """Jobs of (bg, Z, rows, n) with seeded channel batches, and the batches."""
+    from synth import make_batch
+    jobs, batches = [], []
+    for i, (bg, Z, rows, n) in enumerate(shapes):
+        ldpc.register(make_graph(bg, Z))
+        b = make_batch(make_graph(bg, Z, rows), n, ebn0, data_seed=seed + i)
+        batches.append(b)
+        jobs.append(ldpc.BatchJob(torch.from_numpy(b.q).cuda(), bg, Z, rows))
+    return jobs, batches
+
+
+@pytest.mark.parametrize("shapes,ebn0", [
+    # a few codewords: lifts above 256 as one-codeword row-pair tasks
+    ([(1, 384, 46, 3), (2, 320, 20, 2), (1, 352, 10, 1), (2, 64, 42, 5), (1, 128, 30, 4),
+      (2, 288, 42, 2)], 1.5),
+    # more Z = 384 codewords than CUs: codeword-pair tasks
+    ([(2, 384, 6, 300), (1, 32, 20, 7)], 2.5),
+])
+def test_row_pair_and_pair_tasks_equal_oracle(lib, shapes, ebn0):
+    jobs, batches = _shape_jobs(lib, shapes, ebn0, 900)
+    print(f"[batch] shapes {shapes}", flush=True)
+    lib.decode_batch(jobs)
+    for (bg, Z, rows, n), jb, b in zip(shapes, jobs, batches):
+        ref = oracle.decode_i8(library_graph(bg, Z, rows), b.q, n_threads=8)
+        got = (jb.out_bits.cpu().numpy(), jb.out_iters.cpu().numpy(),
+               jb.out_ok.cpu().numpy().astype(bool))
+        for a, r in zip(got, ref[:3]):
+            assert (a == r).all(), (bg, Z, rows, n)
+
+
 def test_plan_graph_replays_match_eager(lib):
     from synth import make_batch
     groups = make_mixed(120, 1.75, seed=12)
     jobs = _jobs(lib, groups)
     plan = lib.Plan(jobs, graph=True, autotune=True)
     info = plan.info()
-    # lifts above 64: one task per 2*floor(384/Z) codewords of a shape; lifts
-    # up to 64: one wave task per 2*floor(64/Z), six wave tasks to a bundle
-    big = sum(-(-len(gr.indices) // (2 * (384 // gr.Z))) for gr in groups if gr.Z > 64)
+    # lifts above 64: one task per 2*floor(384/Z) codewords of a shape (at
+    # lifts above 256 one row-pair task per codeword instead, when every
+    # task then fits a CU of its own); lifts up to 64: one wave task per
+    # 2*floor(64/Z), six wave tasks to a bundle
+    n_cus = torch.cuda.get_device_properties(0).multi_processor_count
+    pair = sum(-(-len(gr.indices) // (2 * (384 // gr.Z))) for gr in groups if gr.Z > 64)
+    rows = sum(len(gr.indices) if gr.Z > 256 else -(-len(gr.indices) // (2 * (384 // gr.Z)))
+               for gr in groups if gr.Z > 64)
     small = sum(-(-len(gr.indices) // (2 * (64 // gr.Z))) for gr in groups if gr.Z <= 64)
-    assert info["n_tasks"] == big + -(-small // 6), info
+    bundles = -(-small // 6)
+    big = rows if rows > pair and rows + bundles <= n_cus else pair
+    assert info["n_tasks"] == big + bundles, info
     assert info["grid"] >= 1 and info["tuned_ms"] > 0
     for rep in range(3):
         # refill every job's input buffer in place with fresh data of its shape
