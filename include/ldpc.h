@@ -313,9 +313,10 @@ int ldpc_tune(const ldpc_args *a, ldpc_tuning *out);
  * 2*floor(384/Z) codewords of one job, or, for lifts up to 64, a bundle of
  * six wave tasks (one per 64-lane wave, each up to 2*floor(64/Z) codewords
  * of its own job), so small shapes with few codewords do not leave most of
- * a workgroup idle; codewords of lifts above 256 are one task each (check
- * rows u and u + Z/2 per lane) when every task of the launch then still
- * gets a CU of its own. Results are identical to decoding each job alone
+ * a workgroup idle. A job with `split` set is cut finer, for latency when
+ * the launch has the device to itself: one codeword pair per task (the
+ * workgroup's other pair slots idle), and for lifts above 256 one codeword
+ * per task as check rows u and u + Z/2 per lane. Results are identical to decoding each job alone
  * (ldpc_decode_ex with the same options). Lifts up to 384, row weights up
  * to 20.
  */
@@ -327,6 +328,7 @@ typedef struct ldpc_job {
     uint8_t *out_ok;
     const uint8_t *wq;
     int wq_iters;
+    int split;              /* 1: small tasks (see above); 0: full tasks */
 } ldpc_job;
 
 /* One-shot batch decode: builds a transient plan, launches it on `stream`,

@@ -62,28 +62,6 @@ hipError_t size_messages(Plan *p, int grid) {
 int build_tasks(const std::vector<BatchJob> &jobs, const std::vector<int> &job_cw, int lds_cap,
                 TaskSet &ts) {
     auto cost = [&](int j) { return (long)jobs[j].E * jobs[j].Z; };
-    // Row-pair tasks (one codeword each) for lifts above kBatchRowPairZ when
-    // every task of the launch still gets a CU of its own (a latency-bound
-    // launch, e.g. a served block); larger batches keep codeword pairs,
-    // whose full workgroups make more of each CU.
-    long pair_tasks = 0, rp_tasks = 0, bundles = 0;
-    for (size_t j = 0; j < jobs.size(); ++j) {
-        const BatchJob &jb = jobs[j];
-        if (jb.Z <= kWaveLanes) {
-            bundles += (job_cw[j] + 2 * (kWaveLanes / jb.Z) - 1) / (2 * (kWaveLanes / jb.Z));
-        } else {
-            const long pt = (job_cw[j] + jb.slots - 1) / jb.slots;
-            pair_tasks += pt;
-            rp_tasks += jb.Z > kBatchRowPairZ ? job_cw[j] : pt;
-        }
-    }
-    int dev = 0, cus = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-        cus = 0;
-    const bool row_pairs =
-        rp_tasks > pair_tasks && rp_tasks + (bundles + kWavesPerBlock - 1) / kWavesPerBlock <= cus;
-    ts.row_pairs = row_pairs;
     std::vector<WaveTask> waves;
     for (size_t j = 0; j < jobs.size(); ++j) {
         const BatchJob &jb = jobs[j];
@@ -95,19 +73,22 @@ int build_tasks(const std::vector<BatchJob> &jobs, const std::vector<int> &job_c
             ts.wave_msg = std::max(ts.wave_msg, pairs * jb.E_pad * jb.Z);
             for (int f = 0; f < job_cw[j]; f += slots)
                 waves.push_back(WaveTask{(int)j, f, std::min(slots, job_cw[j] - f), 0});
-        } else if (row_pairs && jb.Z > kBatchRowPairZ) {
+        } else if (jb.split && jb.Z > kBatchRowPairZ) {
             // one codeword per task on Z/2 lanes (row pairs)
             const int Zh = jb.Z / 2;
             ts.lds = std::max(ts.lds, lds_bytes_i8_pair_post(jb.n_cols, Zh) + lds_flags_bytes_i8(1));
             ts.msg_per_block = std::max(ts.msg_per_block, jb.E_pad * Zh);
             for (int f = 0; f < job_cw[j]; ++f) ts.tasks.push_back(BatchTask{(int)j, f, 1, -1});
+            ts.row_pairs = true;
         } else {
-            const int pairs = jb.slots / 2;
+            // jb.slots codewords per task, or one pair per task when split
+            // (the workgroup's other pair slots stay idle)
+            const int pairs = jb.slots / 2, per = jb.split ? 2 : jb.slots;
             ts.lds = std::max(ts.lds, pairs * lds_bytes_i8_pair_post(jb.n_cols, jb.Z) +
                                           lds_flags_bytes_i8(pairs));
             ts.msg_per_block = std::max(ts.msg_per_block, pairs * jb.E_pad * jb.Z);
-            for (int f = 0; f < job_cw[j]; f += jb.slots)
-                ts.tasks.push_back(BatchTask{(int)j, f, std::min(jb.slots, job_cw[j] - f), 0});
+            for (int f = 0; f < job_cw[j]; f += per)
+                ts.tasks.push_back(BatchTask{(int)j, f, std::min(per, job_cw[j] - f), 0});
         }
     }
     // Longest first (larger lifts and more rows), so that the tail of the

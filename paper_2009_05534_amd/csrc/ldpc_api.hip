@@ -794,6 +794,7 @@ int batch_jobs(const ldpc_job *jobs, int n_jobs, std::vector<BatchJob> &bj,
         b.Z = g.Z;
         b.E = E;
         b.slots = 2 * (kBatchLanes / g.Z);
+        b.split = jb.split ? 1 : 0;
         bj.push_back(b);
         job_cw.push_back(jb.n_cw);
     }

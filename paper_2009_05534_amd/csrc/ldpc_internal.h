@@ -123,12 +123,13 @@ struct BatchJob {
     uint64_t groups;
     int w_iters, w_stride;
     int rows, n_cols, kb, Z, E, E_pad, slots;
+    int split;                // small tasks: one pair, or one codeword as row
+                              // pairs above kBatchRowPairZ
 };
-// Lifts above this decode in the batch kernel as row pairs, one codeword
-// per task (see decode_rp), when the launch's tasks all fit the device's
-// CUs at once: a codeword pair's 2Z lanes would put two waves on some SIMDs
-// of a CU, and a single codeword leaves its workgroup as soon as it
-// converges.
+// Lifts above this decode in the batch kernel's small tasks as row pairs,
+// one codeword per task (see decode_rp): a codeword pair's 2Z lanes would
+// put two waves on some SIMDs of a CU, and a single codeword leaves its
+// workgroup as soon as it converges.
 constexpr int kBatchRowPairZ = 256;
 // A task is either codewords [first, first + n) of job `job` for the whole
 // workgroup (nwave = 0), codeword `first` of job `job` as row pairs on the

@@ -58,6 +58,7 @@ class Job(ctypes.Structure):
         ("bg", ctypes.c_int), ("Z", ctypes.c_int), ("rows", ctypes.c_int), ("n_cw", ctypes.c_int),
         ("llr", ctypes.c_void_p), ("out_bits", ctypes.c_void_p), ("out_iters", ctypes.c_void_p),
         ("out_ok", ctypes.c_void_p), ("wq", ctypes.c_void_p), ("wq_iters", ctypes.c_int),
+        ("split", ctypes.c_int),
     ]
 
 
@@ -352,13 +353,14 @@ class BatchJob:
     device buffers (outputs allocated here unless given)."""
 
     def __init__(self, llr, bg: int, Z: int, rows: int, weights=None, out_bits=None,
-                 out_iters=None, out_ok=None):
+                 out_iters=None, out_ok=None, split: bool = False):
         import torch
         K, T, Nc, E = query(bg, Z, rows)
         n = int(llr.shape[0])
         _require(llr, (n, T), 1, "llr")
         dev = llr.device
         self.bg, self.Z, self.rows, self.n = bg, Z, rows, n
+        self.split = bool(split)  # small tasks (one pair / one codeword as row pairs)
         self.llr = llr
         self.out_bits = out_bits if out_bits is not None else torch.empty(
             (n, K // 8), dtype=torch.uint8, device=dev)
@@ -379,7 +381,8 @@ class BatchJob:
         return Job(self.bg, self.Z, self.rows, self.n, self.llr.data_ptr(),
                    self.out_bits.data_ptr(), self.out_iters.data_ptr(), self.out_ok.data_ptr(),
                    self.weights.data_ptr() if self.weights is not None else None,
-                   int(self.weights.shape[0]) if self.weights is not None else 0)
+                   int(self.weights.shape[0]) if self.weights is not None else 0,
+                   int(self.split))
 
 
 def _job_array(jobs):

@@ -97,7 +97,7 @@ class Server:
     def __init__(self, weights_bg1: np.ndarray | None = None, n_slots: int = 4,
                  mem_budget: int = 256 << 20, max_iter: int = 10, max_blocks_per_launch: int = 256,
                  device: str = "cuda:0", learned_shapes=None, speculate=False,
-                 speculate_queue: int = 4):
+                 speculate_queue: int = 4, split_codewords: int = 64):
         """learned_shapes: the (Z, rows) BG1 shapes the weights apply to (the
         shape they were trained on); None applies them to every BG1 block
         (first `rows` columns). speculate: run the plain pass of learned
@@ -107,7 +107,13 @@ class Server:
         On the benchmark trace at 1,000 blocks/s it takes the fallback
         blocks from two launches to one but raises the other learned
         blocks' median latency from 0.44 to 0.54 ms (they wait for the
-        plain pass), so fewer blocks meet the deadline."""
+        plain pass), so fewer blocks meet the deadline. split_codewords:
+        while the codewords in flight and waiting number at most this many
+        (the default, 64, is a quarter of an MI355X's CUs), launches ask
+        for small tasks (the batch jobs' split flag: one codeword pair per
+        task, one codeword as row pairs at lifts above 256), which lowers
+        their latency on a lightly loaded device; under load launches keep
+        full tasks, which make more of each CU."""
         import torch
         from . import ldpc
         self.ldpc = ldpc
@@ -125,6 +131,7 @@ class Server:
             raise ValueError("speculate must be True, False or 'auto'")
         self.speculate = speculate
         self.speculate_queue = speculate_queue
+        self.split_codewords = split_codewords
 
     def _weights(self, bg: int, rows: int, Z: int | None = None):
         if self._w_full is None or bg != 1:
@@ -177,6 +184,13 @@ class Server:
         if spec and not plain:
             jobs += [b._cjob[True] for b in batch if b._plain is not None]
         return jobs
+
+    def _set_split(self, queue, plain: bool, spec: bool, split: bool):
+        """Sets the split flag of the job records _jobs would launch."""
+        for b in queue:
+            b._cjob[plain].split = int(split)
+            if spec and not plain and b._plain is not None:
+                b._cjob[True].split = int(split)
 
     def _admit(self, queue, plain: bool, room: int, spec: bool = False):
         """The longest earliest-deadline prefix of `queue` (at most
@@ -258,7 +272,16 @@ class Server:
                     spec = not plain and (self.speculate is True or (
                         self.speculate == "auto" and not fallback
                         and len(queue) <= self.speculate_queue))
+                    # small tasks when this launch has the device to itself;
+                    # full ones if the split footprint does not fit
+                    load = sum(b.n_cw for f in in_flight for b in f[2]) + sum(
+                        b.n_cw for q in (fallback, pending) for b in q)
+                    split = load <= self.split_codewords
+                    self._set_split(queue, plain, spec, split)
                     k, mem = self._admit(queue, plain, self.mem_budget - mem_used, spec)
+                    if k == 0 and split:
+                        self._set_split(queue, plain, spec, False)
+                        k, mem = self._admit(queue, plain, self.mem_budget - mem_used, spec)
                     if k == 0:
                         break
                     batch = queue[:k]

@@ -51,7 +51,7 @@ def test_mixed_batch_equals_alone_and_oracle(lib):
             assert (a == b).all(), (gr.bg, gr.Z, gr.rows)
 
 
-def _shape_jobs(ldpc, shapes, ebn0, seed):
+def _shape_jobs(ldpc, shapes, ebn0, seed, split=False):
     """Jobs of (bg, Z, rows, n) with seeded channel batches, and the batches."""
     from synth import make_batch
     jobs, batches = [], []
@@ -59,20 +59,26 @@ def _shape_jobs(ldpc, shapes, ebn0, seed):
         ldpc.register(make_graph(bg, Z))
         b = make_batch(make_graph(bg, Z, rows), n, ebn0, data_seed=seed + i)
         batches.append(b)
-        jobs.append(ldpc.BatchJob(torch.from_numpy(b.q).cuda(), bg, Z, rows))
+        jobs.append(ldpc.BatchJob(torch.from_numpy(b.q).cuda(), bg, Z, rows, split=split))
     return jobs, batches
 
 
-@pytest.mark.parametrize("shapes,ebn0", [
-    # a few codewords: lifts above 256 as one-codeword row-pair tasks
-    ([(1, 384, 46, 3), (2, 320, 20, 2), (1, 352, 10, 1), (2, 64, 42, 5), (1, 128, 30, 4),
-      (2, 288, 42, 2)], 1.5),
-    # more Z = 384 codewords than CUs: codeword-pair tasks
-    ([(2, 384, 6, 300), (1, 32, 20, 7)], 2.5),
+SHAPES_A = [(1, 384, 46, 3), (2, 320, 20, 2), (1, 352, 10, 1), (2, 64, 42, 5), (1, 128, 30, 7),
+            (2, 288, 42, 2), (2, 192, 20, 3)]
+
+
+@pytest.mark.parametrize("shapes,ebn0,split", [
+    # small tasks: one pair per task, lifts above 256 as one-codeword
+    # row-pair tasks, next to wave tasks
+    (SHAPES_A, 1.5, True),
+    (SHAPES_A, 1.5, False),
+    # many Z = 384 codewords, full codeword-pair tasks and small ones
+    ([(2, 384, 6, 300), (1, 32, 20, 7)], 2.5, False),
+    ([(2, 384, 6, 300), (1, 32, 20, 7)], 2.5, True),
 ])
-def test_row_pair_and_pair_tasks_equal_oracle(lib, shapes, ebn0):
-    jobs, batches = _shape_jobs(lib, shapes, ebn0, 900)
-    print(f"[batch] shapes {shapes}", flush=True)
+def test_split_and_full_tasks_equal_oracle(lib, shapes, ebn0, split):
+    jobs, batches = _shape_jobs(lib, shapes, ebn0, 900, split)
+    print(f"[batch] shapes {shapes} split={split}", flush=True)
     lib.decode_batch(jobs)
     for (bg, Z, rows, n), jb, b in zip(shapes, jobs, batches):
         ref = oracle.decode_i8(library_graph(bg, Z, rows), b.q, n_threads=8)
@@ -82,23 +88,36 @@ def test_row_pair_and_pair_tasks_equal_oracle(lib, shapes, ebn0):
             assert (a == r).all(), (bg, Z, rows, n)
 
 
+def test_split_plan_graph_replays(lib):
+    # small tasks (row-pair tasks included) captured in a graph and replayed
+    jobs, batches = _shape_jobs(lib, SHAPES_A, 1.5, 950, split=True)
+    plan = lib.Plan(jobs, graph=True, autotune=False)
+    refs = [oracle.decode_i8(library_graph(bg, Z, rows), b.q, n_threads=8)
+            for (bg, Z, rows, n), b in zip(SHAPES_A, batches)]
+    for rep in range(3):
+        for jb in jobs:
+            jb.out_bits.zero_()
+            jb.out_iters.zero_()
+        plan.launch()
+        torch.cuda.synchronize()
+        _ = torch.ones(1000, device="cuda").sum().item()  # eager work between replays
+        for (bg, Z, rows, n), jb, ref in zip(SHAPES_A, jobs, refs):
+            assert (jb.out_bits.cpu().numpy() == ref[0]).all(), (rep, bg, Z, rows)
+            assert (jb.out_iters.cpu().numpy() == ref[1]).all(), (rep, bg, Z, rows)
+    plan.close()
+
+
 def test_plan_graph_replays_match_eager(lib):
     from synth import make_batch
     groups = make_mixed(120, 1.75, seed=12)
     jobs = _jobs(lib, groups)
     plan = lib.Plan(jobs, graph=True, autotune=True)
     info = plan.info()
-    # lifts above 64: one task per 2*floor(384/Z) codewords of a shape (at
-    # lifts above 256 one row-pair task per codeword instead, when every
-    # task then fits a CU of its own); lifts up to 64: one wave task per
-    # 2*floor(64/Z), six wave tasks to a bundle
-    n_cus = torch.cuda.get_device_properties(0).multi_processor_count
-    pair = sum(-(-len(gr.indices) // (2 * (384 // gr.Z))) for gr in groups if gr.Z > 64)
-    rows = sum(len(gr.indices) if gr.Z > 256 else -(-len(gr.indices) // (2 * (384 // gr.Z)))
-               for gr in groups if gr.Z > 64)
+    # lifts above 64: one task per 2*floor(384/Z) codewords of a shape; lifts
+    # up to 64: one wave task per 2*floor(64/Z), six wave tasks to a bundle
+    big = sum(-(-len(gr.indices) // (2 * (384 // gr.Z))) for gr in groups if gr.Z > 64)
     small = sum(-(-len(gr.indices) // (2 * (64 // gr.Z))) for gr in groups if gr.Z <= 64)
     bundles = -(-small // 6)
-    big = rows if rows > pair and rows + bundles <= n_cus else pair
     assert info["n_tasks"] == big + bundles, info
     assert info["grid"] >= 1 and info["tuned_ms"] > 0
     for rep in range(3):
