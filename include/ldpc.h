@@ -199,18 +199,21 @@ typedef struct ldpc_args {
                                LDPC_PAIR_ROWS (2): check rows u and u + Z/2
                                of one codeword (Z/2 lanes per codeword,
                                cw_per_block codewords per workgroup, default
-                               1; the static schedule, one lane per row and
+                               1, or 2 below Z = 256 where Z/2 leaves half a
+                               wave; the static schedule, one lane per row and
                                device-placed messages, else LDPC_EINVAL): for
                                small batches of large lifts, where a pair's
                                2Z lanes would put two waves on some of a
                                CU's SIMDs, and for early exit (one codeword
                                per workgroup leaves its CU as soon as it
                                converges). LDPC_PAIR_AUTO (0, the default):
-                               row pairs when Z > 256, early exit is on or
-                               n_cw is at most the device's CU count, one
-                               lane per row, the static schedule,
-                               cw_per_block 0 and message placement AUTO;
-                               else codeword pairs.
+                               with one lane per row, the static schedule,
+                               cw_per_block 0 and message placement AUTO,
+                               row pairs for early exit at Z > 256 and at
+                               Z = 128, 192, 256 (two codewords per
+                               workgroup at 192, else one), and for n_cw at
+                               most the device's CU count at Z > 256; else
+                               codeword pairs.
                                Results are identical under both. */
     void *stream;
 } ldpc_args;

@@ -153,14 +153,15 @@ int pow2_bucket(int n) {
 
 // Whether an int8 call decodes with the row-pair kernel: on request
 // (LDPC_PAIR_ROWS; the static schedule, one lane per row and device-placed
-// messages, else the caller gets LDPC_EINVAL), or by default at lifts
-// above 256 (one lane per row, the static schedule, the default packing
-// and message placement) when either there are no more codewords than CUs
-// (a codeword pair's 2Z lanes would put two waves on some SIMDs of a CU,
-// where one codeword's Z/2 lanes leave every wave a SIMD of its own) or
-// early exit is on (one codeword per workgroup leaves the CU as soon as
-// it converges, where a workgroup of two codeword pairs runs until the
-// slowest of its four has). Sets g_msg when a request cannot be met.
+// messages, else the caller gets LDPC_EINVAL), or by default (one lane per
+// row, the static schedule, the default packing and message placement)
+// when early exit is on at lifts above 256 or at 128, 192 and 256 (one or
+// two codewords per workgroup leave the CU as soon as they converge, where
+// a workgroup of codeword pairs runs until the slowest of its 2*floor(768/Z)
+// codewords has), and at lifts above 256 for at most one codeword per CU (a
+// codeword pair's 2Z lanes would put two waves on some SIMDs of a CU, where
+// one codeword's Z/2 lanes leave every wave a SIMD of its own). Sets g_msg
+// when a request cannot be met.
 bool use_row_pairs(const ldpc_args *a, int Z) {
     const bool can = a->schedule == LDPC_SCHED_STATIC && a->lanes_per_row <= 1 &&
                      a->msg_placement != LDPC_MSG_LDS;
@@ -171,10 +172,11 @@ bool use_row_pairs(const ldpc_args *a, int Z) {
                      "messages");
         return can;
     }
-    if (a->pairing != LDPC_PAIR_AUTO || !can || Z <= 256 || a->cw_per_block != 0 ||
+    if (a->pairing != LDPC_PAIR_AUTO || !can || a->cw_per_block != 0 ||
         a->msg_placement != LDPC_MSG_AUTO)
         return false;
-    if (a->early_exit) return true;
+    if (a->early_exit && (Z > 256 || (Z >= 128 && Z % 64 == 0))) return true;
+    if (Z <= 256) return false;
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
@@ -294,7 +296,9 @@ int prepare_decode(const ldpc_args *a0, bool upload, DecodeLaunch &p, bool &msg_
         p.rowpair = 1;
         p.meta = meta_rp;
         const int per_cw = lds_bytes_i8_pair_post(p.n_cols, Zh) + 16;
-        cpw = a->cw_per_block > 0 ? a->cw_per_block : 1;
+        // default: one codeword per workgroup, two where Z/2 leaves half a
+        // wave (Z = 192: three full waves) below the largest lifts
+        cpw = a->cw_per_block > 0 ? a->cw_per_block : (Zh % 64 == 32 && p.Z < 256 ? 2 : 1);
         cpw = std::min(cpw, (lds_cap - 8) / per_cw);
         cpw = std::min(cpw, 768 / Zh);
         cpw = std::min(cpw, a->n_cw);
