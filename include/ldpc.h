@@ -199,8 +199,9 @@ typedef struct ldpc_args {
                                LDPC_PAIR_ROWS (2): check rows u and u + Z/2
                                of one codeword (Z/2 lanes per codeword,
                                cw_per_block codewords per workgroup, default
-                               1, or 2 below Z = 256 where Z/2 leaves half a
-                               wave; the static schedule, one lane per row and
+                               up to Z = 128 the most that fit one wave, at
+                               most 4; 2 to Z = 256; 1 above); the static
+                               schedule, one lane per row and
                                device-placed messages, else LDPC_EINVAL): for
                                small batches of large lifts, where a pair's
                                2Z lanes would put two waves on some of a
@@ -209,11 +210,9 @@ typedef struct ldpc_args {
                                converges). LDPC_PAIR_AUTO (0, the default):
                                with one lane per row, the static schedule,
                                cw_per_block 0 and message placement AUTO,
-                               row pairs for early exit at Z > 256 and at
-                               Z = 128, 192, 256 (two codewords per
-                               workgroup at 192, else one), and for n_cw at
-                               most the device's CU count at Z > 256; else
-                               codeword pairs.
+                               row pairs for early exit at Z >= 16 and for
+                               n_cw at most the device's CU count at
+                               Z > 256; else codeword pairs.
                                Results are identical under both. */
     void *stream;
 } ldpc_args;

@@ -155,13 +155,27 @@ int pow2_bucket(int n) {
 // (LDPC_PAIR_ROWS; the static schedule, one lane per row and device-placed
 // messages, else the caller gets LDPC_EINVAL), or by default (one lane per
 // row, the static schedule, the default packing and message placement)
-// when early exit is on at lifts above 256 or at 128, 192 and 256 (one or
-// two codewords per workgroup leave the CU as soon as they converge, where
-// a workgroup of codeword pairs runs until the slowest of its 2*floor(768/Z)
-// codewords has), and at lifts above 256 for at most one codeword per CU (a
-// codeword pair's 2Z lanes would put two waves on some SIMDs of a CU, where
-// one codeword's Z/2 lanes leave every wave a SIMD of its own). Sets g_msg
-// when a request cannot be met.
+// when early exit is on at lifts from 16 (a workgroup of at most four
+// codewords leaves its CU as soon as they converge, where a workgroup of
+// codeword pairs runs until the slowest of its 2*floor(768/Z) codewords has:
+// half to two thirds of the time at lifts 32 to 128, 5 to 20 % less at
+// 208 to 320, within 4 % either way at 16, 24 and 144), and at lifts above
+// 256 for at most one codeword per CU (a codeword pair's 2Z lanes would put
+// two waves on some SIMDs of a CU, where one codeword's Z/2 lanes leave
+// every wave a SIMD of its own). Sets g_msg when a request cannot be met.
+// Default codewords per row-pair workgroup: up to Z = 128 the most whose
+// Z/2 lanes fit in one wave, at most four (no barrier then couples waves;
+// four at Z = 16 to 32, two to 64, one to 128), two to Z = 256 and one above.
+// Measured on 4,096-codeword early-exit batches: fuller waves or larger
+// workgroups were not faster (at Z = 16 four codewords per wave beat eight;
+// at Z = 208 three per workgroup were a third slower than two).
+int row_pair_default_cpw(int Z) {
+    const int Zh = Z / 2;
+    if (Z > 256) return 1;
+    if (Z > 128) return 2;
+    return std::max(1, std::min(4, 64 / Zh));
+}
+
 bool use_row_pairs(const ldpc_args *a, int Z) {
     const bool can = a->schedule == LDPC_SCHED_STATIC && a->lanes_per_row <= 1 &&
                      a->msg_placement != LDPC_MSG_LDS;
@@ -175,7 +189,7 @@ bool use_row_pairs(const ldpc_args *a, int Z) {
     if (a->pairing != LDPC_PAIR_AUTO || !can || a->cw_per_block != 0 ||
         a->msg_placement != LDPC_MSG_AUTO)
         return false;
-    if (a->early_exit && (Z > 256 || (Z >= 128 && Z % 64 == 0))) return true;
+    if (a->early_exit && Z >= 16) return true;
     if (Z <= 256) return false;
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -296,9 +310,7 @@ int prepare_decode(const ldpc_args *a0, bool upload, DecodeLaunch &p, bool &msg_
         p.rowpair = 1;
         p.meta = meta_rp;
         const int per_cw = lds_bytes_i8_pair_post(p.n_cols, Zh) + 16;
-        // default: one codeword per workgroup, two where Z/2 leaves half a
-        // wave (Z = 192: three full waves) below the largest lifts
-        cpw = a->cw_per_block > 0 ? a->cw_per_block : (Zh % 64 == 32 && p.Z < 256 ? 2 : 1);
+        cpw = a->cw_per_block > 0 ? a->cw_per_block : row_pair_default_cpw(p.Z);
         cpw = std::min(cpw, (lds_cap - 8) / per_cw);
         cpw = std::min(cpw, 768 / Zh);
         cpw = std::min(cpw, a->n_cw);

@@ -86,6 +86,27 @@ def test_auto_pairing_equals_codeword_pairs():
     assert_i8_equal(auto, oracle_i8(g, b.q))
 
 
+@pytest.mark.parametrize("bg,Z,rows,n", [
+    (1, 16, 46, 23),   # four codewords per workgroup by default, ragged end
+    (1, 24, 46, 13),   # four: 48 of 64 lanes
+    (2, 40, 42, 8),    # three: 60 of 64 lanes
+    (2, 56, 30, 5),    # two: 56 of 64 lanes
+    (1, 72, 46, 11),   # one: 36 of 64 lanes
+    (2, 144, 42, 9),   # two: 144 lanes in three waves
+    (1, 208, 46, 5),   # two: 208 lanes in four waves, ragged end
+    (1, 320, 46, 3),   # one: 160 lanes in three waves
+])
+def test_auto_row_pairs_other_lifts(bg, Z, rows, n):
+    # early-exit decodes take row pairs by default from Z = 16; lifts that
+    # are not powers of two leave partial waves
+    g = _graph(bg, Z, rows)
+    b = make_batch(g, n, 1.5, data_seed=800 + Z)
+    print(f"[rowpair auto] bg={bg} Z={Z} rows={rows} n={n}", flush=True)
+    auto = gpu_decode(bg, Z, rows, b.q)
+    assert_i8_equal(auto, oracle_i8(g, b.q))
+    assert_i8_equal(auto, gpu_decode(bg, Z, rows, b.q, pairing="codewords"))
+
+
 def test_rowpair_noalloc():
     g = _graph(1, 384, 46)
     b = make_batch(g, 3, 1.5, data_seed=74)

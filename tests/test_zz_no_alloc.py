@@ -82,8 +82,9 @@ def test_noalloc_refuses_oversize_and_cold_graph():
     ldpc.decode(torch.from_numpy(b.q).cuda(), 1, 384, g.M)  # uploads the tables
     torch.cuda.synchronize()
     K, T, Nc, E = ldpc.query(1, 384, g.M)
-    # 2 * ceil(n/2) * E_pad * Z + 16 bytes of int8 messages: 515 codewords
-    # need 258 pairs, beyond the 64 MiB scratch (257 pairs fit)
+    # n * E_pad * Z + 16 bytes of int8 messages with row pairs (the default
+    # here: early exit), 2 * ceil(n/2) * E_pad * Z + 16 with codeword pairs:
+    # 515 codewords need more than the 64 MiB scratch, 514 fit exactly
     n = 515
     llr = torch.zeros((n, T), dtype=torch.int8, device="cuda")
     bits = torch.full((n, K // 8), 0xA5, dtype=torch.uint8, device="cuda")
