@@ -44,10 +44,10 @@ COUNTERS_FILE = os.path.join(ROOT, "profiles", "decode_i8_bg1_z384_counters.md")
 KERNEL_SOURCES_F16 = ("decode_f16.hip", "ldpc_internal.h")
 COUNTERS_FILE_F16 = os.path.join(ROOT, "profiles", "decode_f16_bg1_z384_counters.md")
 KERNEL_SOURCES = ("decode_i8.hip", "ldpc_internal.h")
-# the kernel the library runs for this workload by default: early-exit
-# decodes at lifts above 256 go to the row-pair kernel (one codeword per
-# workgroup), the others to codeword pairs
+# the kernels the library runs for this workload by default: early-exit int8
+# decodes go to the row-pair kernel (one codeword per workgroup at Z = 384)
 KERNEL_I8 = "decode_i8_rp_kernel"
+KERNEL_F16 = "decode_f16_kernel"
 
 
 def kernel_source_sha(sources=KERNEL_SOURCES) -> str:
@@ -279,12 +279,12 @@ def main():
         log("timing binary16, early exit")
         w16, l16, eu16 = timed("f16", True, 2, 1)
         ach16 = OPS_PER_EDGE_UPDATE * eu16 / (sum(l16) / 1e3) / 1e12
-        t16 = measured_traffic(COUNTERS_FILE_F16, KERNEL_SOURCES_F16)
+        t16 = measured_traffic(COUNTERS_FILE_F16, KERNEL_SOURCES_F16, KERNEL_F16)
         result["f16"] = {
             "gbps": round(2 * len(batches) * n * K / w16 / 1e9, 3),
             "avg_launch_ms": round(float(np.mean(l16)), 4),
             "roofline": {
-                "bound": "alu", "kernel": "decode_f16_kernel", "achieved": round(ach16, 3),
+                "bound": "alu", "kernel": KERNEL_F16, "achieved": round(ach16, 3),
                 "peak": round(PEAK_ALU_TOPS, 2), "unit": "Top/s",
                 "frac": round(ach16 / PEAK_ALU_TOPS, 4), "traffic": t16,
                 "hbm_tb_per_s": (round(t16 / (float(np.mean(l16)) / 1e3) / 1e12, 3)
