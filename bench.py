@@ -418,7 +418,7 @@ def main():
         # one persistent batch launch per admission round, offered load
         # stepped up to saturation; each block's LLR upload is issued at its
         # arrival, on the stream of its launch, and counts in its latency
-        srv = serve.Server(weights_bg1=wq, n_slots=4, mem_budget=256 << 20, learned_shapes=shapes)
+        srv = serve.Server(weights_bg1=wq, n_slots=8, mem_budget=256 << 20, learned_shapes=shapes)
         # warm-up over the whole trace: first uses of the fallback merge and
         # of larger admission rounds (kernel loading, allocator growth) cost
         # tens of milliseconds once and are not serving latency

@@ -94,11 +94,15 @@ def rescale(blocks: list[Block], rate_hz: float) -> list[Block]:
 
 
 class Server:
-    def __init__(self, weights_bg1: np.ndarray | None = None, n_slots: int = 4,
+    def __init__(self, weights_bg1: np.ndarray | None = None, n_slots: int = 8,
                  mem_budget: int = 256 << 20, max_iter: int = 10, max_blocks_per_launch: int = 256,
                  device: str = "cuda:0", learned_shapes=None, speculate=False,
                  speculate_queue: int = 4, split_codewords: int = 64):
-        """learned_shapes: the (Z, rows) BG1 shapes the weights apply to (the
+        """n_slots: launches in flight, one stream each. The default, 8, is
+        twice the hardware queues HIP gives a process by default: a launch
+        whose stream shares a queue with a busy one waits on the device
+        rather than in the host's queue. learned_shapes: the (Z, rows) BG1
+        shapes the weights apply to (the
         shape they were trained on); None applies them to every BG1 block
         (first `rows` columns). speculate: run the plain pass of learned
         blocks in the learned pass's launch -- True always, False never
@@ -550,7 +554,7 @@ def main():
     ap = argparse.ArgumentParser(description="offered-load sweep of the decode server")
     ap.add_argument("--blocks", type=int, default=2000)
     ap.add_argument("--rates", default="20000,50000,100000,200000,400000")
-    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--slots", type=int, default=8)
     ap.add_argument("--mem-mib", type=int, default=256)
     ap.add_argument("--weights", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),
                                                       "weights", "nwms_bg1_z384_select.npz"))
