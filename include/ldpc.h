@@ -341,7 +341,11 @@ int ldpc_decode_batch(const ldpc_job *jobs, int n_jobs, int max_iter, int early_
 /* Asynchronous one-shot batch: the job tables, task queue and message
  * regions are allocated, used and released in stream order on `stream`;
  * the call returns without waiting. *bytes_in_flight (may be NULL) receives
- * the device memory the launch holds until it completes. */
+ * the device memory the launch holds until it completes. Launches needing
+ * at most 32 MiB take it from a buffer the library keeps per (device,
+ * stream), reused by the next such launch on that stream in stream order
+ * (it grows to the largest of them, a power of two, and is kept until the
+ * process ends); larger ones allocate and free in stream order. */
 int ldpc_decode_batch_async(const ldpc_job *jobs, int n_jobs, int max_iter, int early_exit,
                             void *stream, size_t *bytes_in_flight);
 

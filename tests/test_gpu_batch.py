@@ -177,3 +177,36 @@ def test_small_lift_wave_tasks_random_lifts(lib):
             alone = _alone(lib, gr, early_exit=ee)
             for a, b in zip(got, alone):
                 assert (a == b).all(), (ee, gr.bg, gr.Z, gr.rows)
+
+
+def test_async_launches_reuse_stream_buffers(lib):
+    # back-to-back asynchronous launches with no synchronisation between
+    # them, on one stream and on two: launches of up to 32 MiB share a
+    # per-stream buffer that grows (small, larger, small again), a larger
+    # launch allocates its own; every result equals the oracle's
+    small = [(2, 64, 42, 3), (1, 32, 20, 5)]
+    larger = [(1, 384, 46, 6), (2, 128, 30, 9)]
+    big = [(1, 384, 46, 2048)]
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    plan = [(s1, small, 1000), (s1, larger, 1010), (s1, small, 1020), (s2, small, 1030),
+            (s1, big, 1040), (s2, larger, 1050), (s1, larger, 1060), (s2, small, 1070)]
+    launched = []
+    for st, shapes, seed in plan:
+        jobs, batches = _shape_jobs(lib, shapes, 1.5, seed)
+        nbytes = lib.decode_batch_bytes(jobs)
+        assert (nbytes > 32 << 20) == (shapes is big), (shapes, nbytes)
+        torch.cuda.synchronize()  # inputs uploaded; the launches below do not wait
+        launched.append((shapes, jobs, batches, nbytes))
+    for (st, _, _), (shapes, jobs, _, nbytes) in zip(plan, launched):
+        print(f"[batch async] {len(shapes)} shapes, {nbytes} bytes", flush=True)
+        assert lib.decode_batch_async(jobs, stream=st) == nbytes
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(7)
+    for shapes, jobs, batches, _ in launched:
+        for (bg, Z, rows, n), jb, b in zip(shapes, jobs, batches):
+            idx = np.arange(n) if n <= 16 else np.sort(rng.choice(n, 12, replace=False))
+            ref = oracle.decode_i8(library_graph(bg, Z, rows), b.q[idx], n_threads=8)
+            got = (jb.out_bits.cpu().numpy()[idx], jb.out_iters.cpu().numpy()[idx],
+                   jb.out_ok.cpu().numpy().astype(bool)[idx])
+            for a, r in zip(got, ref[:3]):
+                assert (a == r).all(), (bg, Z, rows, n)
