@@ -101,7 +101,11 @@ class Server:
         """n_slots: launches in flight, one stream each. The default, 8, is
         twice the hardware queues HIP gives a process by default: a launch
         whose stream shares a queue with a busy one waits on the device
-        rather than in the host's queue. learned_shapes: the (Z, rows) BG1
+        rather than in the host's queue. mem_budget bounds the bytes the
+        library reports in flight; between launches the library also keeps
+        each stream's reused launch buffer (launches of at most 32 MiB, see
+        ldpc_decode_batch_async), up to n_slots times the largest such
+        launch. learned_shapes: the (Z, rows) BG1
         shapes the weights apply to (the
         shape they were trained on); None applies them to every BG1 block
         (first `rows` columns). speculate: run the plain pass of learned
