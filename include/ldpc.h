@@ -156,17 +156,27 @@ typedef struct ldpc_args {
                                variable order: int8 (I8) or binary16 (F16) */
     int cw_per_block;       /* 0 = library default; else codewords per
                                workgroup (tuning knob; the int8 path decodes
-                               codewords in pairs and rounds it up to even) */
+                               codewords in pairs and rounds it up to even;
+                               by default codeword pairs fill about 768
+                               lanes per workgroup, or fewer when the
+                               batch has fewer pairs than that per CU, so
+                               that a small batch spreads over the CUs) */
     int msg_placement;      /* where the int8 path keeps its check-to-
                                variable messages: LDPC_MSG_AUTO,
                                LDPC_MSG_LDS (next to the posteriors in LDS;
                                LDPC_EINVAL if one codeword pair's posteriors
                                and messages, 2*(Nc/Z + E)*Z bytes, exceed a
-                               workgroup's LDS) or LDPC_MSG_DEVICE (device
+                               workgroup's LDS -- with row pairs, one
+                               codeword's, (Nc/Z + E)*Z bytes: 147 kB for
+                               BG1 at Z = 384) or LDPC_MSG_DEVICE (device
                                memory, allocated
                                by the library per call, stream-ordered; more
-                               codewords then share a CU). binary16 always
-                               uses device memory. */
+                               codewords then share a CU). AUTO: codeword
+                               pairs as described under pairing's default;
+                               row pairs in LDS for at most one codeword per
+                               CU when no row is heavier than 10 blocks and
+                               the state fits, else in device memory.
+                               binary16 always uses device memory. */
     int lanes_per_row;      /* int8: lanes cooperating on one check row
                                (the paper's alpha): 0 or 1 = one lane per row
                                (the throughput mapping); 2 or 4 = the
@@ -201,8 +211,9 @@ typedef struct ldpc_args {
                                cw_per_block codewords per workgroup, default
                                up to Z = 128 the most that fit one wave, at
                                most 4; 2 to Z = 256; 1 above); the static
-                               schedule, one lane per row and
-                               device-placed messages, else LDPC_EINVAL): for
+                               schedule and one lane per row, else
+                               LDPC_EINVAL; messages in device memory unless
+                               msg_placement asks for LDS): for
                                small batches of large lifts, where a pair's
                                2Z lanes would put two waves on some of a
                                CU's SIMDs, and for early exit (one codeword
@@ -210,9 +221,11 @@ typedef struct ldpc_args {
                                converges). LDPC_PAIR_AUTO (0, the default):
                                with one lane per row, the static schedule,
                                cw_per_block 0 and message placement AUTO,
-                               row pairs for early exit at Z >= 16 and for
-                               n_cw at most the device's CU count at
-                               Z > 256; else codeword pairs.
+                               row pairs at Z > 256 with early exit or for
+                               n_cw at most the device's CU count, and at
+                               Z = 16 .. 256 with early exit for n_cw above
+                               four times the CU count; else codeword
+                               pairs.
                                Results are identical under both. */
     void *stream;
 } ldpc_args;

@@ -1022,13 +1022,15 @@ __device__ __forceinline__ void decode_block(const BlockWork &bw, uint8_t *smem,
 // lanes leave every wave a SIMD of its own. Device-placed messages,
 // [codeword][E_pad * Zh] pair words. Every thread of the workgroup must
 // call it; lanes past the last codeword only join the barriers.
-template <int WMAX>
+template <int WMAX, bool IN_LDS = false>
 __device__ __forceinline__ void decode_rp(const BlockWork &bw, uint8_t *smem, crow_t row_ptr,
                                           cmeta_t meta) {
     static_assert(WMAX <= kMetaPad, "row metadata window exceeds the table padding");
     const int Zh = bw.Z, Z = 2 * Zh;
     const int N = bw.n_cols, T = (N - 2) * Z;
-    const int cw_bytes = lds_bytes_i8_pair_post(N, Zh);
+    // a codeword's LDS: its posteriors, then (IN_LDS) its messages as
+    // [edge][Zh] pair words
+    const int cw_bytes = IN_LDS ? lds_bytes_i8_pair(N, bw.E, Zh) : lds_bytes_i8_pair_post(N, Zh);
     const int tid = (int)threadIdx.x;
     const int i = tid / Zh;
     const uint32_t u = tid - i * Zh;
@@ -1036,10 +1038,11 @@ __device__ __forceinline__ void decode_rp(const BlockWork &bw, uint8_t *smem, cr
     const int is = valid ? i : 0;  // keeps idle lanes' addresses in range
     uint8_t *Lc = smem + is * cw_bytes;
     const uint32_t lb = (uint32_t)(is * cw_bytes) + 2u * u;
-    const uint32_t ro = 2u * (uint32_t)(is * bw.E_pad * Zh);
+    const uint32_t ro = IN_LDS ? (uint32_t)(is * cw_bytes + 2 * N * Zh) + 2u * u
+                               : 2u * (uint32_t)(is * bw.E_pad * Zh);
     int *flags = reinterpret_cast<int *>(smem + bw.slots * cw_bytes);
     const __amdgpu_buffer_rsrc_t rsrc =
-        __builtin_amdgcn_make_buffer_rsrc(bw.msg, 0, bw.msg_records, 0x00020000);
+        __builtin_amdgcn_make_buffer_rsrc(bw.msg, 0, IN_LDS ? 0 : bw.msg_records, 0x00020000);
     if (valid) load_rp_llrs<17>(Lc, bw.llr + (size_t)i * T, N, Z, u);
     __syncthreads();
 
@@ -1051,12 +1054,13 @@ __device__ __forceinline__ void decode_rp(const BlockWork &bw, uint8_t *smem, cr
         if (bw.wq) wrow = bw.wq + (size_t)((t < bw.w_iters ? t : bw.w_iters) - 1) * bw.w_stride;
         const bool busy = !done;
         if (t == 1)
-            layer_pass<WMAX, false, true, false, true>(bw, smem, lb, ro, rsrc, row_ptr, meta, wrow,
-                                                       u, busy, off16, pre, t < bw.max_iter);
-        else
-            layer_pass<WMAX, false, false, false, true>(bw, smem, lb, ro, rsrc, row_ptr, meta,
+            layer_pass<WMAX, IN_LDS, true, false, true>(bw, smem, lb, ro, rsrc, row_ptr, meta,
                                                         wrow, u, busy, off16, pre,
                                                         t < bw.max_iter);
+        else
+            layer_pass<WMAX, IN_LDS, false, false, true>(bw, smem, lb, ro, rsrc, row_ptr, meta,
+                                                         wrow, u, busy, off16, pre,
+                                                         t < bw.max_iter);
         if (bw.early_exit || t == bw.max_iter) {
             // flags[0, slots): a failing check per codeword; flags[slots]:
             // stays 1 while every codeword of the workgroup is finished
@@ -1316,7 +1320,7 @@ hipError_t launch_placed(const DecodeLaunch &p, hipStream_t stream) {
 // CU; the register budget this leaves (up to 102) spills six values, none
 // inside a row update (the four-wave budget fits five workgroups and was
 // 1.5 % slower).
-template <int WMAX>
+template <int WMAX, bool IN_LDS>
 __global__ __launch_bounds__(768) __attribute__((amdgpu_waves_per_eu(5))) void decode_i8_rp_kernel(
     DecodeLaunch p, const int32_t *__restrict__ row_ptr, const uint32_t *__restrict__ meta) {
     extern __shared__ __align__(16) uint8_t smem[];
@@ -1330,8 +1334,10 @@ __global__ __launch_bounds__(768) __attribute__((amdgpu_waves_per_eu(5))) void d
     bw.out_ok = p.out_ok ? p.out_ok + first : nullptr;
     bw.out_llr = p.out_llr ? static_cast<int8_t *>(p.out_llr) + (size_t)first * p.n_cols * p.Z
                            : nullptr;
-    bw.msg = reinterpret_cast<uint16_t *>(p.msg) + (size_t)first * p.E_pad * Zh;
-    {
+    bw.msg = nullptr;
+    bw.msg_records = 0;
+    if (!IN_LDS) {
+        bw.msg = reinterpret_cast<uint16_t *>(p.msg) + (size_t)first * p.E_pad * Zh;
         // this workgroup's codewords up to the end of the allocation
         const size_t base = (size_t)first * p.E_pad * Zh * 2;
         const size_t full = (size_t)p.cpw * p.E_pad * Zh * 2;
@@ -1353,28 +1359,33 @@ __global__ __launch_bounds__(768) __attribute__((amdgpu_waves_per_eu(5))) void d
     bw.early_exit = p.early_exit;
     bw.beta = p.beta;
     bw.offset = p.offset;
-    decode_rp<WMAX>(bw, smem, (crow_t)row_ptr, (cmeta_t)meta);
+    decode_rp<WMAX, IN_LDS>(bw, smem, (crow_t)row_ptr, (cmeta_t)meta);
 }
 
-template <int WMAX>
+// Row-pair launch: messages in device memory (p.msg) or, without p.msg,
+// in LDS after each codeword's posteriors.
+template <int WMAX, bool IN_LDS>
 hipError_t launch_rp_w(const DecodeLaunch &p, hipStream_t stream) {
     const int Zh = p.Z / 2;
-    const int lds = p.cpw * lds_bytes_i8_pair_post(p.n_cols, Zh) + lds_flags_bytes_i8(p.cpw);
+    const int per_cw =
+        IN_LDS ? lds_bytes_i8_pair(p.n_cols, p.E, Zh) : lds_bytes_i8_pair_post(p.n_cols, Zh);
+    const int lds = p.cpw * per_cw + lds_flags_bytes_i8(p.cpw);
     static std::once_flag attr_once;
     std::call_once(attr_once, [] {
         const hipError_t e = hipFuncSetAttribute(
-            reinterpret_cast<const void *>(&decode_i8_rp_kernel<WMAX>),
+            reinterpret_cast<const void *>(&decode_i8_rp_kernel<WMAX, IN_LDS>),
             hipFuncAttributeMaxDynamicSharedMemorySize, max_lds_bytes());
         if (e != hipSuccess) note_hip_error("hipFuncSetAttribute(decode_i8_rp_kernel)", e);
     });
-    if (p.cpw < 1 || p.cpw * Zh > 768 || Zh % 4 != 0 || !p.msg || lds > max_lds_bytes()) {
+    if (p.cpw < 1 || p.cpw * Zh > 768 || Zh % 4 != 0 || (!IN_LDS && !p.msg) ||
+        lds > max_lds_bytes()) {
         note_hip_error("decode_i8_rp_kernel: bad workgroup shape", hipErrorInvalidValue);
         return hipErrorInvalidValue;
     }
     const int blocks = (p.n_cw + p.cpw - 1) / p.cpw;
     (void)hipGetLastError();
-    hipLaunchKernelGGL((decode_i8_rp_kernel<WMAX>), dim3(blocks), dim3(p.cpw * Zh), lds, stream,
-                       p, p.row_ptr, p.meta);
+    hipLaunchKernelGGL((decode_i8_rp_kernel<WMAX, IN_LDS>), dim3(blocks), dim3(p.cpw * Zh), lds,
+                       stream, p, p.row_ptr, p.meta);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) note_hip_error("launch decode_i8_rp_kernel", e);
     return e;
@@ -1991,10 +2002,15 @@ hipError_t launch_ll(const DecodeLaunch &p, hipStream_t stream) {
 hipError_t launch_decode_i8(const DecodeLaunch &p, hipStream_t stream) {
     if (p.alpha == 2) return p.wmax <= 10 ? launch_ll<10, 2>(p, stream) : launch_ll<20, 2>(p, stream);
     if (p.alpha == 4) return p.wmax <= 10 ? launch_ll<10, 4>(p, stream) : launch_ll<20, 4>(p, stream);
+    if (p.rowpair && p.msg) {
+        if (p.wmax <= 10) return launch_rp_w<10, false>(p, stream);
+        if (p.wmax <= 20) return launch_rp_w<20, false>(p, stream);
+        return launch_rp_w<32, false>(p, stream);
+    }
     if (p.rowpair) {
-        if (p.wmax <= 10) return launch_rp_w<10>(p, stream);
-        if (p.wmax <= 20) return launch_rp_w<20>(p, stream);
-        return launch_rp_w<32>(p, stream);
+        if (p.wmax <= 10) return launch_rp_w<10, true>(p, stream);
+        if (p.wmax <= 20) return launch_rp_w<20, true>(p, stream);
+        return launch_rp_w<32, true>(p, stream);
     }
     if (p.refill) {
         if (p.wmax <= 10) return launch_refill_w<10>(p, stream);

@@ -151,18 +151,30 @@ int pow2_bucket(int n) {
     return b;
 }
 
+// Compute units of the current device, 0 if the runtime cannot say.
+int device_cus() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    return cus;
+}
+
 // Whether an int8 call decodes with the row-pair kernel: on request
-// (LDPC_PAIR_ROWS; the static schedule, one lane per row and device-placed
-// messages, else the caller gets LDPC_EINVAL), or by default (one lane per
-// row, the static schedule, the default packing and message placement)
-// when early exit is on at lifts from 16 (a workgroup of at most four
-// codewords leaves its CU as soon as they converge, where a workgroup of
-// codeword pairs runs until the slowest of its 2*floor(768/Z) codewords has:
-// half to two thirds of the time at lifts 32 to 128, 5 to 20 % less at
-// 208 to 320, within 4 % either way at 16, 24 and 144), and at lifts above
-// 256 for at most one codeword per CU (a codeword pair's 2Z lanes would put
-// two waves on some SIMDs of a CU, where one codeword's Z/2 lanes leave
-// every wave a SIMD of its own). Sets g_msg when a request cannot be met.
+// (LDPC_PAIR_ROWS; the static schedule and one lane per row, else the
+// caller gets LDPC_EINVAL), or by default (one lane per row, the static
+// schedule, the default packing and message placement):
+// * at lifts above 256 with early exit, and for at most one codeword per
+//   CU (a codeword pair's 2Z lanes would put two waves on some SIMDs of a
+//   CU, where one codeword's Z/2 lanes leave every wave a SIMD of its own);
+// * at lifts 16 to 256 with early exit for more than four codewords per CU:
+//   codeword pairs then need more than one round of workgroups per CU, and
+//   a workgroup of codeword pairs runs until the slowest of its codewords
+//   has converged, where row-pair workgroups of one to four codewords leave
+//   as soon as theirs have (4,096 codewords: 30 to 45 % less time at lifts
+//   32 to 128). Up to 1,024 codewords, codeword pairs spread over the CUs
+//   were as fast or faster (row pairs spend two more instructions per edge).
+// Sets g_msg when a request cannot be met.
 // Default codewords per row-pair workgroup: up to Z = 128 the most whose
 // Z/2 lanes fit in one wave, at most four (no barrier then couples waves;
 // four at Z = 16 to 32, two to 64, one to 128), two to Z = 256 and one above.
@@ -177,25 +189,19 @@ int row_pair_default_cpw(int Z) {
 }
 
 bool use_row_pairs(const ldpc_args *a, int Z) {
-    const bool can = a->schedule == LDPC_SCHED_STATIC && a->lanes_per_row <= 1 &&
-                     a->msg_placement != LDPC_MSG_LDS;
+    const bool can = a->schedule == LDPC_SCHED_STATIC && a->lanes_per_row <= 1;
     if (a->pairing == LDPC_PAIR_ROWS) {
         if (!can)
             snprintf(g_msg, sizeof(g_msg),
-                     "row pairs need the static schedule, one lane per row and device-placed "
-                     "messages");
+                     "row pairs need the static schedule and one lane per row");
         return can;
     }
     if (a->pairing != LDPC_PAIR_AUTO || !can || a->cw_per_block != 0 ||
-        a->msg_placement != LDPC_MSG_AUTO)
+        a->msg_placement != LDPC_MSG_AUTO || Z < 16)
         return false;
-    if (a->early_exit && Z >= 16) return true;
-    if (Z <= 256) return false;
-    int dev = 0, cus = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-        return false;
-    return a->n_cw <= cus;
+    const int cus = device_cus();
+    if (Z > 256) return a->early_exit || a->n_cw <= cus;
+    return a->early_exit && a->n_cw > 4 * cus;
 }
 
 int prepare_decode(const ldpc_args *a0, bool upload, DecodeLaunch &p, bool &msg_in_lds,
@@ -306,15 +312,28 @@ int prepare_decode(const ldpc_args *a0, bool upload, DecodeLaunch &p, bool &msg_
             return LDPC_EINVAL;
         cpw = 2 * pairs;
     } else if (rowpair) {
-        // One codeword per Z/2 lanes (row pairs), device-placed messages.
+        // One codeword per Z/2 lanes (row pairs); messages in device memory,
+        // or in LDS after each codeword's posteriors on request.
         p.rowpair = 1;
         p.meta = meta_rp;
-        const int per_cw = lds_bytes_i8_pair_post(p.n_cols, Zh) + 16;
+        // By default the messages go to LDS for at most one codeword per CU
+        // when every row has weight 10 or less and one codeword's state fits
+        // (BG2-shaped at Z = 384: 28.8 against 32.3 us per iteration; with
+        // weight-19 rows the separate 16-bit message accesses cancel it).
+        msg_in_lds = a->msg_placement == LDPC_MSG_LDS ||
+                     (a->msg_placement == LDPC_MSG_AUTO && a->cw_per_block == 0 &&
+                      p.wmax <= 10 && a->n_cw <= device_cus() &&
+                      lds_bytes_i8_pair(p.n_cols, p.E, Zh) + 16 <= lds_cap - 8);
+        const int per_cw = (msg_in_lds ? lds_bytes_i8_pair(p.n_cols, p.E, Zh)
+                                       : lds_bytes_i8_pair_post(p.n_cols, Zh)) + 16;
         cpw = a->cw_per_block > 0 ? a->cw_per_block : row_pair_default_cpw(p.Z);
         cpw = std::min(cpw, (lds_cap - 8) / per_cw);
         cpw = std::min(cpw, 768 / Zh);
         cpw = std::min(cpw, a->n_cw);
-        if (cpw < 1) return LDPC_EINVAL;
+        if (cpw < 1) {
+            snprintf(g_msg, sizeof(g_msg), "one codeword's row-pair state does not fit in LDS");
+            return LDPC_EINVAL;
+        }
     } else if (i8) {
         // Codewords go in pairs of Z lanes. Message placement: LDS when two
         // pairs' full state fits a CU, else device memory so that several
@@ -333,7 +352,17 @@ int prepare_decode(const ldpc_args *a0, bool upload, DecodeLaunch &p, bool &msg_
         // else about 768 (two pairs per workgroup at the largest lift, one
         // workgroup per CU: measured as fast as three pairs per CU in steady
         // state, and with a finer tail for batches of a few thousand).
-        if (pairs == 0) pairs = std::max(1, (msg_in_lds ? 256 : 768) / p.Z);
+        // A batch of fewer pairs than that fills the device spreads them
+        // over the CUs instead (eight codewords at Z = 256 in one
+        // workgroup: 62 us per iteration against 41 on separate CUs).
+        if (pairs == 0) {
+            pairs = std::max(1, (msg_in_lds ? 256 : 768) / p.Z);
+            const int cus = device_cus();
+            if (cus > 0) {
+                const int n_pairs = (a->n_cw + 1) / 2;
+                pairs = std::min(pairs, std::max(1, (n_pairs + cus - 1) / cus));
+            }
+        }
         pairs = std::min(pairs, (lds_cap - 8) / per_pair);
         pairs = std::min(pairs, 768 / p.Z);
         pairs = std::min(pairs, (a->n_cw + 1) / 2);

@@ -3,8 +3,8 @@ check rows u and u + Z/2 as the two halves of its packed registers) against
 the CPU oracle, through the C ABI: bit-exact hard decisions, posteriors,
 iteration counts and flags over lifts whose halves fill whole waves or not
 (Z/2 = 8 .. 192), several codewords per workgroup with a ragged last
-workgroup, the normalisation options, and the same results as codeword
-pairs."""
+workgroup, the normalisation options, messages in device memory or in LDS,
+and the same results as codeword pairs."""
 import numpy as np
 import pytest
 
@@ -75,15 +75,17 @@ def test_rowpair_saturated_inputs():
         assert_i8_equal(got, oracle_i8(g, q, max_iter=4))
 
 
-def test_auto_pairing_equals_codeword_pairs():
-    # small batches at Z = 384 take row pairs by default; results are the
-    # same as codeword pairs and the oracle's
-    g = _graph(1, 384, 46)
+@pytest.mark.parametrize("bg,rows,early_exit", [(1, 46, True), (1, 46, False), (2, 42, False)])
+def test_auto_pairing_equals_codeword_pairs(bg, rows, early_exit):
+    # small batches at Z = 384 take row pairs by default (BG2-shaped, whose
+    # rows weigh at most 10 blocks: with the messages in LDS); results are
+    # the same as codeword pairs and the oracle's
+    g = _graph(bg, 384, rows)
     b = make_batch(g, 7, 1.5, data_seed=73)
-    auto = gpu_decode(1, 384, 46, b.q)
-    cw = gpu_decode(1, 384, 46, b.q, pairing="codewords")
+    auto = gpu_decode(bg, 384, rows, b.q, early_exit=early_exit)
+    cw = gpu_decode(bg, 384, rows, b.q, pairing="codewords", early_exit=early_exit)
     assert_i8_equal(auto, cw)
-    assert_i8_equal(auto, oracle_i8(g, b.q))
+    assert_i8_equal(auto, oracle_i8(g, b.q, early_exit=early_exit))
 
 
 @pytest.mark.parametrize("bg,Z,rows,n", [
@@ -96,15 +98,51 @@ def test_auto_pairing_equals_codeword_pairs():
     (1, 208, 46, 5),   # two: 208 lanes in four waves, ragged end
     (1, 320, 46, 3),   # one: 160 lanes in three waves
 ])
-def test_auto_row_pairs_other_lifts(bg, Z, rows, n):
-    # early-exit decodes take row pairs by default from Z = 16; lifts that
-    # are not powers of two leave partial waves
+def test_rowpair_default_cpw_other_lifts(bg, Z, rows, n):
+    # row pairs with the default codewords per workgroup; lifts that are
+    # not powers of two leave partial waves
     g = _graph(bg, Z, rows)
     b = make_batch(g, n, 1.5, data_seed=800 + Z)
-    print(f"[rowpair auto] bg={bg} Z={Z} rows={rows} n={n}", flush=True)
-    auto = gpu_decode(bg, Z, rows, b.q)
-    assert_i8_equal(auto, oracle_i8(g, b.q))
-    assert_i8_equal(auto, gpu_decode(bg, Z, rows, b.q, pairing="codewords"))
+    print(f"[rowpair default cpw] bg={bg} Z={Z} rows={rows} n={n}", flush=True)
+    got = gpu_decode(bg, Z, rows, b.q, pairing="rows")
+    assert_i8_equal(got, oracle_i8(g, b.q))
+    assert_i8_equal(got, gpu_decode(bg, Z, rows, b.q, pairing="codewords"))
+
+
+def test_auto_row_pairs_large_batch():
+    # early exit at a small lift with more than four codewords per CU: the
+    # default launch takes row pairs; same results as codeword pairs, and
+    # the oracle's on a sample
+    g = _graph(2, 16, 42)
+    n = 4 * torch.cuda.get_device_properties(0).multi_processor_count + 37
+    b = make_batch(g, n, 1.5, data_seed=830)
+    print(f"[rowpair auto] BG2 Z=16 n={n}", flush=True)
+    auto = gpu_decode(2, 16, 42, b.q)
+    assert_i8_equal(auto, gpu_decode(2, 16, 42, b.q, pairing="codewords"))
+    idx = np.random.default_rng(8).choice(n, 64, replace=False)
+    assert_i8_equal(tuple(x[idx] for x in auto), oracle_i8(g, b.q[idx]))
+
+
+@pytest.mark.parametrize("bg,Z,rows,n,cpw", [
+    (1, 384, 46, 2, 1),    # one codeword's state: 147 kB of LDS
+    (2, 384, 42, 3, 0),
+    (1, 128, 46, 5, 2),    # ragged last workgroup
+    (2, 64, 30, 9, 4),
+    (1, 40, 46, 7, 3),     # partial wave
+    (2, 16, 42, 11, 0),
+])
+def test_rowpair_lds_messages(bg, Z, rows, n, cpw):
+    # messages in LDS after each codeword's posteriors: same results as
+    # device-placed messages and as the oracle, with and without early exit
+    g = _graph(bg, Z, rows)
+    b = make_batch(g, n, 1.5, data_seed=820 + Z)
+    print(f"[rowpair lds] bg={bg} Z={Z} rows={rows} n={n} cpw={cpw}", flush=True)
+    for ee in (True, False):
+        got = gpu_decode(bg, Z, rows, b.q, pairing="rows", msg_placement="lds", cw_per_block=cpw,
+                         early_exit=ee)
+        assert_i8_equal(got, oracle_i8(g, b.q, early_exit=ee))
+        assert_i8_equal(got, gpu_decode(bg, Z, rows, b.q, pairing="rows",
+                                        msg_placement="device", cw_per_block=cpw, early_exit=ee))
 
 
 def test_rowpair_noalloc():
@@ -119,8 +157,7 @@ def test_rowpair_refusals():
     from paper_2009_05534_amd import ldpc
     g = _graph(1, 64, 30)
     q = make_batch(g, 4, 1.5, data_seed=75).q
-    for kw in (dict(pairing="rows", msg_placement="lds"),
-               dict(pairing="rows", schedule="persistent"),
+    for kw in (dict(pairing="rows", schedule="persistent"),
                dict(pairing="rows", lanes_per_row=2),
                dict(pairing="rows", precision="f16")):
         with pytest.raises(ldpc.LdpcError):
