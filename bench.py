@@ -330,15 +330,23 @@ def main():
         q128 = torch.from_numpy(make_batch(g128, 1, EBN0_POINTS[4], data_seed=9).q).to(dev)
         lat128 = {str(al): one_cw_us_per_iter(BG, 128, ROWS, q128, al) for al in (1, 2, 4)}
         lat128["1_row_pairs"] = one_cw_us_per_iter(BG, 128, ROWS, q128, 1, pairing="rows")
+        # BG2-shaped Z = 384, all 42 rows: by default one codeword takes row
+        # pairs with its messages in LDS (no row weighs more than 10 blocks)
+        g2 = make_graph(2, Z)
+        ldpc.register(g2)
+        q2 = torch.from_numpy(make_batch(g2, 1, EBN0_POINTS[4], data_seed=9).q).to(dev)
+        lat_bg2 = {"1": one_cw_us_per_iter(2, Z, g2.M, q2, 1),
+                   "1_codeword_pairs": one_cw_us_per_iter(2, Z, g2.M, q2, 1, pairing="codewords")}
         result["latency_ms"]["single_codeword_us_per_iter_p50"] = min(lat1.values())
         # binary16: one codeword on Z/2 lanes (two check rows per lane)
         lat16 = {f"Z{Z}": one_cw_us_per_iter(BG, Z, ROWS, one, 0, "f16"),
                  "Z128": one_cw_us_per_iter(BG, 128, ROWS, q128, 0, "f16")}
         result["latency_ms"]["single_codeword_us_per_iter"] = {
             "note": "one codeword, 10 iterations, p50 over 50 calls, by lanes per check row "
-                    "(int8 '1': check rows u and u + Z/2 per lane at Z = 384, codeword pairs at "
+                    "(int8 '1': check rows u and u + Z/2 per lane at Z = 384 -- for the "
+                    "BG2-shaped code with the messages in LDS -- and codeword pairs at "
                     "Z = 128; '1_codeword_pairs' / '1_row_pairs': the other pairing)",
-            f"Z{Z}": lat1, "Z128": lat128, "f16": lat16}
+            f"Z{Z}": lat1, "Z128": lat128, f"bg2_Z{Z}": lat_bg2, "f16": lat16}
 
     if "batched" in extras:
         # ldpc_tune on two single-shape batches (int8, early exit): the
