@@ -563,13 +563,15 @@ def main():
     ap.add_argument("--weights", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),
                                                       "weights", "nwms_bg1_z384_select.npz"))
     ap.add_argument("--seed", type=int, default=6)
+    ap.add_argument("--embb-share", type=float, default=0.0,
+                    help="share of full-rate BG1 Z = 384 blocks (the benchmark uses 0.25)")
     args = ap.parse_args()
     from . import ldpc, nwms
     wq, shapes = None, None
     if args.weights and os.path.exists(args.weights):
         wq, meta = nwms.load_weights(args.weights)
         shapes = [(meta["Z"], meta["rows"])]
-    blocks = make_trace(args.blocks, seed=args.seed)
+    blocks = make_trace(args.blocks, seed=args.seed, embb_share=args.embb_share)
     for bg in (1, 2):
         for Z in LIFTS:
             ldpc.register(make_graph(bg, Z))
