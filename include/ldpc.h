@@ -212,8 +212,8 @@ typedef struct ldpc_args {
                                up to Z = 128 the most that fit one wave, at
                                most 4; 2 to Z = 256; 1 above); the static
                                schedule and one lane per row, else
-                               LDPC_EINVAL; messages in device memory unless
-                               msg_placement asks for LDS): for
+                               LDPC_EINVAL; messages placed as msg_placement
+                               says): for
                                small batches of large lifts, where a pair's
                                2Z lanes would put two waves on some of a
                                CU's SIMDs, and for early exit (one codeword
