@@ -221,8 +221,11 @@ typedef struct ldpc_args {
                                converges). LDPC_PAIR_AUTO (0, the default):
                                with one lane per row, the static schedule,
                                cw_per_block 0 and message placement AUTO,
-                               row pairs at Z > 256 with early exit or for
-                               n_cw at most the device's CU count, and at
+                               row pairs at Z > 256 for n_cw at most the
+                               device's CU count and with early exit (if no
+                               row weighs more than 10 blocks, not for n_cw
+                               of four to eight times the CU count, four
+                               excluded), and at
                                Z = 16 .. 256 with early exit for n_cw above
                                four times the CU count; else codeword
                                pairs.
